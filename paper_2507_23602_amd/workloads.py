@@ -1,0 +1,371 @@
+"""Seeded synthetic inputs for the semi-discrete RSOT dual evaluation.
+
+This module builds the *data* both the HIP library and the CPU oracle consume:
+finite-element meshes, their quadrature points x_q and masses mu_q =
+rho_h(x_q) w_q (Sec. 3.1-3.2, Remark 3.1), and target clouds {y_j, nu_j}
+(Sec. 2). It holds none of the method's arithmetic (no cost, no log-sum-exp,
+no gradient): it is shared input plumbing only, importable without torch or
+the compiled library.
+
+Readings fixed here (the paper leaves them open):
+  * quadrature: the symmetric degree-2 rules -- triangle barycentric
+    (2/3, 1/6, 1/6) and permutations with weights |K|/3; tetrahedron
+    (a, b, b, b) and permutations, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20,
+    weights |K|/4. Both integrate quadratics exactly.
+  * meshes: unit square split along the (i,j)-(i+1,j+1) diagonal; unit cube
+    split into the 6 Kuhn tetrahedra around its (0,0,0)-(1,1,1) diagonal;
+    unit disk from hexagonal rings, refined by midpoint (red) refinement with
+    new boundary midpoints pushed radially onto the circle.
+  * densities: P1 nodal interpolation of the analytic density (Sec. 3.1),
+    evaluated at the quadrature points from barycentric coordinates, then
+    masses scaled so that sum mu_q = 1 (normalised measures, Sec. 2).
+  * Gaussian mixtures: equal weights, isotropic sigma; samples not clipped.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# quadrature rules (reference-element barycentric coordinates + weights)
+# --------------------------------------------------------------------------
+TRI3_BARY = np.array([[2.0 / 3, 1.0 / 6, 1.0 / 6],
+                      [1.0 / 6, 2.0 / 3, 1.0 / 6],
+                      [1.0 / 6, 1.0 / 6, 2.0 / 3]])
+_A = (5.0 + 3.0 * math.sqrt(5.0)) / 20.0
+_B = (5.0 - math.sqrt(5.0)) / 20.0
+TET4_BARY = np.array([[_A, _B, _B, _B],
+                      [_B, _A, _B, _B],
+                      [_B, _B, _A, _B],
+                      [_B, _B, _B, _A]])
+
+
+@dataclass
+class Mesh:
+    """Simplicial mesh: vertices (nv x d) and cells (nc x (d+1)) of vertex ids."""
+    verts: np.ndarray
+    cells: np.ndarray
+
+    @property
+    def dim(self) -> int:
+        return self.verts.shape[1]
+
+
+@dataclass
+class Problem:
+    """One semi-discrete instance: source quadrature measure and target cloud."""
+    x: np.ndarray            # (nq, d) quadrature points
+    mu: np.ndarray           # (nq,) masses rho_h(x_q) w_q, sum 1
+    y: np.ndarray            # (n, d) targets
+    nu: np.ndarray           # (n,) target masses, sum 1
+    eps: float
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return self.x.shape[1]
+
+    @property
+    def nq(self) -> int:
+        return self.x.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.y.shape[0]
+
+
+# --------------------------------------------------------------------------
+# meshes
+# --------------------------------------------------------------------------
+def square_mesh(n: int, lo: float = 0.0, hi: float = 1.0) -> Mesh:
+    """n x n squares of [lo,hi]^2, each split by its (i,j)-(i+1,j+1) diagonal."""
+    t = np.linspace(lo, hi, n + 1)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    vid = np.arange((n + 1) ** 2).reshape(n + 1, n + 1)
+    v00 = vid[:-1, :-1].ravel()
+    v10 = vid[1:, :-1].ravel()
+    v11 = vid[1:, 1:].ravel()
+    v01 = vid[:-1, 1:].ravel()
+    lower = np.stack([v00, v10, v11], axis=1)
+    upper = np.stack([v00, v11, v01], axis=1)
+    cells = np.empty((2 * n * n, 3), dtype=np.int64)
+    cells[0::2] = lower
+    cells[1::2] = upper
+    return Mesh(verts, cells)
+
+
+def cube_mesh(n: int, lo: float = 0.0, hi: float = 1.0) -> Mesh:
+    """n^3 cubes of [lo,hi]^3, each split into the 6 Kuhn tetrahedra.
+
+    Kuhn tetrahedron for a permutation (a, b, c) of the axes:
+    v0, v0 + e_a, v0 + e_a + e_b, v0 + e_a + e_b + e_c (= the far corner).
+    The split is conforming because every cube uses the same diagonal.
+    """
+    t = np.linspace(lo, hi, n + 1)
+    X, Y, Z = np.meshgrid(t, t, t, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    m = n + 1
+    i, j, k = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    base = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
+
+    def vid(off):
+        p = base + np.asarray(off)
+        return (p[:, 0] * m + p[:, 1]) * m + p[:, 2]
+
+    e = np.eye(3, dtype=np.int64)
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    tets = []
+    for (a, b, c) in perms:
+        o0 = np.zeros(3, dtype=np.int64)
+        o1 = e[a]
+        o2 = e[a] + e[b]
+        o3 = e[a] + e[b] + e[c]
+        tets.append(np.stack([vid(o0), vid(o1), vid(o2), vid(o3)], axis=1))
+    cells = np.stack(tets, axis=1).reshape(-1, 4)
+    return Mesh(verts, cells)
+
+
+def disk_mesh(rings: int, radius: float = 1.0) -> Mesh:
+    """Disk triangulation from hexagonal rings (6 r^2 triangles for r rings).
+
+    Ring k (k = 1..rings) holds 6k vertices on the circle of radius
+    k * radius / rings; consecutive rings are stitched into 6(2k-1) triangles.
+    """
+    pts = [np.zeros((1, 2))]
+    ring_start = [0]
+    count = 1
+    for k in range(1, rings + 1):
+        ang = 2.0 * np.pi * np.arange(6 * k) / (6 * k)
+        r = k * radius / rings
+        pts.append(np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1))
+        ring_start.append(count)
+        count += 6 * k
+    verts = np.concatenate(pts, axis=0)
+    cells = []
+    for k in range(1, rings + 1):
+        inner_n = 6 * (k - 1) if k > 1 else 1
+        outer_n = 6 * k
+        s_in = ring_start[k - 1]
+        s_out = ring_start[k]
+        for side in range(6):
+            for t in range(k):
+                o = side * k + t
+                o1 = (o + 1) % outer_n
+                if k == 1:
+                    cells.append((s_in, s_out + o, s_out + o1))
+                    continue
+                i0 = (side * (k - 1) + t) % inner_n
+                cells.append((s_in + i0, s_out + o, s_out + o1))
+                if t < k - 1:
+                    i1 = (i0 + 1) % inner_n
+                    cells.append((s_in + i0, s_out + o1, s_in + i1))
+    cells = np.asarray(cells, dtype=np.int64)
+    return Mesh(verts, cells)
+
+
+def refine_triangles(mesh: Mesh, radius: float | None = None) -> Mesh:
+    """Red refinement: every triangle into 4 through edge midpoints.
+
+    With ``radius`` set, midpoints of boundary edges are pushed radially onto
+    the circle of that radius (disk hierarchy). The refined mesh is nested in
+    the sense of the multilevel remark of Sec. 5.1 up to this boundary move.
+    """
+    v = mesh.verts
+    c = mesh.cells
+    edges = np.concatenate([c[:, [0, 1]], c[:, [1, 2]], c[:, [2, 0]]], axis=0)
+    e_sorted = np.sort(edges, axis=1)
+    uniq, inv, counts = np.unique(e_sorted, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    mids = 0.5 * (v[uniq[:, 0]] + v[uniq[:, 1]])
+    if radius is not None:
+        boundary = counts == 1
+        r = np.linalg.norm(mids[boundary], axis=1)
+        mids[boundary] *= (radius / r)[:, None]
+    nv = v.shape[0]
+    verts = np.concatenate([v, mids], axis=0)
+    nc = c.shape[0]
+    m01 = nv + inv[0:nc]
+    m12 = nv + inv[nc:2 * nc]
+    m20 = nv + inv[2 * nc:3 * nc]
+    a, b, cc = c[:, 0], c[:, 1], c[:, 2]
+    new = np.stack([
+        np.stack([a, m01, m20], axis=1),
+        np.stack([m01, b, m12], axis=1),
+        np.stack([m20, m12, cc], axis=1),
+        np.stack([m01, m12, m20], axis=1),
+    ], axis=1).reshape(-1, 3)
+    return Mesh(verts, new)
+
+
+# --------------------------------------------------------------------------
+# quadrature measure
+# --------------------------------------------------------------------------
+def cell_measures(mesh: Mesh) -> np.ndarray:
+    """|K| for every simplex (area in 2D, volume in 3D)."""
+    v = mesh.verts[mesh.cells]           # (nc, d+1, d)
+    e = v[:, 1:, :] - v[:, :1, :]        # (nc, d, d)
+    det = np.linalg.det(e)
+    return np.abs(det) / math.factorial(mesh.dim)
+
+
+def quadrature(mesh: Mesh, vertex_density: np.ndarray | None = None,
+               normalise: bool = True):
+    """Quadrature points and masses mu_q = rho_h(x_q) w_q (Remark 3.1).
+
+    ``vertex_density`` holds nodal values of rho (P1 interpolation); None
+    means rho = 1. Points are ordered cell by cell.
+    """
+    d = mesh.dim
+    bary = TRI3_BARY if d == 2 else TET4_BARY
+    npc = bary.shape[0]
+    vol = cell_measures(mesh)
+    cv = mesh.verts[mesh.cells]                          # (nc, d+1, d)
+    x = np.einsum("pk,ckd->cpd", bary, cv).reshape(-1, d)
+    w = np.repeat(vol / npc, npc)
+    if vertex_density is None:
+        rho = np.ones_like(w)
+    else:
+        rv = vertex_density[mesh.cells]                  # (nc, d+1)
+        rho = np.einsum("pk,ck->cp", bary, rv).reshape(-1)
+    mu = rho * w
+    if normalise:
+        mu = mu / mu.sum()
+    return np.ascontiguousarray(x), np.ascontiguousarray(mu)
+
+
+# --------------------------------------------------------------------------
+# densities and clouds
+# --------------------------------------------------------------------------
+def mixture_means(rng: np.random.Generator, k: int, d: int, lo=0.2, hi=0.8):
+    return rng.uniform(lo, hi, size=(k, d))
+
+
+def mixture_density(pts: np.ndarray, means: np.ndarray, sigma: float) -> np.ndarray:
+    """Equal-weight isotropic Gaussian mixture, up to a constant factor."""
+    r2 = ((pts[:, None, :] - means[None, :, :]) ** 2).sum(-1)
+    return np.exp(-r2 / (2.0 * sigma * sigma)).mean(axis=1)
+
+
+def mixture_samples(rng: np.random.Generator, means: np.ndarray, sigma: float,
+                    n: int) -> np.ndarray:
+    comp = rng.integers(0, means.shape[0], size=n)
+    return means[comp] + sigma * rng.standard_normal((n, means.shape[1]))
+
+
+def uniform_targets(seed: int, n: int, d: int) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(0.0, 1.0, size=(n, d))
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+def square_uniform(n_cells: int, n_targets: int, seed: int, eps: float) -> Problem:
+    """Unit square, uniform density, targets uniform in the square."""
+    x, mu = quadrature(square_mesh(n_cells))
+    y = uniform_targets(seed, n_targets, 2)
+    nu = np.full(n_targets, 1.0 / n_targets)
+    return Problem(x, mu, y, nu, eps, name=f"square{n_cells}_n{n_targets}")
+
+
+def config1() -> Problem:
+    """2D unit square, 32x32 -> 2048 P1 triangles x 3 points = 6144 points,
+    uniform density, N = 256 uniform targets (seed 1), nu = 1/N, eps = 1e-2."""
+    p = square_uniform(32, 256, seed=1, eps=1e-2)
+    p.name = "square32_tri3_n256_eps1e-2"
+    return p
+
+
+def cube_mixture(n_cells: int, n_targets: int, eps: float, src_seed: int = 2,
+                 tgt_mean_seed: int = 3, tgt_sample_seed: int = 4,
+                 sigma: float = 0.1, k: int = 3) -> Problem:
+    """Unit cube, Kuhn tetrahedra x 4 points, Gaussian-mixture source density
+    (P1-interpolated), targets sampled from a different seeded mixture."""
+    mesh = cube_mesh(n_cells)
+    src_means = mixture_means(np.random.default_rng(src_seed), k, 3)
+    rho_v = mixture_density(mesh.verts, src_means, sigma)
+    x, mu = quadrature(mesh, rho_v)
+    tgt_means = mixture_means(np.random.default_rng(tgt_mean_seed), k, 3)
+    y = mixture_samples(np.random.default_rng(tgt_sample_seed), tgt_means, sigma, n_targets)
+    nu = np.full(n_targets, 1.0 / n_targets)
+    return Problem(x, mu, y, nu, eps, name=f"cube{n_cells}_tet4_mix_n{n_targets}",
+                   meta={"src_means": src_means, "tgt_means": tgt_means})
+
+
+def config2() -> Problem:
+    """3D unit cube, 64^3 cells x 6 Kuhn tets = 1,572,864 tets x 4 points =
+    6,291,456 points; 3-Gaussian-mixture source (seed 2, sigma 0.1);
+    N = 65,536 targets from another mixture (means seed 3, samples seed 4);
+    nu uniform, eps = 1e-3."""
+    p = cube_mixture(64, 65536, 1e-3)
+    p.name = "cube64_tet4_mix_nq6291456_n65536_eps1e-3"
+    return p
+
+
+def gaussian_blob_square(n_cells: int, centre, s: float, y: np.ndarray,
+                         eps: float) -> Problem:
+    """Unit square with rho(x) = exp(-|x-c|^2 / (2 s^2)), P1-interpolated."""
+    mesh = square_mesh(n_cells)
+    c = np.asarray(centre, dtype=np.float64)
+    rho_v = np.exp(-((mesh.verts - c) ** 2).sum(1) / (2.0 * s * s))
+    x, mu = quadrature(mesh, rho_v)
+    nu = np.full(y.shape[0], 1.0 / y.shape[0])
+    return Problem(x, mu, y, nu, eps)
+
+
+def config4_instance(i: int, n_cells: int = 128, n_targets: int = 65536) -> Problem:
+    """Instance i of the learned-warm-start family: c ~ U[0.2,0.8]^2,
+    s ~ U[0.05,0.2], eps ~ logU[1e-3,1e-1] (seed 1000+i); fixed cloud of
+    uniform targets (seed 7)."""
+    rng = np.random.default_rng(1000 + i)
+    c = rng.uniform(0.2, 0.8, size=2)
+    s = rng.uniform(0.05, 0.2)
+    eps = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e-1))))
+    y = uniform_targets(7, n_targets, 2)
+    p = gaussian_blob_square(n_cells, c, s, y, eps)
+    p.name = f"blob{i}"
+    p.meta = {"c": c, "s": s}
+    return p
+
+
+def config5_instance(i: int, scale: float = 1.0) -> Problem:
+    """Instance i of the batched family (seed 2000+i): N_q ~ logU[1e5, 4e6]
+    realised as a cube of n^3 x 24 points, N ~ logU[4096, 262144], mixture
+    source and targets (sigma 0.1), eps ~ logU[1e-4, 1e-2]. ``scale`` shrinks
+    both sizes for tests."""
+    rng = np.random.default_rng(2000 + i)
+    nq_t = float(np.exp(rng.uniform(np.log(1e5), np.log(4e6)))) * scale
+    n_t = float(np.exp(rng.uniform(np.log(4096), np.log(262144)))) * scale
+    eps = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+    n_cells = max(2, int(round((nq_t / 24.0) ** (1.0 / 3.0))))
+    n_targets = max(8, int(round(n_t)))
+    src_seed, tm_seed, ts_seed = rng.integers(0, 2**31, size=3)
+    p = cube_mixture(n_cells, n_targets, eps, int(src_seed), int(tm_seed), int(ts_seed))
+    p.name = f"batch{i}"
+    return p
+
+
+def disk_hierarchy(rings: int = 60, levels: int = 4):
+    """Nested disk meshes L0..L(levels-1) with uniform density."""
+    meshes = [disk_mesh(rings)]
+    for _ in range(levels - 1):
+        meshes.append(refine_triangles(meshes[-1], radius=1.0))
+    return meshes
+
+
+def blob_targets_disk(n: int, seed: int = 5, k: int = 5, sigma: float = 0.08,
+                      rmax: float = 0.6) -> np.ndarray:
+    """n points from an equal-weight k-blob mixture, means uniform in the disk
+    of radius rmax."""
+    rng = np.random.default_rng(seed)
+    r = rmax * np.sqrt(rng.uniform(size=k))
+    a = rng.uniform(0, 2 * np.pi, size=k)
+    means = np.stack([r * np.cos(a), r * np.sin(a)], axis=1)
+    return mixture_samples(rng, means, sigma, n)
+
+
+def random_psi(seed: int, n: int, scale: float) -> np.ndarray:
+    return scale * np.random.default_rng(seed).standard_normal(n)

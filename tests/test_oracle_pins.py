@@ -1,0 +1,329 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test ties an oracle function to something other than itself: a closed
+form, an invariant, a limit, a library routine or an independent algorithm.
+A dropped term, a wrong sign, index or operand in the oracle fails at least
+one of them (see the note on each test).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import logsumexp, softmax
+from scipy.spatial import cKDTree
+
+import oracle
+from paper_2507_23602_amd import workloads as W
+
+
+def _tiny(d, nq_cells, n, seed, eps, psi_scale=0.0, nu_random=True):
+    rng = np.random.default_rng(seed)
+    mesh = W.square_mesh(nq_cells) if d == 2 else W.cube_mesh(nq_cells)
+    rho_v = rng.uniform(0.5, 1.5, size=mesh.verts.shape[0])
+    x, mu = W.quadrature(mesh, rho_v)
+    y = rng.uniform(-0.1, 1.1, size=(n, d))
+    nu = rng.uniform(0.5, 1.5, size=n) if nu_random else np.ones(n)
+    nu /= nu.sum()
+    psi = psi_scale * rng.standard_normal(n)
+    return x, mu, y, nu, psi
+
+
+# -- library routine: scipy's weighted logsumexp / softmax ------------------
+# Catches: a dropped ln nu_j, a wrong cost scale, a sign error on psi, a
+# missing mu_q weight or the -sum psi nu term.
+@pytest.mark.parametrize("d", [2, 3])
+def test_library_logsumexp_pin(d):
+    eps = 0.03
+    x, mu, y, nu, psi = _tiny(d, 3, 9, seed=11 + d, eps=eps, psi_scale=0.02)
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps, want_L=True)
+    sq = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    a = (psi[None, :] - 0.5 * sq) / eps
+    L = logsumexp(a, b=nu[None, :], axis=1)
+    J = eps * np.dot(mu, L) - np.dot(psi, nu)
+    P = softmax(a + np.log(nu)[None, :], axis=1)
+    g = mu @ P - nu
+    assert abs(r.J - J) <= 1e-13 * abs(J)
+    np.testing.assert_allclose(r.L, L, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r.grad, g, rtol=0, atol=1e-15)
+
+
+# -- closed form, one target --------------------------------------------------
+# rho = 1 on the unit square/cube, N = 1, nu = 1: L_q = (psi - c_q)/eps so
+# J = -int 1/2 |x - y|^2 dx = -(1/2 |y - 1/2|^2 + d/24) exactly (degree-2 rules
+# are exact for quadratics), for every psi and eps; grad = sum mu - 1 = 0.
+# Catches: a wrong cost scale, a missing eps factor, a missing -psi nu term.
+@pytest.mark.parametrize("d,cells", [(2, 6), (3, 3)])
+@pytest.mark.parametrize("psi0,eps", [(0.0, 1e-2), (0.37, 1e-3), (-2.0, 0.5)])
+def test_one_target_closed_form(d, cells, psi0, eps):
+    mesh = W.square_mesh(cells) if d == 2 else W.cube_mesh(cells)
+    x, mu = W.quadrature(mesh)
+    y = np.array([[0.3, 0.8, 0.55][:d]])
+    r = oracle.dual_eval(x, mu, y, np.ones(1), np.array([psi0]), eps)
+    exact = -(0.5 * np.sum((y[0] - 0.5) ** 2) + d / 24.0)
+    assert abs(r.J - exact) < 1e-13
+    assert abs(r.grad[0]) < 1e-13
+
+
+# -- large eps asymptote --------------------------------------------------------
+# psi = 0: J -> -sum_j nu_j int c(x, y_j) dx as eps -> inf, and with rho = 1
+# the integral is 1/2 |y_j - 1/2|^2 + d/24; the gap shrinks like 1/eps.
+def test_large_eps_limit():
+    x, mu = W.quadrature(W.square_mesh(6))
+    rng = np.random.default_rng(5)
+    y = rng.uniform(0, 1, size=(7, 2))
+    nu = rng.uniform(0.5, 1.5, 7)
+    nu /= nu.sum()
+    limit = -np.dot(nu, 0.5 * ((y - 0.5) ** 2).sum(1) + 2 / 24.0)
+    errs = []
+    for eps in [1e2, 1e3, 1e4]:
+        errs.append(abs(oracle.dual_eval(x, mu, y, nu, np.zeros(7), eps).J - limit))
+    assert errs[1] < errs[0] / 5 and errs[2] < errs[1] / 5
+    assert errs[2] < 1e-5
+
+
+# -- finite differences of the objective ----------------------------------------
+# Catches any mismatch between the gradient and the objective (sign, index,
+# missing mu_q, nu_k term).
+@pytest.mark.parametrize("d", [2, 3])
+def test_gradient_matches_finite_differences(d):
+    eps = 0.05
+    x, mu, y, nu, psi = _tiny(d, 3, 11, seed=3 + d, eps=eps, psi_scale=0.03)
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps)
+    rng = np.random.default_rng(99)
+    for _ in range(3):
+        v = rng.standard_normal(psi.shape[0])
+        h = 1e-5
+        Jp = oracle.dual_eval(x, mu, y, nu, psi + h * v, eps, want_grad=False).J
+        Jm = oracle.dual_eval(x, mu, y, nu, psi - h * v, eps, want_grad=False).J
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - r.grad.dot(v)) <= 1e-8 * np.abs(r.grad).dot(np.abs(v)) + 1e-10
+
+
+# -- invariants -------------------------------------------------------------------
+# sum_j grad_j = sum mu - sum nu (sum_j p_qj = 1, Sec. 2); grad invariant and J
+# shifted by t (sum mu - sum nu) under psi -> psi + t; L_q between max_j z_qj
+# and max_j z_qj + ln N (the log-sum-exp bounds used in App. A).
+def test_conservation_and_shift():
+    eps = 0.02
+    x, mu, y, nu, psi = _tiny(2, 5, 13, seed=21, eps=eps, psi_scale=0.05)
+    mu = mu * 1.3                          # deliberately unbalanced masses
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps, want_L=True)
+    assert abs(r.grad.sum() - (mu.sum() - nu.sum())) < 1e-13
+    t = 0.123
+    r2 = oracle.dual_eval(x, mu, y, nu, psi + t, eps)
+    np.testing.assert_allclose(r2.grad, r.grad, rtol=0, atol=1e-14)
+    assert abs(r2.J - (r.J + t * (mu.sum() - nu.sum()))) < 1e-13
+    sq = ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    zmax = ((psi[None, :] - 0.5 * sq) / eps + np.log(nu)[None, :]).max(1)
+    assert np.all(r.L >= zmax - 1e-12)
+    assert np.all(r.L <= zmax + np.log(len(nu)) + 1e-12)
+
+
+# -- symmetry of the meshes ---------------------------------------------------------
+# The "/" split square mesh is invariant under x -> 1 - x and (x1, x2) -> (x2, x1);
+# mirrored targets with equal mass get equal gradients at psi = 0, and a solved
+# potential is symmetric. Catches index/transposition mistakes.
+def test_symmetry():
+    x, mu = W.quadrature(W.square_mesh(8))
+    a = np.array([0.21, 0.64])
+    y = np.array([a, 1.0 - a, a[::-1], 1.0 - a[::-1]])
+    nu = np.full(4, 0.25)
+    r = oracle.dual_eval(x, mu, y, nu, np.zeros(4), 0.01)
+    assert abs(r.grad[0] - r.grad[1]) < 1e-14
+    assert abs(r.grad[2] - r.grad[3]) < 1e-14
+    assert abs(r.grad[0] - r.grad[2]) < 1e-14
+
+
+# -- eps -> 0: power diagram by brute force (Remark 2.1) ------------------------------
+def test_eps_to_zero_power_cells_bruteforce():
+    x, mu = W.quadrature(W.square_mesh(8))
+    rng = np.random.default_rng(7)
+    y = rng.uniform(0.1, 0.9, size=(4, 2))
+    psi = 0.05 * rng.standard_normal(4)
+    nu = np.full(4, 0.25)
+    eps = 1e-6
+    masses, gap = oracle.power_cell_masses(x, mu, y, psi)
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps)
+    nut = r.grad + nu
+    amb = mu[gap < 50 * eps].sum()         # points too close to a cell boundary
+    assert np.abs(nut - masses).sum() <= 2 * amb + 1e-15
+
+
+# -- eps -> 0 and h -> 0: exact Laguerre cell areas by polygon clipping ----------------
+def test_laguerre_areas_limit():
+    rng = np.random.default_rng(17)
+    y = rng.uniform(0.15, 0.85, size=(5, 2))
+    psi = 0.03 * rng.standard_normal(5)
+    exact = oracle.laguerre_areas_2d(y, psi)
+    assert abs(exact.sum() - 1.0) < 1e-12
+    nu = np.full(5, 0.2)
+    errs = []
+    for n in [8, 16, 32, 64]:
+        x, mu = W.quadrature(W.square_mesh(n))
+        r = oracle.dual_eval(x, mu, y, nu, psi, 1e-7)
+        errs.append(np.abs(r.grad + nu - exact).sum())
+    # boundary points are misclassified at a rate O(h)
+    assert errs[-1] < 0.03
+    assert errs[-1] < errs[0] / 3
+
+
+# -- quadrature convergence against the continuous two-target closed form -----------
+# Theorem 3.1's setting: nu~_1 -> int sigma((a - b x1)/eps) dx as h -> 0.
+def test_two_target_quadrature_convergence():
+    y = np.array([[0.3, 0.5], [0.7, 0.5]])
+    nu = np.array([0.5, 0.5])
+    psi = np.array([0.02, -0.01])
+    eps = 0.05
+    b = 0.4
+    a = psi[0] - psi[1] + 0.5 * (y[1].dot(y[1]) - y[0].dot(y[0]))
+    exact = oracle.two_target_mass(a, b, eps)
+    errs = []
+    for n in [4, 8, 16, 32]:
+        x, mu = W.quadrature(W.square_mesh(n))
+        r = oracle.dual_eval(x, mu, y, nu, psi, eps)
+        errs.append(abs(r.grad[0] + nu[0] - exact))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert min(rates) > 1.9, (errs, rates)
+    assert errs[-1] < 1e-5
+
+
+# -- solver: L-BFGS psi* against an independent log-domain Sinkhorn -----------------
+def test_lbfgs_matches_sinkhorn():
+    x, mu = W.quadrature(W.square_mesh(8))
+    rng = np.random.default_rng(4)
+    y = rng.uniform(0, 1, size=(16, 2))
+    nu = rng.uniform(0.5, 1.5, 16)
+    nu /= nu.sum()
+    eps = 0.05
+
+    def fun(p):
+        r = oracle.dual_eval(x, mu, y, nu, p, eps)
+        return r.J, r.grad
+
+    psi, J, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(16), tol=1e-11)
+    assert np.abs(g).sum() <= 1e-11
+    ps = oracle.sinkhorn_psi(x, mu, y, nu, eps)
+    c1 = psi - np.dot(nu, psi)
+    c2 = ps - np.dot(nu, ps)
+    np.testing.assert_allclose(c1, c2, rtol=0, atol=1e-9)
+
+
+# -- truncation: sign and bound (App. B) ----------------------------------------------
+def test_truncation_geom_bound():
+    eps = 0.01
+    x, mu, y, nu, psi = _tiny(2, 10, 40, seed=8, eps=eps, psi_scale=0.01)
+    y = np.clip(y, 0, 1)
+    dense = oracle.dual_eval(x, mu, y, nu, psi, eps)
+    C0 = oracle.covering_cost(x, y)
+    for tau in [1e-2, 1e-4, 1e-8]:
+        C = oracle.cutoff_geom(C0, psi, nu, tau, abs(dense.J), eps)
+        tr = oracle.dual_eval(x, mu, y, nu, psi, eps, cutoff=C)
+        assert tr.nempty == 0
+        assert tr.kept < x.shape[0] * y.shape[0]
+        E = dense.J - tr.J
+        assert 0.0 <= E <= tau * abs(dense.J)
+        # the truncated gradient still renormalises over I_q
+        assert abs(tr.grad.sum() - (mu.sum() - nu.sum())) < 1e-13
+
+
+def test_truncation_integral_bound_fixed_point():
+    eps = 0.01
+    x, mu, y, nu, psi = _tiny(2, 10, 40, seed=9, eps=eps, psi_scale=0.01)
+    y = np.clip(y, 0, 1)
+    dense = oracle.dual_eval(x, mu, y, nu, psi, eps)
+    C0 = oracle.covering_cost(x, y)
+    tau = 1e-3
+    C = np.inf
+    D = oracle.integral_D(mu, dense.L if dense.L is not None else
+                          oracle.dual_eval(x, mu, y, nu, psi, eps, want_L=True).L)
+    for _ in range(6):                    # lag D by one evaluation, as in Sec. 4.1
+        C = oracle.cutoff_int(C0, psi, D, tau, abs(dense.J), eps)
+        tr = oracle.dual_eval(x, mu, y, nu, psi, eps, cutoff=C, want_L=True)
+        D = oracle.integral_D(mu, tr.L)
+    # at the fixed point C satisfies Eq. truncation_cutoff_int with its own D
+    assert C >= psi.max() + eps * math.log(eps * D / (tau * abs(dense.J))) - 1e-12
+    assert 0.0 <= dense.J - tr.J <= tau * abs(dense.J)
+
+
+def test_truncation_pointwise_rule():
+    eps = 0.01
+    x, mu, y, nu, psi = _tiny(2, 6, 30, seed=10, eps=eps, psi_scale=0.02)
+    delta = 1e-6
+    C = oracle.cutoff_pw(psi, nu, delta, eps)
+    tr = oracle.dual_eval(x, mu, y, nu, psi, eps, cutoff=C)
+    sq = 0.5 * ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    dropped = sq >= C
+    terms = nu[None, :] * np.exp((psi[None, :] - sq) / eps)
+    assert np.all(terms[dropped] < delta)        # Eq. pointwise_criterion
+    assert tr.kept == int((~dropped).sum())
+
+
+def test_covering_cost_against_kdtree():
+    x, mu = W.quadrature(W.cube_mesh(4))
+    y = np.random.default_rng(2).uniform(0, 1, size=(37, 3))
+    dist, _ = cKDTree(y).query(x)
+    assert abs(oracle.covering_cost(x, y) - 0.5 * dist.max() ** 2) < 1e-15
+
+
+# -- tile-local bound (derived from App. B) ---------------------------------------------
+def test_tile_rule_bound_and_degenerate_cases():
+    eps = 0.002
+    x, mu = W.quadrature(W.square_mesh(16))
+    rng = np.random.default_rng(12)
+    y = rng.uniform(0, 1, size=(256, 2))
+    nu = np.full(256, 1 / 256)
+    psi = 0.002 * rng.standard_normal(256)
+    dense = oracle.dual_eval(x, mu, y, nu, psi, eps)
+    # spatial groups: tiles of 16 points sorted by (cell row, col), blocks of 16 targets
+    qo = np.lexsort((x[:, 1], np.floor(x[:, 0] * 8)))
+    tile_of = np.empty(x.shape[0], np.int32)
+    tile_of[qo] = np.arange(x.shape[0]) // 16
+    to = np.lexsort((y[:, 1], np.floor(y[:, 0] * 4)))
+    block_of = np.empty(256, np.int32)
+    block_of[to] = np.arange(256) // 16
+    nt, nb = x.shape[0] // 16, 16
+    for tau in [1e-3, 1e-8, 1e-12]:
+        r = oracle.dual_eval_tile(x, mu, y, nu, psi, eps, tile_of, nt, block_of, nb,
+                                  tau, abs(dense.J), want_keep=True)
+        E = dense.J - r.J
+        assert 0.0 <= E <= tau * abs(dense.J)
+        assert r.keep.any(axis=1).all()
+        assert abs(r.grad.sum() - (mu.sum() - nu.sum())) < 1e-13
+        if tau == 1e-3:
+            assert r.kept < 0.55 * x.shape[0] * 256
+    # tau -> 0 keeps every pair: equals dense
+    r = oracle.dual_eval_tile(x, mu, y, nu, psi, eps, tile_of, nt, block_of, nb,
+                              1e-300, abs(dense.J))
+    assert r.kept == x.shape[0] * 256
+    assert abs(r.J - dense.J) <= 1e-14 * abs(dense.J)
+
+
+# -- softmax refinement (Eq. softmax_refinement_formula) -----------------------------------
+# With fine targets = coarse targets the formula is one Sinkhorn half-step:
+# psi_init_k = psi_k - eps ln(nu~_k / nu_k); at the optimum it returns psi*.
+def test_softmax_refine_identity_and_fixed_point():
+    eps = 0.03
+    x, mu, y, nu, psi = _tiny(2, 6, 12, seed=31, eps=eps, psi_scale=0.02)
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps, want_L=True)
+    out = oracle.softmax_refine(x, mu, r.L, y, eps)
+    np.testing.assert_allclose(out, psi - eps * np.log((r.grad + nu) / nu), rtol=0, atol=1e-13)
+
+    def fun(p):
+        e = oracle.dual_eval(x, mu, y, nu, p, eps)
+        return e.J, e.grad
+
+    ps, *_ = oracle.lbfgs_solve(fun, np.zeros(12), tol=1e-12)
+    L = oracle.dual_eval(x, mu, y, nu, ps, eps, want_L=True).L
+    np.testing.assert_allclose(oracle.softmax_refine(x, mu, L, y, eps), ps, rtol=0, atol=1e-10)
+
+
+def test_empty_set_handling_pointwise():
+    # a cutoff below the covering cost leaves points with empty I_q; they are
+    # dropped (the S_q > 0 test of Alg. 2) and counted
+    x, mu = W.quadrature(W.square_mesh(4))
+    y = np.array([[0.1, 0.1]])
+    r = oracle.dual_eval(x, mu, y, np.ones(1), np.zeros(1), 0.01, cutoff=0.05, want_L=True)
+    sq = 0.5 * ((x - y[0]) ** 2).sum(1)
+    assert r.nempty == int((sq >= 0.05).sum()) > 0
+    assert np.all(np.isneginf(r.L[sq >= 0.05]))
+    assert abs((r.grad[0] + 1.0) - mu[sq < 0.05].sum()) < 1e-14
