@@ -1,0 +1,244 @@
+"""Benchmark of the RSOT dual evaluation on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one rsot_dual_eval (objective + gradient, dense, mixed precision)
+on the 3D workload: unit cube, 64^3 cells x 6 Kuhn tetrahedra x 4 points =
+6,291,456 quadrature points, 3-Gaussian-mixture source, 65,536 mixture
+targets, eps = 1e-3, psi a seeded N(0, eps^2) perturbation. Inputs are
+resident in device memory before the timed region. The JSON line (stdout)
+reports dense pairs/s as ``value`` plus the truncated rules, the FP64 path,
+the time to ||grad||_1 < 1e-6 on the 2D workload, the roofline of the
+dominant kernel and the CPU oracle on a bounded sample. Progress goes to
+stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X figures used by the roofline (256 CUs at 2.4 GHz):
+#   FP32 vector 157.3 TFLOP/s -> 7.86e13 lane-ops/s (128 lanes/clk/CU, an FMA
+#   counted as one op); the rate probe reaches 6.26e13/s with non-packed
+#   v_fma_f32, so no packed instructions are needed to approach it.
+#   v_exp_f32 at a quarter of that: 32 lanes/clk/CU = 1.966e13/s (probe:
+#   1.905e13/s). These are the published FP32 rate and the transcendental
+#   quarter rate; the per-pair op counts are the algorithm's, not the kernel's.
+PEAK_VALU_OPS = 256 * 2.4e9 * 128          # 7.86e13 FP32 lane-ops/s
+PEAK_EXP = 256 * 2.4e9 * 32                # 1.966e13 exp/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pair_roofline(d: int, n_exp: int, n_ops: int) -> float:
+    """pairs/s at the ALU roofline for n_exp exponentials and n_ops FP32 ops per pair"""
+    return 1.0 / (n_exp / PEAK_EXP + n_ops / PEAK_VALU_OPS)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one plain 256 MiB device copy first (scale for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU path is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calib:
+        a = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del a, b
+    t0 = time.time()
+    p = W.config2()
+    log(f"[bench] workload {p.name}: nq={p.nq} n={p.n} eps={p.eps} (gen {time.time()-t0:.1f}s)")
+    x_d = torch.as_tensor(p.x, device=dev)
+    mu_d = torch.as_tensor(p.mu, device=dev)
+    y_d = torch.as_tensor(p.y, device=dev)
+    nu_d = torch.as_tensor(p.nu, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    prob = rsot.Problem(x_d, mu_d, y_d, nu_d, precision="mixed")
+    torch.cuda.synchronize()
+    setup_s = time.time() - t1
+    log(f"[bench] setup (sort, tiles, boxes) {setup_s:.3f}s")
+    psi = torch.as_tensor(W.random_psi(11, p.n, p.eps), device=dev)
+    grad = torch.empty(p.n, dtype=torch.float64, device=dev)
+
+    def run(k):
+        infos = []
+        r = None
+        for _ in range(k):
+            r = prob.dual_eval(psi, p.eps, out=grad)
+            infos.append(r.info)
+        return r, infos
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    r, infos = run(args.steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t2) / args.steps
+    pairs = p.nq * p.n
+    value = pairs / dt
+    p1 = float(np.mean([i["pass1_ms"] for i in infos]))
+    p2 = float(np.mean([i["pass2_ms"] for i in infos]))
+    log(f"[bench] dense mixed: {dt*1e3:.2f} ms/eval, {value:.3e} pairs/s, "
+        f"pass1 {p1:.2f} ms, pass2 {p2:.2f} ms, J={r.J:.12e}")
+
+    d = 3
+    roof_p1 = pair_roofline(d, 1, 2 * d + 4)
+    roof_p2 = pair_roofline(d, 1, 2 * d + 3)
+    roof_all = pair_roofline(d, 2, 4 * d + 7)
+    if p1 >= p2:
+        name, ms, peak = "objective pass (k_pass1, dense)", p1, roof_p1
+    else:
+        name, ms, peak = "gradient pass (k_pass2, dense)", p2, roof_p2
+    achieved = pairs / (ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": name, "achieved": achieved / 1e9,
+                "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
+                "traffic": None,
+                "eval_frac": value / roof_all, "eval_peak_Gpair_s": roof_all / 1e9}
+
+    out = {"metric": "quad-target pairs/s for dual obj+grad (dense, truncated); "
+                     "time-to-||g||1<1e-6",
+           "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64-arg/f32-exp/f64-acc",
+           "data": "synthetic",
+           "config": {"workload": p.name, "n_quad": p.nq, "n_target": p.n, "dim": 3,
+                      "eps": p.eps, "precision": "mixed", "truncation": "dense",
+                      "psi": "N(0, eps^2) seed 11"},
+           "roofline": roofline,
+           "setup_s": setup_s,
+           "J": r.J, "grad_l1": r.info["grad_l1"]}
+
+    if not args.no_extras:
+        extras = {}
+        absJ = abs(r.J)
+        for rule in ["geom", "tile"]:
+            prob.set_truncation(rule, tau=1e-12)
+            prob.set_reference(absJ)
+            rr = prob.dual_eval(psi, p.eps, out=grad)           # warm
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            k = max(2, args.steps)
+            for _ in range(k):
+                rr = prob.dual_eval(psi, p.eps, out=grad)
+            torch.cuda.synchronize()
+            tt = (time.perf_counter() - ts) / k
+            kept = rr.info["kept_pairs"]
+            extras[rule] = {"ms_per_eval": tt * 1e3, "effective_pairs_s": pairs / tt,
+                            "kept_pairs": kept, "kept_frac": kept / pairs,
+                            "kept_pairs_s": kept / tt, "J": rr.J,
+                            "J_minus_dense_rel": (r.J - rr.J) / absJ,
+                            "cutoff": rr.info["cutoff"], "setup_ms": rr.info["setup_ms"],
+                            "pass1_ms": rr.info["pass1_ms"], "pass2_ms": rr.info["pass2_ms"]}
+            log(f"[bench] {rule}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
+                f"effective {pairs/tt:.3e} pairs/s, kept {kept/tt:.3e} pairs/s")
+        prob.set_truncation("dense")
+        prob.set_precision("fp64")
+        rr = prob.dual_eval(psi, p.eps, out=grad)
+        ts = time.perf_counter()
+        rr = prob.dual_eval(psi, p.eps, out=grad)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - ts
+        extras["fp64_dense"] = {"ms_per_eval": tf * 1e3, "pairs_s": pairs / tf, "J": rr.J,
+                                "J_mixed_minus_fp64_rel": (r.J - rr.J) / abs(rr.J)}
+        g64 = grad.clone()
+        prob.set_precision("mixed")
+        rm = prob.dual_eval(psi, p.eps, out=grad)
+        nu_t = torch.as_tensor(p.nu, device=dev)
+        eg = torch.max(torch.abs(grad - g64) / (nu_t + g64 + nu_t)).item()
+        extras["fp64_dense"]["grad_err_mixed_vs_fp64"] = eg
+        log(f"[bench] fp64 dense: {tf*1e3:.1f} ms/eval; mixed vs fp64: "
+            f"J rel {(rm.J - rr.J)/abs(rr.J):.2e}, grad err {eg:.2e}")
+        prob.close()
+
+        # time to ||grad||_1 < 1e-6 on the 2D workload (FP64 path)
+        c1 = W.config1()
+        pr1 = rsot.Problem(c1.x, c1.mu, c1.y, c1.nu, precision="fp64")
+        pr1.solve([c1.eps], tol=1e-6)                     # warm (kernels loaded)
+        ts = time.perf_counter()
+        psi1, info1 = pr1.solve([c1.eps], tol=1e-6)
+        tsol = time.perf_counter() - ts
+        extras["time_to_tol_config1"] = {"workload": c1.name, "seconds": tsol,
+                                         "iterations": info1["iterations"],
+                                         "evaluations": info1["evaluations"],
+                                         "grad_l1": info1["grad_l1"],
+                                         "status": info1["status"]}
+        log(f"[bench] config1 solve: {tsol*1e3:.1f} ms, {info1['iterations']} it, "
+            f"{info1['evaluations']} evals, |g|_1={info1['grad_l1']:.2e}")
+        pr1.close()
+        out["extras"] = extras
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
+                                           psi1 if not args.no_extras else None)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, psi, psi_c1):
+    """The oracle (plain FP64 C, OpenMP) on a bounded sample of the same
+    workload: a seeded subset of quadrature points against all targets,
+    sized to take ~15 s; pairs/s scaled to the sample."""
+    import oracle
+    from paper_2507_23602_amd import workloads as W
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(0)
+    probe = rng.choice(p.nq, size=2048, replace=False)
+    ts = time.perf_counter()
+    oracle.dual_eval(p.x[probe], p.mu[probe], p.y, p.nu, psi, p.eps, threads=threads)
+    tp = time.perf_counter() - ts
+    m = int(min(p.nq, max(2048, 2048 * 15.0 / max(tp, 1e-3))))
+    idx = rng.choice(p.nq, size=m, replace=False)
+    ts = time.perf_counter()
+    oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, threads=threads)
+    t = time.perf_counter() - ts
+    res = {"value": m * p.n / t, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+           "sample": f"{m} random quadrature points of the workload x all {p.n} targets "
+                     f"(dense objective + gradient), {t:.1f} s"}
+    log(f"[bench] cpu oracle: {res['value']:.3e} pairs/s on {threads} threads ({t:.1f}s)")
+    if psi_c1 is not None:
+        c1 = W.config1()
+
+        def fun(v):
+            e = oracle.dual_eval(c1.x, c1.mu, c1.y, c1.nu, v, c1.eps, threads=threads)
+            return e.J, e.grad
+        ts = time.perf_counter()
+        _, _, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(c1.n), tol=1e-6)
+        res["config1_solve_seconds"] = time.perf_counter() - ts
+        res["config1_solve_iterations"] = it
+        recheck = oracle.dual_eval(c1.x, c1.mu, c1.y, c1.nu, psi_c1, c1.eps, threads=threads)
+        res["config1_gpu_psi_grad_l1_recheck"] = float(np.abs(recheck.grad).sum())
+        log(f"[bench] cpu oracle config1 solve {res['config1_solve_seconds']:.2f}s ({it} it); "
+            f"recheck of GPU psi: |g|_1 = {res['config1_gpu_psi_grad_l1_recheck']:.2e}")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * rsot.h -- C ABI of the MI355X semi-discrete RSOT dual library (librsot.so).
+ *
+ * The library evaluates, for a source measure given as quadrature points
+ * {x_q, mu_q} (mu_q = rho_h(x_q) w_q, Sec. 3.2 Remark 3.1) and a discrete
+ * target measure {y_j, nu_j} (Sec. 2), the discretised dual objective
+ *
+ *   J(psi) = sum_q eps ln( sum_j nu_j exp((psi_j - c(x_q,y_j))/eps) ) mu_q
+ *            - sum_j psi_j nu_j                       (Eq. discretized_functional)
+ *
+ * and its gradient
+ *
+ *   dJ/dpsi_k = sum_q p_k(x_q|psi) mu_q - nu_k        (Eq. discretized_gradient)
+ *
+ * with p_k the plan density of Eq. final_plan_density and the cost
+ * c(x, y) = cost_scale |x - y|^2 (Sec. 2 uses cost_scale = 1/2). J is the
+ * convex functional the paper minimises; the gradient has the paper's sign
+ * (target marginal of the plan minus nu).
+ *
+ * Conventions for every call:
+ *   - Every call returns an rsot_status; nothing throws or aborts across the
+ *     ABI. Outputs are left untouched unless RSOT_OK is returned, except
+ *     rsot_solve*, which always write the best accepted potential and info.
+ *   - Arrays are row-major: points are n x dim doubles.
+ *   - "device pointer" means memory of the current HIP device (e.g. a torch
+ *     CUDA tensor's data_ptr()); "host pointer" means ordinary host memory.
+ *   - Work is issued on the HIP stream given at creation, in stream order.
+ *   - Handles are not thread safe: one handle, one host thread at a time.
+ */
+#ifndef RSOT_H
+#define RSOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSOT_OK = 0,
+    RSOT_ERR_INVALID_ARG = 1,   /* bad size, dim, eps, option or NULL pointer     */
+    RSOT_ERR_NONFINITE = 2,     /* NaN/Inf in x, mu, y, nu or psi                  */
+    RSOT_ERR_UNBALANCED = 3,    /* |sum mu - sum nu| > 1e-12 sum nu (solve only)   */
+    RSOT_ERR_DEVICE = 4,        /* a HIP call failed                               */
+    RSOT_ERR_OOM = 5,           /* device allocation failed or exceeds mem_limit   */
+    RSOT_ERR_LINESEARCH = 6,    /* line search found no acceptable step            */
+    RSOT_ERR_NOT_CONVERGED = 7, /* iteration cap reached before ||grad||_1 <= tol  */
+    RSOT_ERR_CANCELLED = 8      /* cancel flag or callback asked to stop           */
+} rsot_status;
+
+/* Arithmetic of the pair loop.
+ * MIXED: exponent arguments formed in FP64, exponentials and per-chunk sums
+ *        in FP32, per-point log-sum-exp, per-target sums and J in FP64.
+ * FP64 : everything in FP64 (software exp2). */
+typedef enum { RSOT_PREC_MIXED = 0, RSOT_PREC_FP64 = 1 } rsot_precision;
+
+/* Which (point, target) pairs enter the sums.
+ * DENSE: all (Eqs. discretized_functional/gradient).
+ * GEOM : c < C_geom, Eq. truncation_cutoff_geom (paper default).
+ * INT  : c < C_int, Eq. truncation_cutoff_int, D lagged one evaluation.
+ * PW   : c < C_pw, Eq. cost_cutoff_delta.
+ * TILE : tile-local bound derived from App. B: pairs of (point tile, target
+ *        block) whose bound is below tau |J_ref| eps-scaled are skipped whole;
+ *        J_dense - J_trunc <= tau |J_ref|. */
+typedef enum {
+    RSOT_TRUNC_DENSE = 0,
+    RSOT_TRUNC_GEOM = 1,
+    RSOT_TRUNC_INT = 2,
+    RSOT_TRUNC_PW = 3,
+    RSOT_TRUNC_TILE = 4
+} rsot_truncation;
+
+typedef struct {
+    double cost_scale;        /* c(x,y) = cost_scale |x-y|^2; default 0.5         */
+    int precision;            /* rsot_precision; default MIXED                     */
+    int truncation;           /* rsot_truncation; default DENSE                    */
+    double tau;               /* relative error tolerance (GEOM, INT, TILE); 1e-12 */
+    double delta_thr;         /* pointwise threshold (PW); default 1e-12           */
+    int inputs_on_device;     /* 1: x, mu, y, nu passed to create are device ptrs  */
+    int seg_tiles;            /* gradient pass: point tiles per work item; 0=auto  */
+    int chunk_log2;           /* reserved for the autotuner; 0 = default           */
+    int64_t mem_limit_bytes;  /* cap on library device memory; 0 = none            */
+} rsot_options;
+
+typedef struct rsot_problem rsot_problem;
+
+typedef struct {
+    int64_t total_pairs;      /* N_q * N                                           */
+    int64_t kept_pairs;       /* pairs summed in the objective pass                */
+    int64_t n_empty_qp;       /* points whose kept set was empty (dropped, Alg. 2) */
+    double cutoff;            /* C used by GEOM/INT/PW, else 0                     */
+    double absJ_ref;          /* |J| the cutoff rule used                           */
+    double log_D;             /* ln sum_q mu_q exp(-L_q)  (D of Sec. 4.1)           */
+    double grad_l1;           /* ||grad||_1  (Remark 3.2)                           */
+    double grad_linf;         /* ||grad||_inf                                       */
+    double kernel_ms;         /* device time of the evaluation (HIP events)        */
+    double setup_ms;          /* of which: target records, cutoff and culling      */
+    double passes_ms;         /* of which: objective + gradient passes             */
+    double pass1_ms;          /* objective pass (per-point log-sum-exp)            */
+    double pass2_ms;          /* gradient pass (per-target masses)                 */
+    int dense_fallback;       /* 1 if a truncated rule ran dense (no |J| yet)       */
+} rsot_eval_info;
+
+/* Fills *opt with the defaults listed above. */
+void rsot_options_default(rsot_options *opt);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *rsot_status_string(rsot_status s);
+
+/*
+ * Creates a problem: copies the source quadrature measure and the targets
+ * into library-owned device buffers (spatially sorted, padded), so the
+ * caller keeps ownership of its arrays and may free them afterwards.
+ *   dim          2 or 3
+ *   n_quad, x,mu quadrature points (n_quad x dim) and masses (n_quad), mu >= 0,
+ *                sum mu > 0 (Sec. 3.2, Remark 3.1)
+ *   n_target,y,nu targets (n_target x dim) and masses nu > 0 (Sec. 2)
+ *   opt          options (NULL = defaults); opt->inputs_on_device selects
+ *                host or device pointers for x, mu, y, nu
+ *   hip_stream   hipStream_t to issue work on (NULL = default stream)
+ *   out          receives the handle
+ * Errors: INVALID_ARG (dim, sizes, NULL, options), NONFINITE, OOM, DEVICE.
+ */
+rsot_status rsot_problem_create(int dim, int64_t n_quad, const double *x, const double *mu,
+                                int64_t n_target, const double *y, const double *nu,
+                                const rsot_options *opt, void *hip_stream,
+                                rsot_problem **out);
+
+/* Frees all library-owned memory of the problem. Safe on NULL. */
+void rsot_problem_destroy(rsot_problem *p);
+
+/* Sizes of a problem (any pointer may be NULL). */
+rsot_status rsot_problem_sizes(const rsot_problem *p, int *dim, int64_t *n_quad,
+                               int64_t *n_target);
+
+/* Changes the truncation rule / tolerances of an existing problem. */
+rsot_status rsot_set_truncation(rsot_problem *p, int truncation, double tau, double delta_thr);
+
+/* Changes the arithmetic (rsot_precision) of an existing problem. */
+rsot_status rsot_set_precision(rsot_problem *p, int precision);
+
+/*
+ * Sets |J_ref|, the magnitude of J used by the GEOM, INT and TILE rules
+ * (Eqs. truncation_cutoff_geom/int: |J(psi)| of the current iterate, read here
+ * as the last accepted one). 0 clears it: the next truncated evaluation then
+ * runs dense and stores its own |J|.
+ */
+rsot_status rsot_set_reference(rsot_problem *p, double absJ_ref);
+
+/*
+ * Evaluates J(psi) and grad J(psi) (Eqs. discretized_functional/gradient;
+ * Alg. 2 with the problem's truncation rule).
+ *   eps       regularisation > 0 (Sec. 2)
+ *   psi       DEVICE pointer, n_target doubles, caller's target order
+ *   J_out     HOST pointer, receives J
+ *   grad_out  DEVICE pointer, n_target doubles in caller's order, or NULL for
+ *             the objective only
+ *   info      HOST pointer or NULL
+ * The call synchronises the problem's stream before returning (J is a host
+ * value). Errors: INVALID_ARG, NONFINITE (psi), DEVICE, OOM.
+ */
+rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi, double *J_out,
+                           double *grad_out, rsot_eval_info *info);
+
+/*
+ * Per-point log-sum-exp L_q = ln sum_j nu_j exp((psi_j - c_qj)/eps) of the
+ * last evaluation (the log of S_q in Alg. 2; -inf for a dropped point), in
+ * the caller's point order. L_out: DEVICE pointer, n_quad doubles.
+ */
+rsot_status rsot_get_lse(rsot_problem *p, double *L_out);
+
+/*
+ * Covering cost C_0 = max_q min_j c(x_q, y_j) (Sec. 4.1 / App. B, maximum
+ * over the quadrature points). C0_out: HOST pointer.
+ */
+rsot_status rsot_covering_cost(rsot_problem *p, double *C0_out);
+
+/*
+ * Tile structure of the problem (for checking the TILE rule against an
+ * independent implementation): for every point (caller's order) its tile id,
+ * for every target its block id. Both DEVICE pointers to int32, or NULL.
+ */
+rsot_status rsot_get_partition(rsot_problem *p, int32_t *tile_of_point, int32_t *block_of_target,
+                               int64_t *n_tiles, int64_t *n_blocks);
+
+/* ------------------------------------------------------------------------ */
+/* Solver (Alg. 1): L-BFGS on J with an eps schedule (Sec. 4.2).            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int stage;                /* index into the eps schedule                       */
+    int iteration;            /* accepted iterations in this stage                 */
+    int evaluations;          /* dual evaluations in this stage                     */
+    double eps;
+    double J, grad_l1, grad_linf, step;
+    int64_t kept_pairs;
+    double cutoff;
+} rsot_iter_info;
+
+/* Return nonzero to cancel the solve. */
+typedef int (*rsot_callback)(const rsot_iter_info *it, void *user);
+
+typedef struct {
+    const double *eps_schedule; /* HOST array: eps_0 > ... > eps_final (Sec. 4.2)  */
+    int n_eps;                  /* >= 1                                            */
+    double tol;                 /* stop when ||grad||_1 <= tol (Remark 3.2); 1e-6  */
+    int max_iter;               /* accepted iterations per stage; default 10000    */
+    int lbfgs_m;                /* history pairs; default 10                       */
+    double c1, c2;              /* Wolfe constants; default 1e-4, 0.9              */
+    int max_ls;                 /* evaluations per line search; default 20         */
+    double stage_tol;           /* ||grad||_1 target of non-final stages; 0 = tol  */
+    rsot_callback callback;     /* called after every accepted iteration, or NULL  */
+    void *user;
+    volatile int *cancel;       /* polled between evaluations, or NULL             */
+} rsot_solve_params;
+
+typedef struct {
+    int iterations;             /* accepted iterations, all stages                 */
+    int evaluations;            /* dual evaluations, all stages                    */
+    int stages;                 /* stages completed                                */
+    double J, grad_l1, grad_linf;
+    double seconds;             /* wall time of the solve                           */
+    double eval_ms;             /* device time spent in evaluations                */
+    int status;                 /* rsot_status of the solve                         */
+} rsot_solve_info;
+
+void rsot_solve_params_default(rsot_solve_params *sp);
+
+/*
+ * Minimises J with L-BFGS (Alg. 1, Sec. 3.4) through the eps schedule
+ * (Sec. 4.2), warm-starting each stage from the previous one.
+ *   psi_inout HOST pointer, n_target doubles: warm start in (zeros allowed),
+ *             solution out, centred so that sum_j nu_j psi_j = 0
+ *             (App. A: the minimiser is unique up to a constant).
+ * Errors: INVALID_ARG, UNBALANCED, NONFINITE, LINESEARCH, NOT_CONVERGED,
+ * CANCELLED, DEVICE; psi_inout and info hold the best accepted iterate.
+ */
+rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp, double *psi_inout,
+                       rsot_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSOT_H */

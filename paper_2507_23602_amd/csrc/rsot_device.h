@@ -1,0 +1,40 @@
+// Device helpers shared by the library's kernels (wavefront reductions and
+// box distances). Wavefront = 64 lanes on CDNA.
+#pragma once
+#include <hip/hip_runtime.h>
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// least distance between the intervals [a0,a1] and [b0,b1] along one axis
+__device__ inline double box_gap(double a0, double a1, double b0, double b1) {
+    if (b0 > a1) return b0 - a1;
+    if (a0 > b1) return a0 - b1;
+    return 0.0;
+}
+// greatest distance between a point of [a0,a1] and a point of [b0,b1]
+__device__ inline double box_far(double a0, double a1, double b0, double b1) {
+    return fmax(fabs(b1 - a0), fabs(a1 - b0));
+}
+// greatest distance between a point of [a0,a1] and the value y
+__device__ inline double box_far_pt(double a0, double a1, double y) {
+    return fmax(fabs(y - a0), fabs(a1 - y));
+}

@@ -1,0 +1,909 @@
+// One evaluation of J(psi) and grad J(psi) (Eqs. discretized_functional and
+// discretized_gradient; Alg. 2), re-derived for CDNA wavefronts.
+//
+// Exponents are carried in base 2. With kappa = log2(e)/eps and cs the cost
+// scale, for a point x (shifted coordinates) and a target y:
+//   z2(x, y_j) = log2(e) * ((psi_j - cs|x - y_j|^2)/eps + ln nu_j)
+//              = B_j + A(x) + x . Y_j
+//   B_j = kappa (psi_j - cs|y_j|^2) + log2 nu_j,   Y_j = 2 kappa cs y_j,
+//   A(x) = -kappa cs |x|^2.
+// The expansion is formed in FP64 (full rate on CDNA), so the argument of every
+// exponential carries ~1e-16 relative error before it is rounded to FP32; the
+// rounded argument is then O(10) for every term that matters, which keeps the
+// relative error of each weight near FP32 round-off.
+//
+// Objective pass (one wavefront = one 64-point tile, lane = point): the
+// per-point log-sum-exp Lt(x) = log2 sum_j 2^(B_j + x.Y_j) is accumulated
+// against an integer reference m that only grows, so rescaling the running
+// sum is an exact ldexp; target records are wave-uniform and reach the
+// wavefront through the scalar cache.
+// Gradient pass (one wavefront = one 64-target block, lane = target): the
+// target mass nu~_j = sum_q mu_q p_qj = sum_q 2^(B_j + S_q + x_q.Y_j) with
+// S_q = log2 mu_q - Lt(x_q) stored by the objective pass; point records are
+// wave-uniform. Each work item sums a segment of point tiles; segments are
+// merged per target in a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "rsot_device.h"
+#include "rsot_internal.h"
+
+#define RSOT_LN2 0.69314718055994530942
+#define RSOT_LOG2E 1.44269504088896340736
+#define CH 8   // pairs per chunk between FP64 flushes
+
+// v_exp_f32 is accurate to < 1 ulp (max relative error 8.4e-8 measured on
+// gfx950) but its error has a nonzero mean: -3.40e-9 relative over
+// arguments whose fractional parts are uniformly spread. Per-point sums
+// inherit that mean, and J = eps sum_q mu_q L_q picks it up as
+// eps * 3.4e-9 * sum mu. The FP32 chunk sums are therefore scaled by
+// 1 + 3.40e-9 (an FP64 multiply per chunk), which removes the mean and
+// leaves the zero-mean part, which averages out over points. The GPU tests
+// re-measure the mean on the device.
+#define RSOT_EXP2F_MEAN_CORR (1.0 + 3.40e-9)
+
+enum { MODE_DENSE = 0, MODE_LIST = 1, MODE_MASK = 2 };
+
+// ---------------------------------------------------------------------------
+// per-target records and block statistics
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_prep_targets(
+    const double *__restrict__ psi, const int32_t *__restrict__ tperm,
+    const double *__restrict__ ty, const double *__restrict__ tnu,
+    const double *__restrict__ tlog2nu, int64_t n_blocks, double kappa, double cs,
+    double4 *__restrict__ trec, double *__restrict__ tpsi, double *__restrict__ blk_stat) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= n_blocks) return;
+    const int64_t j = b * 64 + lane;
+    const int32_t src = tperm[j];
+    const bool real = src >= 0;
+    const double ps = real ? psi[src] : 0.0;
+    const double y0 = ty[j * 3 + 0], y1 = ty[j * 3 + 1], y2 = D == 3 ? ty[j * 3 + 2] : 0.0;
+    const double r2 = y0 * y0 + y1 * y1 + y2 * y2;
+    double4 rec;
+    rec.x = 2.0 * kappa * cs * y0;
+    rec.y = 2.0 * kappa * cs * y1;
+    rec.z = 2.0 * kappa * cs * y2;
+    rec.w = real ? kappa * (ps - cs * r2) + tlog2nu[j] : -INFINITY;
+    trec[j] = rec;
+    tpsi[j] = ps;
+    const bool fin = isfinite(ps);
+    const double vmax = wave_max(real && fin ? ps : -INFINITY);
+    const double vmin = wave_min(real && fin ? ps : INFINITY);
+    const double pn = wave_sum(real && fin ? ps * tnu[j] : 0.0);
+    const double nf = wave_sum(real && !fin ? 1.0 : 0.0);
+    if (lane == 0) {
+        blk_stat[b * 4 + 0] = vmax;
+        blk_stat[b * 4 + 1] = vmin;
+        blk_stat[b * 4 + 2] = pn;
+        blk_stat[b * 4 + 3] = nf;
+    }
+}
+
+// cutoff constant of the per-pair test: keep iff z2 > G_j + (per point term)
+__global__ void k_target_G(const double *__restrict__ tpsi, const double *__restrict__ tlog2nu,
+                           const int32_t *__restrict__ tperm, int64_t n_pad, double kappa,
+                           const double *__restrict__ dscal, double *__restrict__ tG) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_pad) return;
+    const double C = dscal[SC_C];
+    tG[j] = tperm[j] >= 0 ? kappa * (tpsi[j] - C) + tlog2nu[j] : INFINITY;
+}
+
+// Single workgroup: psi statistics and the cutoff of the T1 rules.
+//   GEOM (Eq. truncation_cutoff_geom): C0 + (M - m) + eps ln(eps/(nu_min tau |J|)), >= C0
+//   INT  (Eq. truncation_cutoff_int):  M + eps ln(eps D/(tau |J|)), >= C0
+//   PW   (Eq. cost_cutoff_delta):      M + eps ln(nu_max / delta)
+__global__ __launch_bounds__(256) void k_pre_scalars(const double *__restrict__ blk_stat,
+                                                     int64_t n_blocks, int rule, double eps,
+                                                     double C0, double nu_min, double nu_max,
+                                                     double tau, double absJ, double log_D,
+                                                     double delta, double *__restrict__ dscal) {
+    __shared__ double red[4][4];
+    double M = -INFINITY, m = INFINITY, pn = 0.0, nf = 0.0;
+    for (int64_t b = threadIdx.x; b < n_blocks; b += 256) {
+        M = fmax(M, blk_stat[b * 4 + 0]);
+        m = fmin(m, blk_stat[b * 4 + 1]);
+        pn += blk_stat[b * 4 + 2];
+        nf += blk_stat[b * 4 + 3];
+    }
+    M = wave_max(M);
+    m = wave_min(m);
+    pn = wave_sum(pn);
+    nf = wave_sum(nf);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = M;
+        red[w][1] = m;
+        red[w][2] = pn;
+        red[w][3] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < 4; ++i) {
+        M = fmax(red[0][0], red[i][0]);
+        red[0][0] = M;
+        red[0][1] = fmin(red[0][1], red[i][1]);
+        red[0][2] += red[i][2];
+        red[0][3] += red[i][3];
+    }
+    M = red[0][0];
+    m = red[0][1];
+    double C = INFINITY;
+    if (rule == RSOT_TRUNC_GEOM) {
+        C = C0 + (M - m) + eps * log(eps / (nu_min * tau * absJ));
+        C = fmax(C, C0);
+    } else if (rule == RSOT_TRUNC_INT) {
+        C = M + eps * (log(eps) + log_D - log(tau * absJ));
+        C = fmax(C, C0);
+    } else if (rule == RSOT_TRUNC_PW) {
+        C = M + eps * log(nu_max / delta);
+    }
+    dscal[SC_PSIMAX] = M;
+    dscal[SC_PSIMIN] = m;
+    dscal[SC_PSINU] = red[0][2];
+    dscal[SC_NONFINITE] = red[0][3];
+    dscal[SC_C] = C;
+}
+
+// ---------------------------------------------------------------------------
+// culling: (tile, block) flags, transposition, CSR lists
+// ---------------------------------------------------------------------------
+// Cutoff rules (Alg. 2 with I_q = {j : c < C}): a pair of boxes is skipped
+// when even its least distance reaches C, kept whole when its greatest
+// distance stays below C, and tested pair by pair otherwise.
+template <int D>
+__global__ __launch_bounds__(256) void k_flags_cutoff(
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi, int64_t n_tiles,
+    int64_t n_blocks, double cs, const double *__restrict__ dscal, uint8_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const double C = dscal[SC_C];
+    double tl[3], th[3];
+    for (int k = 0; k < 3; ++k) {
+        tl[k] = tile_lo[t * 3 + k];
+        th[k] = tile_hi[t * 3 + k];
+    }
+    for (int64_t b = lane; b < n_blocks; b += 64) {
+        double dmin2 = 0.0, dmax2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
+            const double f = box_far(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
+            dmin2 += g * g;
+            dmax2 += f * f;
+        }
+        uint8_t fl = PAIR_PARTIAL;
+        if (cs * dmin2 >= C) fl = PAIR_SKIP;
+        else if (cs * dmax2 < C) fl = PAIR_FULL;
+        flags[t * n_blocks + b] = fl;
+    }
+}
+
+// Tile-local rule (derived from App. B). For tile T and block B:
+//   ln U_TB = ln nu(B) + (max_{j in B} psi_j - cs dmin^2(T,B)) / eps   (upper bound)
+//   B* = argmax_B ln U_TB (lowest index on ties);
+//   ln L_T = max_{j in B*} ln nu_j + (psi_j - cs dmax^2(T, y_j)) / eps (lower bound of S)
+//   keep (T,B) iff B = B* or ln U_TB > ln L_T + ln(eta / n_blocks),
+//   eta = tau |J_ref| / (eps sum mu): then J_dense - J_trunc <= tau |J_ref|.
+template <int D>
+__global__ __launch_bounds__(256) void k_flags_tile(
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi,
+    const double *__restrict__ blk_lnnu, const double *__restrict__ blk_stat,
+    const int32_t *__restrict__ blk_cnt, const double *__restrict__ ty,
+    const double *__restrict__ tnu, const double *__restrict__ tpsi, int64_t n_tiles,
+    int64_t n_blocks, double cs, double eps, double ln_eta_nb, uint8_t *__restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    double tl[3], th[3];
+    for (int k = 0; k < 3; ++k) {
+        tl[k] = tile_lo[t * 3 + k];
+        th[k] = tile_hi[t * 3 + k];
+    }
+    const double inv_eps = 1.0 / eps;
+    double best = -INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int64_t b = lane; b < n_blocks; b += 64) {
+        double dmin2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
+            dmin2 += g * g;
+        }
+        const double lnU = blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
+        if (lnU > best) {
+            best = lnU;
+            bi = b;
+        }
+    }
+    // wavefront argmax, ties to the lowest block index
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int64_t oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    // reference target: best lower bound among the targets of B*
+    double lb = -INFINITY;
+    if (lane < blk_cnt[bi]) {
+        const int64_t j = bi * 64 + lane;
+        double dmax2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double f = box_far_pt(tl[k], th[k], ty[j * 3 + k]);
+            dmax2 += f * f;
+        }
+        lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) * inv_eps;
+    }
+    const double thr = wave_max(lb) + ln_eta_nb;
+    for (int64_t b = lane; b < n_blocks; b += 64) {
+        double dmin2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
+            dmin2 += g * g;
+        }
+        const double lnU = blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
+        flags[t * n_blocks + b] = (b == bi || lnU > thr) ? PAIR_FULL : PAIR_SKIP;
+    }
+}
+
+// out[c * R + r] = in[r * Cn + c], 64x64 byte tiles through LDS
+__global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t *__restrict__ in, int64_t R,
+                                                      int64_t Cn, uint8_t *__restrict__ out) {
+    __shared__ uint8_t s[64][65];
+    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+    for (int i = 0; i < 16; ++i) {
+        const int e = threadIdx.x + i * 256;
+        const int rr = e >> 6, cc = e & 63;
+        const int64_t r = r0 + rr, c = c0 + cc;
+        s[rr][cc] = (r < R && c < Cn) ? in[r * Cn + c] : 0;
+    }
+    __syncthreads();
+    for (int i = 0; i < 16; ++i) {
+        const int e = threadIdx.x + i * 256;
+        const int cc = e >> 6, rr = e & 63;
+        const int64_t r = r0 + rr, c = c0 + cc;
+        if (r < R && c < Cn) out[c * R + r] = s[rr][cc];
+    }
+}
+
+// one wavefront per row: number of non-skipped entries
+__global__ __launch_bounds__(256) void k_count_rows(const uint8_t *__restrict__ flags,
+                                                    int64_t nrows, int64_t ncols,
+                                                    int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    int c = 0;
+    for (int64_t k = lane; k < ncols; k += 64) c += flags[r * ncols + k] != PAIR_SKIP;
+    c = wave_sum_int(c);
+    if (lane == 0) cnt[r] = c;
+}
+
+// one wavefront per row: kept column indices in increasing order
+__global__ __launch_bounds__(256) void k_fill_rows(const uint8_t *__restrict__ flags,
+                                                   int64_t nrows, int64_t ncols,
+                                                   const int64_t *__restrict__ ptr,
+                                                   uint32_t *__restrict__ idx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    int64_t base = ptr[r];
+    for (int64_t k0 = 0; k0 < ncols; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const uint8_t f = k < ncols ? flags[r * ncols + k] : PAIR_SKIP;
+        const uint64_t mask = __ballot(f != PAIR_SKIP);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (f != PAIR_SKIP)
+            idx[base + below] = (uint32_t)k | (f == PAIR_PARTIAL ? RSOT_PARTIAL_BIT : 0u);
+        base += __popcll(mask);
+    }
+}
+
+// Single workgroup exclusive scan: ptr[0..n] from cnt[0..n-1]; ptr[n] = total.
+// With seg > 0 the scanned quantity is ceil(cnt / seg) (work items per block).
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n,
+                                               int seg, int64_t *__restrict__ ptr,
+                                               double *__restrict__ total_out) {
+    __shared__ int64_t sums[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a = std::min<int64_t>(n, tid * chunk), b = std::min<int64_t>(n, a + chunk);
+    int64_t loc = 0;
+    for (int64_t i = a; i < b; ++i) loc += seg > 0 ? (cnt[i] + seg - 1) / seg : cnt[i];
+    sums[tid] = loc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t v = tid >= off ? sums[tid - off] : 0;
+        __syncthreads();
+        sums[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = sums[tid] - loc;
+    for (int64_t i = a; i < b; ++i) {
+        ptr[i] = run;
+        run += seg > 0 ? (cnt[i] + seg - 1) / seg : cnt[i];
+    }
+    if (tid == 1023) {
+        ptr[n] = sums[1023];
+        *total_out = (double)sums[1023];
+    }
+}
+
+// work items of the gradient pass: block b owns ceil(len_b / seg) segments of
+// its column list
+__global__ void k_fill_work(const int64_t *__restrict__ col_ptr, const int64_t *__restrict__ wi_ptr,
+                            int64_t n_blocks, int seg, int32_t *__restrict__ wi_block,
+                            int64_t *__restrict__ wi_range) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_blocks) return;
+    const int64_t c0 = col_ptr[b], c1 = col_ptr[b + 1];
+    int64_t w = wi_ptr[b];
+    for (int64_t s = c0; s < c1; s += seg, ++w) {
+        wi_block[w] = (int32_t)b;
+        wi_range[2 * w] = s;
+        wi_range[2 * w + 1] = std::min<int64_t>(c1, s + seg);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// objective pass
+// ---------------------------------------------------------------------------
+// Accumulates one 64-target block into the running (m, s) of this lane's point:
+// s = sum 2^(t_j - m) with t_j = B_j + x.Y_j. m is an integer that only grows;
+// when a chunk's max exceeds it, s is rescaled by an exact power of two.
+template <int D, bool F64, bool MASK>
+__device__ __forceinline__ void lse_block(const double4 *__restrict__ T,
+                                          const double *__restrict__ G, double x0, double x1,
+                                          double x2, double A, double &m, double &s,
+                                          double &kept) {
+    for (int k0 = 0; k0 < 64; k0 += CH) {
+        double tv[CH];
+        double cm = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const double4 r = T[k0 + k];
+            double v = x0 * r.x;
+            v = fma(x1, r.y, v);
+            if (D == 3) v = fma(x2, r.z, v);
+            v += r.w;
+            if (MASK) {
+                const bool in = v > G[k0 + k] - A;
+                v = in ? v : -INFINITY;
+                kept += in ? 1.0 : 0.0;
+            }
+            tv[k] = v;
+            cm = fmax(cm, v);
+        }
+        if (cm > m) {
+            const double mn = ceil(cm);
+            s = ldexp(s, (int)fmax(m - mn, -2000.0));
+            m = mn;
+        }
+        if (F64) {
+            double cs = 0.0;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) cs += exp2(tv[k] - m);
+            s += cs;
+        } else {
+            float cs = 0.0f;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
+            s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+        }
+    }
+}
+
+template <int D, bool F64, int MODE>
+__global__ __launch_bounds__(256) void k_pass1(
+    double4 *__restrict__ qp, const double *__restrict__ qmu, const double *__restrict__ qlog2mu,
+    const int32_t *__restrict__ qperm, const double4 *__restrict__ trec,
+    const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
+    const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ row_idx, int64_t n_tiles,
+    int64_t n_blocks, double kcs, double *__restrict__ qH, double *__restrict__ qlse,
+    double *__restrict__ tile_part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const int64_t q = t * 64 + lane;
+    const double4 xr = qp[q];
+    const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
+    const double A = -kcs * (x0 * x0 + x1 * x1 + x2 * x2);
+    int64_t e0 = 0, e1 = n_blocks;
+    if (MODE != MODE_DENSE) {
+        e0 = row_ptr[t];
+        e1 = row_ptr[t + 1];
+    }
+    double m = -1e300, s = 0.0, kept = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
+        const int64_t b = ent & ~RSOT_PARTIAL_BIT;
+        const double4 *__restrict__ T = trec + b * 64;
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
+            lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
+        } else {
+            lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
+            kept += (double)blk_cnt[b];
+        }
+    }
+    const bool real = qperm[q] >= 0;
+    const bool empty = !(s > 0.0);
+    const double Lt = empty ? -INFINITY : m + log2(s);
+    const double lm = qlog2mu[q];
+    const double S = empty ? -INFINITY : lm - Lt;
+    reinterpret_cast<double *>(qp)[q * 4 + 3] = S;
+    if (MODE == MODE_MASK) qH[q] = S - A;
+    const double L2 = Lt + A;
+    qlse[q] = empty ? -INFINITY : L2 * RSOT_LN2;
+    const double jp = (real && !empty) ? qmu[q] * L2 : 0.0;
+    const double dl = (real && !empty && lm > -INFINITY) ? (lm - L2) * RSOT_LN2 : -INFINITY;
+    const double js = wave_sum(jp);
+    const double dm = wave_max(dl);
+    const double ds = wave_sum(dm > -INFINITY ? exp(dl - dm) : 0.0);
+    const double ks = wave_sum(real ? kept : 0.0);
+    const double es = wave_sum(real && empty ? 1.0 : 0.0);
+    if (lane == 0) {
+        tile_part[t * 4 + 0] = js;
+        tile_part[t * 4 + 1] = dm > -INFINITY ? dm + log(ds) : -INFINITY;
+        tile_part[t * 4 + 2] = ks;
+        tile_part[t * 4 + 3] = es;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gradient pass
+// ---------------------------------------------------------------------------
+template <int D, bool F64, bool MASK>
+__device__ __forceinline__ double mass_tile(const double4 *__restrict__ Q,
+                                            const double *__restrict__ H, double Y0, double Y1,
+                                            double Y2, double B, double G) {
+    double acc = 0.0;
+    for (int i0 = 0; i0 < 64; i0 += CH) {
+        if (F64) {
+            double cs = 0.0;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const double4 r = Q[i0 + k];
+                double v = B + r.w;
+                v = fma(r.x, Y0, v);
+                v = fma(r.y, Y1, v);
+                if (D == 3) v = fma(r.z, Y2, v);
+                if (MASK) v = v > G + H[i0 + k] ? v : -INFINITY;
+                cs += exp2(v);
+            }
+            acc += cs;
+        } else {
+            float cs = 0.0f;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const double4 r = Q[i0 + k];
+                double v = B + r.w;
+                v = fma(r.x, Y0, v);
+                v = fma(r.y, Y1, v);
+                if (D == 3) v = fma(r.z, Y2, v);
+                if (MASK) v = v > G + H[i0 + k] ? v : -INFINITY;
+                cs += __builtin_amdgcn_exp2f((float)v);
+            }
+            acc += (double)cs * RSOT_EXP2F_MEAN_CORR;
+        }
+    }
+    return acc;
+}
+
+template <int D, bool F64, int MODE>
+__global__ __launch_bounds__(256) void k_pass2(
+    const double4 *__restrict__ qp, const double *__restrict__ qH,
+    const double4 *__restrict__ trec, const double *__restrict__ tG,
+    const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
+    const uint32_t *__restrict__ col_idx, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
+    int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t b, w, e0, e1;
+    if (MODE == MODE_DENSE) {
+        // the four wavefronts of a workgroup share the point segment
+        const int64_t nbg = (n_blocks + 3) / 4;
+        const int64_t sgi = blockIdx.x / nbg;
+        b = (blockIdx.x % nbg) * 4 + wave;
+        if (b >= n_blocks) return;
+        e0 = sgi * seg;
+        e1 = std::min<int64_t>(e0 + seg, n_tiles);
+        w = b * n_seg + sgi;
+    } else {
+        w = (int64_t)blockIdx.x * 4 + wave;
+        if (w >= n_wi) return;
+        b = wi_block[w];
+        e0 = wi_range[2 * w];
+        e1 = wi_range[2 * w + 1];
+    }
+    const int64_t j = b * 64 + lane;
+    const double4 rec = trec[j];
+    const double G = MODE == MODE_MASK ? tG[j] : 0.0;
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
+        const int64_t t = ent & ~RSOT_PARTIAL_BIT;
+        const double4 *__restrict__ Q = qp + t * 64;
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
+            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G);
+        else
+            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G);
+    }
+    gpart[w * 64 + lane] = acc;
+}
+
+// per target: merge the work-item partials in order, un-permute, norms
+__global__ __launch_bounds__(256) void k_grad_reduce(
+    const double *__restrict__ gpart, const int64_t *__restrict__ wi_ptr, int64_t n_seg,
+    const double *__restrict__ tnu, const int32_t *__restrict__ tperm, int64_t n_blocks,
+    const double *__restrict__ dscal, double *__restrict__ grad_out,
+    double *__restrict__ blk_gpart) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= n_blocks) return;
+    const int64_t j = b * 64 + lane;
+    const int64_t w0 = wi_ptr ? wi_ptr[b] : b * n_seg;
+    const int64_t w1 = wi_ptr ? wi_ptr[b + 1] : w0 + n_seg;
+    double nut = 0.0;
+    for (int64_t w = w0; w < w1; ++w) nut += gpart[w * 64 + lane];
+    const double g = nut - tnu[j];
+    const int32_t dst = tperm[j];
+    const bool ok = dscal[SC_NONFINITE] == 0.0;
+    if (dst >= 0 && ok && grad_out) grad_out[dst] = g;
+    const double a = dst >= 0 ? fabs(g) : 0.0;
+    const double s1 = wave_sum(a);
+    const double mx = wave_max(a);
+    if (lane == 0) {
+        blk_gpart[b * 2 + 0] = s1;
+        blk_gpart[b * 2 + 1] = mx;
+    }
+}
+
+// single workgroup: evaluation statistics (kept pairs, empty points, ln D,
+// gradient norms), each summed in a fixed order
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ tile_part,
+                                                  int64_t n_tiles,
+                                                  const double *__restrict__ blk_gpart,
+                                                  int64_t n_blocks, int have_grad,
+                                                  double *__restrict__ dscal) {
+    __shared__ double red[4][6];
+    const int w = threadIdx.x >> 6;
+    const bool l0 = (threadIdx.x & 63) == 0;
+    double kp = 0.0, em = 0.0, dmx = -INFINITY;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += 256) {
+        dmx = fmax(dmx, tile_part[t * 4 + 1]);
+        kp += tile_part[t * 4 + 2];
+        em += tile_part[t * 4 + 3];
+    }
+    kp = wave_sum(kp);
+    em = wave_sum(em);
+    dmx = wave_max(dmx);
+    if (l0) {
+        red[w][0] = kp;
+        red[w][1] = em;
+        red[w][2] = dmx;
+    }
+    __syncthreads();
+    const double dall = fmax(fmax(red[0][2], red[1][2]), fmax(red[2][2], red[3][2]));
+    double dsum = 0.0;
+    if (dall > -INFINITY)
+        for (int64_t t = threadIdx.x; t < n_tiles; t += 256) {
+            const double v = tile_part[t * 4 + 1];
+            dsum += v > -INFINITY ? exp(v - dall) : 0.0;
+        }
+    double g1 = 0.0, gi = 0.0;
+    if (have_grad)
+        for (int64_t b = threadIdx.x; b < n_blocks; b += 256) {
+            g1 += blk_gpart[b * 2 + 0];
+            gi = fmax(gi, blk_gpart[b * 2 + 1]);
+        }
+    dsum = wave_sum(dsum);
+    g1 = wave_sum(g1);
+    gi = wave_max(gi);
+    if (l0) {
+        red[w][3] = dsum;
+        red[w][4] = g1;
+        red[w][5] = gi;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double ks = 0.0, es = 0.0, ds = 0.0, gs = 0.0, gm = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        ks += red[i][0];
+        es += red[i][1];
+        ds += red[i][3];
+        gs += red[i][4];
+        gm = fmax(gm, red[i][5]);
+    }
+    dscal[SC_KEPT] = ks;
+    dscal[SC_EMPTY] = es;
+    dscal[SC_LOGD] = dall > -INFINITY ? dall + log(ds) : -INFINITY;
+    dscal[SC_GL1] = gs;
+    dscal[SC_GLINF] = gm;
+}
+
+// J = eps ln2 sum_q mu_q L2_q - sum_j psi_j nu_j (Alg. 2, last two lines);
+// kept in its own single-workgroup kernel so the sum order is fixed.
+__global__ __launch_bounds__(256) void k_objective(const double *__restrict__ tile_part,
+                                                   int64_t n_tiles, double eps,
+                                                   double *__restrict__ dscal) {
+    __shared__ double red[4];
+    double js = 0.0;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += 256) js += tile_part[t * 4 + 0];
+    js = wave_sum(js);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = js;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double s = (red[0] + red[1]) + (red[2] + red[3]);
+    dscal[SC_SUM_L2] = s;
+    dscal[SC_J] = eps * RSOT_LN2 * s - dscal[SC_PSINU];
+}
+
+// ---------------------------------------------------------------------------
+// driver
+// ---------------------------------------------------------------------------
+template <typename T>
+static rsot_status grow(rsot_problem *p, T **ptr, size_t *cap, size_t count) {
+    if (*ptr && *cap >= count) return RSOT_OK;
+    if (*ptr) rsot_dev_free(p, *ptr);
+    *ptr = nullptr;
+    void *q = nullptr;
+    size_t c = std::max<size_t>(count + count / 4, 64);
+    RSOT_TRY(rsot_dev_alloc(p, &q, c * sizeof(T)));
+    *ptr = (T *)q;
+    *cap = c;
+    return RSOT_OK;
+}
+
+template <int D, bool F64, int MODE>
+static void launch_pass1(rsot_problem *p, double kcs) {
+    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256),
+                       0, p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->trec, p->tG,
+                       p->blk_cnt, p->row_ptr, p->row_idx, p->n_tiles, p->n_blocks, kcs, p->qH,
+                       p->qlse, p->tile_part);
+}
+
+template <int D, bool F64, int MODE>
+static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t seg) {
+    unsigned grid;
+    if (MODE == MODE_DENSE)
+        grid = (unsigned)(((p->n_blocks + 3) / 4) * n_seg);
+    else
+        grid = (unsigned)((n_wi + 3) / 4);
+    hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
+                       p->trec, p->tG, p->wi_block, p->wi_range, p->col_idx, p->n_tiles,
+                       p->n_blocks, n_wi, n_seg, seg, p->gpart);
+}
+
+template <int D, bool F64>
+static void launch_passes(rsot_problem *p, int mode, bool grad, double kcs, int64_t n_wi,
+                          int64_t n_seg, int64_t seg) {
+    if (mode == MODE_DENSE) launch_pass1<D, F64, MODE_DENSE>(p, kcs);
+    else if (mode == MODE_LIST) launch_pass1<D, F64, MODE_LIST>(p, kcs);
+    else launch_pass1<D, F64, MODE_MASK>(p, kcs);
+    (void)hipEventRecord(p->ev_mid, p->stream);
+    if (!grad) return;
+    if (mode == MODE_DENSE) launch_pass2<D, F64, MODE_DENSE>(p, n_wi, n_seg, seg);
+    else if (mode == MODE_LIST) launch_pass2<D, F64, MODE_LIST>(p, n_wi, n_seg, seg);
+    else launch_pass2<D, F64, MODE_MASK>(p, n_wi, n_seg, seg);
+}
+
+static rsot_status ensure_cull_buffers(rsot_problem *p) {
+    if (p->flags_rm) return RSOT_OK;
+    const size_t nf = (size_t)p->n_tiles * (size_t)p->n_blocks;
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->flags_rm, nf));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->flags_cm, nf));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_cnt, sizeof(int32_t) * p->n_tiles));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_cnt, sizeof(int32_t) * p->n_blocks));
+    return RSOT_OK;
+}
+
+rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi, double *J_out,
+                           double *grad_out, rsot_eval_info *info) {
+    const int D = p->dim;
+    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
+    const bool grad = grad_out != nullptr;
+    const double cs = p->opt.cost_scale;
+    const double kappa = RSOT_LOG2E / eps;
+    int rule = p->opt.truncation;
+    int dense_fallback = 0;
+    if ((rule == RSOT_TRUNC_GEOM || rule == RSOT_TRUNC_TILE || rule == RSOT_TRUNC_INT) &&
+        !(p->absJ_ref > 0.0)) {
+        rule = RSOT_TRUNC_DENSE;
+        dense_fallback = 1;
+    }
+    if (rule == RSOT_TRUNC_INT && !p->have_D) {
+        rule = RSOT_TRUNC_DENSE;
+        dense_fallback = 1;
+    }
+    if (rule == RSOT_TRUNC_GEOM || rule == RSOT_TRUNC_INT) RSOT_TRY(rsot_compute_covering_cost(p));
+
+    RSOT_HIP(hipEventRecord(p->ev0, p->stream));
+    const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
+    const dim3 gtile((unsigned)((p->n_tiles + 3) / 4));
+    if (D == 2)
+        hipLaunchKernelGGL(k_prep_targets<2>, gblk, dim3(256), 0, p->stream, psi, p->tperm, p->ty,
+                           p->tnu, p->tlog2nu, p->n_blocks, kappa, cs, p->trec, p->tpsi,
+                           p->blk_stat);
+    else
+        hipLaunchKernelGGL(k_prep_targets<3>, gblk, dim3(256), 0, p->stream, psi, p->tperm, p->ty,
+                           p->tnu, p->tlog2nu, p->n_blocks, kappa, cs, p->trec, p->tpsi,
+                           p->blk_stat);
+    hipLaunchKernelGGL(k_pre_scalars, dim3(1), dim3(256), 0, p->stream, p->blk_stat, p->n_blocks,
+                       rule, eps, p->C0 < 0 ? 0.0 : p->C0, p->nu_min, p->nu_max, p->opt.tau,
+                       p->absJ_ref, p->log_D_prev, p->opt.delta_thr, p->dscal);
+
+    int mode = MODE_DENSE;
+    int64_t n_wi = 0, n_seg = 1, seg = 1;
+    const int64_t seg_cfg = p->opt.seg_tiles;
+    if (rule == RSOT_TRUNC_DENSE) {
+        n_seg = std::max<int64_t>(1, (32768 + p->n_blocks - 1) / p->n_blocks);
+        if (seg_cfg > 0) n_seg = (p->n_tiles + seg_cfg - 1) / seg_cfg;
+        n_seg = std::min<int64_t>(n_seg, p->n_tiles);
+        seg = (p->n_tiles + n_seg - 1) / n_seg;
+        n_seg = (p->n_tiles + seg - 1) / seg;
+        n_wi = p->n_blocks * n_seg;
+    } else {
+        RSOT_TRY(ensure_cull_buffers(p));
+        mode = rule == RSOT_TRUNC_TILE ? MODE_LIST : MODE_MASK;
+        if (rule == RSOT_TRUNC_TILE) {
+            const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
+                                     std::log((double)p->n_blocks);
+            if (D == 2)
+                hipLaunchKernelGGL(k_flags_tile<2>, gtile, dim3(256), 0, p->stream, p->tile_lo,
+                                   p->tile_hi, p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat,
+                                   p->blk_cnt, p->ty, p->tnu, p->tpsi, p->n_tiles, p->n_blocks,
+                                   cs, eps, ln_eta_nb, p->flags_rm);
+            else
+                hipLaunchKernelGGL(k_flags_tile<3>, gtile, dim3(256), 0, p->stream, p->tile_lo,
+                                   p->tile_hi, p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat,
+                                   p->blk_cnt, p->ty, p->tnu, p->tpsi, p->n_tiles, p->n_blocks,
+                                   cs, eps, ln_eta_nb, p->flags_rm);
+        } else {
+            hipLaunchKernelGGL(k_target_G, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0,
+                               p->stream, p->tpsi, p->tlog2nu, p->tperm, p->n_pad, kappa, p->dscal,
+                               p->tG);
+            if (D == 2)
+                hipLaunchKernelGGL(k_flags_cutoff<2>, gtile, dim3(256), 0, p->stream, p->tile_lo,
+                                   p->tile_hi, p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs,
+                                   p->dscal, p->flags_rm);
+            else
+                hipLaunchKernelGGL(k_flags_cutoff<3>, gtile, dim3(256), 0, p->stream, p->tile_lo,
+                                   p->tile_hi, p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs,
+                                   p->dscal, p->flags_rm);
+        }
+        hipLaunchKernelGGL(k_transpose_u8,
+                           dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
+                           dim3(256), 0, p->stream, p->flags_rm, p->n_tiles, p->n_blocks,
+                           p->flags_cm);
+        hipLaunchKernelGGL(k_count_rows, gtile, dim3(256), 0, p->stream, p->flags_rm, p->n_tiles,
+                           p->n_blocks, p->row_cnt);
+        hipLaunchKernelGGL(k_count_rows, gblk, dim3(256), 0, p->stream, p->flags_cm, p->n_blocks,
+                           p->n_tiles, p->col_cnt);
+        seg = seg_cfg > 0 ? seg_cfg : 64;
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->row_cnt, p->n_tiles, 0,
+                           p->row_ptr, p->dscal + SC_ROWTOT);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->col_cnt, p->n_blocks, 0,
+                           p->col_ptr, p->dscal + SC_COLTOT);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->col_cnt, p->n_blocks,
+                           (int)seg, p->wi_ptr, p->dscal + SC_NWI);
+        RSOT_HIP(hipGetLastError());
+        RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT,
+                                hipMemcpyDeviceToHost, p->stream));
+        RSOT_HIP(hipStreamSynchronize(p->stream));
+        if (p->hscal[SC_NONFINITE] != 0.0) return RSOT_ERR_NONFINITE;
+        const int64_t rtot = (int64_t)p->hscal[SC_ROWTOT];
+        const int64_t ctot = (int64_t)p->hscal[SC_COLTOT];
+        n_wi = (int64_t)p->hscal[SC_NWI];
+        size_t cap_r = p->list_cap, cap_c = p->list_cap;
+        RSOT_TRY(grow(p, &p->row_idx, &cap_r, (size_t)std::max<int64_t>(rtot, 1)));
+        RSOT_TRY(grow(p, &p->col_idx, &cap_c, (size_t)std::max<int64_t>(ctot, 1)));
+        p->list_cap = std::min(cap_r, cap_c);
+        size_t cap_b = p->wi_cap, cap_rg = p->wi_cap;
+        RSOT_TRY(grow(p, &p->wi_block, &cap_b, (size_t)std::max<int64_t>(n_wi, 1)));
+        RSOT_TRY(grow(p, &p->wi_range, &cap_rg, (size_t)std::max<int64_t>(2 * n_wi, 2)));
+        p->wi_cap = std::min(cap_b, cap_rg / 2);
+        hipLaunchKernelGGL(k_fill_rows, gtile, dim3(256), 0, p->stream, p->flags_rm, p->n_tiles,
+                           p->n_blocks, p->row_ptr, p->row_idx);
+        hipLaunchKernelGGL(k_fill_rows, gblk, dim3(256), 0, p->stream, p->flags_cm, p->n_blocks,
+                           p->n_tiles, p->col_ptr, p->col_idx);
+        hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((p->n_blocks + 255) / 256)), dim3(256), 0,
+                           p->stream, p->col_ptr, p->wi_ptr, p->n_blocks, (int)seg, p->wi_block,
+                           p->wi_range);
+    }
+    if (grad) RSOT_TRY(grow(p, &p->gpart, &p->gpart_cap, (size_t)std::max<int64_t>(n_wi, 1) * 64));
+
+    const double kcs = kappa * cs;
+    RSOT_HIP(hipEventRecord(p->ev_p1, p->stream));
+    if (D == 2) {
+        if (f64) launch_passes<2, true>(p, mode, grad, kcs, n_wi, n_seg, seg);
+        else launch_passes<2, false>(p, mode, grad, kcs, n_wi, n_seg, seg);
+    } else {
+        if (f64) launch_passes<3, true>(p, mode, grad, kcs, n_wi, n_seg, seg);
+        else launch_passes<3, false>(p, mode, grad, kcs, n_wi, n_seg, seg);
+    }
+    RSOT_HIP(hipEventRecord(p->ev_p2, p->stream));
+    if (grad)
+        hipLaunchKernelGGL(k_grad_reduce, gblk, dim3(256), 0, p->stream, p->gpart,
+                           mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi_ptr, n_seg, p->tnu,
+                           p->tperm, p->n_blocks, p->dscal, grad_out, p->blk_gpart);
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, p->stream, p->tile_part, p->n_tiles,
+                       eps, p->dscal);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p->stream, p->tile_part, p->n_tiles,
+                       p->blk_gpart, p->n_blocks, grad ? 1 : 0, p->dscal);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipEventRecord(p->ev1, p->stream));
+    RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                            p->stream));
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    const double *h = p->hscal;
+    if (h[SC_NONFINITE] != 0.0) return RSOT_ERR_NONFINITE;
+    float ms = 0.0f, ms_pre = 0.0f, ms_passes = 0.0f;
+    RSOT_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    RSOT_HIP(hipEventElapsedTime(&ms_pre, p->ev0, p->ev_p1));
+    RSOT_HIP(hipEventElapsedTime(&ms_passes, p->ev_p1, p->ev_p2));
+    float ms_p1 = 0.0f, ms_p2 = 0.0f;
+    RSOT_HIP(hipEventElapsedTime(&ms_p1, p->ev_p1, p->ev_mid));
+    RSOT_HIP(hipEventElapsedTime(&ms_p2, p->ev_mid, p->ev_p2));
+    *J_out = h[SC_J];
+    if (rule == RSOT_TRUNC_INT || p->opt.truncation == RSOT_TRUNC_INT) {
+        p->log_D_prev = h[SC_LOGD];
+        p->have_D = 1;
+    }
+    if (dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
+    p->last_eval_valid = 1;
+    if (info) {
+        info->total_pairs = p->nq * p->n;
+        info->kept_pairs = (int64_t)h[SC_KEPT];
+        info->n_empty_qp = (int64_t)h[SC_EMPTY];
+        info->cutoff = (rule == RSOT_TRUNC_GEOM || rule == RSOT_TRUNC_INT || rule == RSOT_TRUNC_PW)
+                           ? h[SC_C]
+                           : 0.0;
+        info->absJ_ref = p->absJ_ref;
+        info->log_D = h[SC_LOGD];
+        info->grad_l1 = grad ? h[SC_GL1] : 0.0;
+        info->grad_linf = grad ? h[SC_GLINF] : 0.0;
+        info->kernel_ms = ms;
+        info->setup_ms = ms_pre;
+        info->passes_ms = ms_passes;
+        info->pass1_ms = ms_p1;
+        info->pass2_ms = grad ? ms_p2 : 0.0;
+        info->dense_fallback = dense_fallback;
+    }
+    return RSOT_OK;
+}
+
+extern "C" rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi,
+                                      double *J_out, double *grad_out, rsot_eval_info *info) {
+    if (!p || !psi || !J_out) return RSOT_ERR_INVALID_ARG;
+    if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
+    return rsot_eval_impl(p, eps, psi, J_out, grad_out, info);
+}
+
+__global__ void k_unpermute_lse(const double *__restrict__ qlse, const int32_t *__restrict__ qperm,
+                                int64_t nq_pad, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq_pad) return;
+    const int32_t d = qperm[i];
+    if (d >= 0) out[d] = qlse[i];
+}
+
+extern "C" rsot_status rsot_get_lse(rsot_problem *p, double *L_out) {
+    if (!p || !L_out || !p->last_eval_valid) return RSOT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_unpermute_lse, dim3((unsigned)((p->nq_pad + 255) / 256)), dim3(256), 0,
+                       p->stream, p->qlse, p->qperm, p->nq_pad, L_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    return RSOT_OK;
+}

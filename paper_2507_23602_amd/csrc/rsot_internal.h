@@ -1,0 +1,154 @@
+// Internal declarations of librsot (not part of the ABI).
+//
+// Data layout in device memory (all library-owned):
+//   points  : spatially sorted (Morton order of a grid over their bounding
+//             box), padded to a multiple of 64 so that one 64-point tile is one
+//             wavefront. qp[q] = {x0, x1, x2, S_q} (x2 = 0 in 2D; S_q is the
+//             per-point constant of the gradient pass, rewritten by every
+//             objective pass). Padding points copy the last real point and
+//             carry mu = 0.
+//   targets : sorted the same way, padded to a multiple of 64 (one 64-target
+//             block per wavefront in the gradient pass); padding targets
+//             carry nu = 0 (log2 nu = -inf), so they add nothing.
+//   Coordinates are shifted by the centre of the target bounding box (the
+//   cost only depends on x - y).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/rsot.h"
+
+#define RSOT_WAVE 64
+#define RSOT_TILE 64
+#define RSOT_BLOCK 64
+
+// flag values of a (tile, block) pair after culling
+enum : uint8_t { PAIR_SKIP = 0, PAIR_PARTIAL = 1, PAIR_FULL = 2 };
+// list entries: index, with the top bit set when the pair needs the per-pair
+// cutoff test
+#define RSOT_PARTIAL_BIT 0x80000000u
+
+struct rsot_problem {
+    int dim = 0;
+    int64_t nq = 0, n = 0;
+    int64_t nq_pad = 0, n_pad = 0;
+    int64_t n_tiles = 0, n_blocks = 0;
+    rsot_options opt{};
+    hipStream_t stream = nullptr;
+    double shift[3] = {0, 0, 0};
+    double sum_mu = 0, sum_nu = 0, nu_min = 0, nu_max = 0;
+
+    // allocations (for cleanup and the memory cap)
+    std::vector<void *> allocs;
+    std::vector<size_t> alloc_bytes;
+    size_t bytes = 0;
+
+    // points
+    double4 *qp = nullptr;       // [nq_pad] {x0,x1,x2,S}
+    double *qmu = nullptr;       // [nq_pad]
+    double *qlog2mu = nullptr;   // [nq_pad]
+    double *qH = nullptr;        // [nq_pad] S_q - A_q (per-pair cutoff test)
+    double *qlse = nullptr;      // [nq_pad] L_q (natural log)
+    int32_t *qperm = nullptr;    // [nq_pad] sorted slot -> caller index (-1 pad)
+    double *tile_lo = nullptr;   // [n_tiles*3]
+    double *tile_hi = nullptr;   // [n_tiles*3]
+    int32_t *tile_cnt = nullptr; // [n_tiles] real points per tile
+
+    // targets
+    double *ty = nullptr;        // [n_pad*3] shifted coordinates (AoS, 3 per target)
+    double *tnu = nullptr;       // [n_pad]
+    double *tlog2nu = nullptr;   // [n_pad]
+    int32_t *tperm = nullptr;    // [n_pad]
+    double4 *trec = nullptr;     // [n_pad] per evaluation {Y0,Y1,Y2,B}
+    double *tG = nullptr;        // [n_pad] per evaluation cutoff constant
+    double *tpsi = nullptr;      // [n_pad] sorted psi (per evaluation)
+    double *blk_lo = nullptr;    // [n_blocks*3]
+    double *blk_hi = nullptr;
+    double *blk_nu = nullptr;    // [n_blocks] block mass
+    double *blk_lnnu = nullptr;  // [n_blocks] ln of the block mass
+    int32_t *blk_cnt = nullptr;  // [n_blocks] real targets per block
+    double *blk_stat = nullptr;  // [n_blocks*4] per evaluation: psimax, psimin, psi.nu, nonfinite
+
+    // per-evaluation partials and scalars
+    double *tile_part = nullptr; // [n_tiles*4] sum mu L2, logD part, kept, empty
+    double *blk_gpart = nullptr; // [n_blocks*2] |g|_1, |g|_inf per block
+    double *dscal = nullptr;     // [32] device scalars
+    double *hscal = nullptr;     // [32] pinned host copy
+    double *hpsi = nullptr;      // pinned host staging (n)
+    double *hgrad = nullptr;     // pinned host staging (n)
+    double *dpsi = nullptr;      // device staging for solve (n)
+    double *dgrad = nullptr;     // device staging for solve (n)
+
+    // gradient pass work items and partials
+    double *gpart = nullptr;     // [n_wi*64]
+    size_t gpart_cap = 0;
+    int32_t *wi_block = nullptr; // list mode: block of each work item
+    int64_t *wi_range = nullptr; // list mode: [start,end) into the column list
+    int64_t *wi_ptr = nullptr;   // [n_blocks+1] first work item of each block
+    size_t wi_cap = 0;
+
+    // culling (truncated rules)
+    uint8_t *flags_rm = nullptr; // [n_tiles*n_blocks]
+    uint8_t *flags_cm = nullptr; // [n_blocks*n_tiles]
+    int64_t *row_ptr = nullptr;  // [n_tiles+1]
+    int64_t *col_ptr = nullptr;  // [n_blocks+1]
+    int32_t *row_cnt = nullptr;  // [n_tiles]
+    int32_t *col_cnt = nullptr;  // [n_blocks]
+    uint32_t *row_idx = nullptr; // kept entries per tile
+    uint32_t *col_idx = nullptr; // kept entries per block
+    size_t list_cap = 0;
+    int64_t *i64tmp = nullptr;   // small scratch for counts
+
+    // state
+    double C0 = -1.0;            // covering cost (lazy)
+    double absJ_ref = 0.0;       // |J| for the cutoff rules (0 = unknown)
+    double log_D_prev = 0.0;     // ln D of the previous evaluation (INT rule)
+    int have_D = 0;
+    int last_eval_valid = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
+};
+
+// ---- helpers --------------------------------------------------------------
+rsot_status rsot_dev_alloc(rsot_problem *p, void **ptr, size_t bytes);
+void rsot_dev_free(rsot_problem *p, void *ptr);
+
+#define RSOT_HIP(call)                                                    \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return RSOT_ERR_DEVICE;                     \
+    } while (0)
+
+#define RSOT_TRY(call)                                                    \
+    do {                                                                  \
+        rsot_status s_ = (call);                                          \
+        if (s_ != RSOT_OK) return s_;                                     \
+    } while (0)
+
+// kernels launched from the evaluation driver
+rsot_status rsot_compute_covering_cost(rsot_problem *p);
+rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi_dev, double *J_out,
+                           double *grad_dev, rsot_eval_info *info);
+
+// device scalar slots
+enum {
+    SC_J = 0,        // J
+    SC_SUM_L2,       // sum_q mu_q L2_q
+    SC_LOGD,         // ln D
+    SC_KEPT,         // kept pairs
+    SC_EMPTY,        // empty points
+    SC_PSIMAX,
+    SC_PSIMIN,
+    SC_PSINU,        // sum psi nu
+    SC_NONFINITE,    // count of non-finite psi
+    SC_GL1,
+    SC_GLINF,
+    SC_C,            // cutoff used
+    SC_C0,
+    SC_ROWTOT,       // total row entries (culling)
+    SC_COLTOT,
+    SC_NWI,          // work items of the gradient pass
+    SC_COUNT
+};

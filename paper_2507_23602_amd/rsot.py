@@ -1,0 +1,315 @@
+"""Python binding of librsot (ctypes). Argument marshalling only: every step
+of the evaluation and the solve runs inside the library; torch supplies
+device buffers and the stream.
+
+The library must be built (``python -m paper_2507_23602_amd.build``);
+importing this module raises if it is missing, so no code path silently
+falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsot.so")
+
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_NONFINITE = 2
+ERR_UNBALANCED = 3
+ERR_DEVICE = 4
+ERR_OOM = 5
+ERR_LINESEARCH = 6
+ERR_NOT_CONVERGED = 7
+ERR_CANCELLED = 8
+
+PREC_MIXED = 0
+PREC_FP64 = 1
+
+TRUNC_DENSE = 0
+TRUNC_GEOM = 1
+TRUNC_INT = 2
+TRUNC_PW = 3
+TRUNC_TILE = 4
+
+_TRUNC_NAMES = {"dense": TRUNC_DENSE, "geom": TRUNC_GEOM, "int": TRUNC_INT, "pw": TRUNC_PW,
+                "tile": TRUNC_TILE}
+_PREC_NAMES = {"mixed": PREC_MIXED, "fp64": PREC_FP64}
+
+
+class RsotError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("cost_scale", ctypes.c_double), ("precision", ctypes.c_int),
+                ("truncation", ctypes.c_int), ("tau", ctypes.c_double),
+                ("delta_thr", ctypes.c_double), ("inputs_on_device", ctypes.c_int),
+                ("seg_tiles", ctypes.c_int), ("chunk_log2", ctypes.c_int),
+                ("mem_limit_bytes", ctypes.c_int64)]
+
+
+class EvalInfo(ctypes.Structure):
+    _fields_ = [("total_pairs", ctypes.c_int64), ("kept_pairs", ctypes.c_int64),
+                ("n_empty_qp", ctypes.c_int64), ("cutoff", ctypes.c_double),
+                ("absJ_ref", ctypes.c_double), ("log_D", ctypes.c_double),
+                ("grad_l1", ctypes.c_double), ("grad_linf", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
+                ("passes_ms", ctypes.c_double), ("pass1_ms", ctypes.c_double),
+                ("pass2_ms", ctypes.c_double), ("dense_fallback", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class IterInfo(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int), ("iteration", ctypes.c_int),
+                ("evaluations", ctypes.c_int), ("eps", ctypes.c_double),
+                ("J", ctypes.c_double), ("grad_l1", ctypes.c_double),
+                ("grad_linf", ctypes.c_double), ("step", ctypes.c_double),
+                ("kept_pairs", ctypes.c_int64), ("cutoff", ctypes.c_double)]
+
+
+CALLBACK = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(IterInfo), ctypes.c_void_p)
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("eps_schedule", ctypes.POINTER(ctypes.c_double)), ("n_eps", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("lbfgs_m", ctypes.c_int), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("max_ls", ctypes.c_int), ("stage_tol", ctypes.c_double),
+                ("callback", CALLBACK), ("user", ctypes.c_void_p),
+                ("cancel", ctypes.POINTER(ctypes.c_int))]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int),
+                ("stages", ctypes.c_int), ("J", ctypes.c_double), ("grad_l1", ctypes.c_double),
+                ("grad_linf", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("eval_ms", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+# name -> (restype, argtypes); every symbol declared in include/rsot.h
+SIGNATURES = {
+    "rsot_options_default": (None, [ctypes.POINTER(Options)]),
+    "rsot_status_string": (ctypes.c_char_p, [_I]),
+    "rsot_problem_create": (_I, [_I, _I64, _P, _P, _I64, _P, _P, ctypes.POINTER(Options), _P,
+                                 ctypes.POINTER(_P)]),
+    "rsot_problem_destroy": (None, [_P]),
+    "rsot_problem_sizes": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I64),
+                                ctypes.POINTER(_I64)]),
+    "rsot_set_truncation": (_I, [_P, _I, _D, _D]),
+    "rsot_set_precision": (_I, [_P, _I]),
+    "rsot_set_reference": (_I, [_P, _D]),
+    "rsot_dual_eval": (_I, [_P, _D, _P, ctypes.POINTER(_D), _P, ctypes.POINTER(EvalInfo)]),
+    "rsot_get_lse": (_I, [_P, _P]),
+    "rsot_covering_cost": (_I, [_P, ctypes.POINTER(_D)]),
+    "rsot_get_partition": (_I, [_P, _P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "rsot_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
+    "rsot_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, ctypes.POINTER(SolveInfo)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads librsot.so and binds every ABI symbol. Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librsot.so not built at {path}: run python -m paper_2507_23602_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return load_library().rsot_status_string(code).decode()
+    except Exception:
+        return str(code)
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise RsotError(code, what)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load_library().rsot_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "truncation" and isinstance(v, str):
+            v = _TRUNC_NAMES[v]
+        if k == "precision" and isinstance(v, str):
+            v = _PREC_NAMES[v]
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f64(t, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t, dtype=np.float64), device="cuda")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+@dataclass
+class EvalResult:
+    J: float
+    grad: object          # torch.Tensor (cuda, float64) or None
+    info: dict
+
+
+class Problem:
+    """Owns an rsot_problem handle. Inputs are host numpy arrays or CUDA
+    tensors (float64); the library copies them."""
+
+    def __init__(self, x, mu, y, nu, *, cost_scale=0.5, precision="mixed", truncation="dense",
+                 tau=1e-12, delta_thr=1e-12, seg_tiles=0, mem_limit_bytes=0, stream=None):
+        torch = _torch()
+        lib = load_library()
+        on_dev = isinstance(x, torch.Tensor) and x.is_cuda
+        if on_dev:
+            xs, mus, ys, nus = (t.to(torch.float64).contiguous() for t in (x, mu, y, nu))
+            ptrs = [t.data_ptr() for t in (xs, mus, ys, nus)]
+            self._keep = (xs, mus, ys, nus)
+        else:
+            xs, mus, ys, nus = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, mu, y, nu))
+            ptrs = [a.ctypes.data for a in (xs, mus, ys, nus)]
+            self._keep = (xs, mus, ys, nus)
+        dim = xs.shape[1]
+        nq, n = xs.shape[0], ys.shape[0]
+        opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
+                              tau=tau, delta_thr=delta_thr, inputs_on_device=int(on_dev),
+                              seg_tiles=seg_tiles, mem_limit_bytes=mem_limit_bytes)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = _P()
+        _check(lib.rsot_problem_create(dim, nq, ptrs[0], ptrs[1], n, ptrs[2], ptrs[3],
+                                       ctypes.byref(opt), _P(stream.cuda_stream), ctypes.byref(h)),
+               "rsot_problem_create")
+        self._h = h
+        self._keep = None
+        self.dim, self.nq, self.n = dim, nq, n
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().rsot_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_truncation(self, truncation, tau=1e-12, delta_thr=1e-12):
+        if isinstance(truncation, str):
+            truncation = _TRUNC_NAMES[truncation]
+        _check(load_library().rsot_set_truncation(self._h, truncation, tau, delta_thr),
+               "rsot_set_truncation")
+
+    def set_precision(self, precision):
+        if isinstance(precision, str):
+            precision = _PREC_NAMES[precision]
+        _check(load_library().rsot_set_precision(self._h, precision), "rsot_set_precision")
+
+    def set_reference(self, absJ):
+        _check(load_library().rsot_set_reference(self._h, float(absJ)), "rsot_set_reference")
+
+    def dual_eval(self, psi, eps, want_grad=True, out=None) -> EvalResult:
+        """J(psi) and grad J(psi); psi (N,) float64 CUDA tensor or array."""
+        torch = _torch()
+        psi_t = _dev_f64(psi, self.n)
+        grad = None
+        if want_grad:
+            grad = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        J = _D(0.0)
+        info = EvalInfo()
+        _check(load_library().rsot_dual_eval(self._h, float(eps), psi_t.data_ptr(), ctypes.byref(J),
+                                             grad.data_ptr() if grad is not None else None,
+                                             ctypes.byref(info)), "rsot_dual_eval")
+        return EvalResult(J.value, grad, info.as_dict())
+
+    def lse(self):
+        torch = _torch()
+        out = torch.empty(self.nq, dtype=torch.float64, device="cuda")
+        _check(load_library().rsot_get_lse(self._h, out.data_ptr()), "rsot_get_lse")
+        return out
+
+    def covering_cost(self) -> float:
+        c = _D(0.0)
+        _check(load_library().rsot_covering_cost(self._h, ctypes.byref(c)), "rsot_covering_cost")
+        return c.value
+
+    def partition(self):
+        torch = _torch()
+        t = torch.empty(self.nq, dtype=torch.int32, device="cuda")
+        b = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        nt, nb = _I64(0), _I64(0)
+        _check(load_library().rsot_get_partition(self._h, t.data_ptr(), b.data_ptr(),
+                                                 ctypes.byref(nt), ctypes.byref(nb)),
+               "rsot_get_partition")
+        return t, b, nt.value, nb.value
+
+    def solve(self, eps_schedule, psi0=None, tol=1e-6, max_iter=10000, lbfgs_m=10,
+              stage_tol=0.0, callback=None, max_ls=20):
+        """rsot_solve: returns (psi numpy array, info dict). Raises on error
+        codes other than NOT_CONVERGED (reported in info['status'])."""
+        lib = load_library()
+        eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
+        psi = np.zeros(self.n) if psi0 is None else np.array(psi0, dtype=np.float64)
+        sp = SolveParams()
+        lib.rsot_solve_params_default(ctypes.byref(sp))
+        sp.eps_schedule = eps_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        sp.n_eps = eps_arr.shape[0]
+        sp.tol = tol
+        sp.max_iter = max_iter
+        sp.lbfgs_m = lbfgs_m
+        sp.stage_tol = stage_tol
+        sp.max_ls = max_ls
+        cb = None
+        if callback is not None:
+            def _cb(ptr, _user):
+                return int(bool(callback(ptr.contents)))
+            cb = CALLBACK(_cb)
+            sp.callback = cb
+        info = SolveInfo()
+        rc = lib.rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data, ctypes.byref(info))
+        if rc not in (OK, ERR_NOT_CONVERGED):
+            raise RsotError(rc, "rsot_solve")
+        return psi, info.as_dict()

@@ -1,0 +1,276 @@
+"""GPU parity of rsot_dual_eval against the CPU oracle (through the C ABI).
+
+Tolerances (from the precision targets): gradient
+    e_g = max_j |g_j - g_ref_j| / (nu_j + nu~_ref_j) <= 1e-6 (mixed), 1e-12 (fp64)
+objective |J - J_ref| / |J_ref| <= 1e-9 (both), for problems with many
+points. The mixed path's per-point sums carry the FP32 exponential's
+zero-mean error (<= 8.4e-8 relative per term, measured), which averages out
+over points; with a single point it does not, and the bound used there is the
+arithmetic one, |J - J_ref| <= eps * sum(mu) * 1e-7. Per-point L_q:
+absolute error <= 1e-6 (mixed), 1e-10 (fp64) relative to max(1, |L_q|).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_23602_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"mixed": (1e-6, 1e-9, 1e-6), "fp64": (1e-12, 1e-12, 1e-10)}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def grad_err(g, gref, nu):
+    return float(np.max(np.abs(g - gref) / (nu + (gref + nu))))
+
+
+def _problem(x, mu, y, nu, **kw):
+    from paper_2507_23602_amd import rsot
+    return rsot.Problem(x, mu, y, nu, **kw)
+
+
+def _check(prob, x, mu, y, nu, psi, eps, prec, cutoff=math.inf, check_L=True, ref=None,
+           r=None):
+    import torch
+    if r is None:
+        r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), eps)
+    if ref is None:
+        ref = oracle.dual_eval(x, mu, y, nu, psi, eps, cutoff=cutoff, want_L=check_L)
+    tg, tj, tl = TOL[prec]
+    g = r.grad.cpu().numpy()
+    eg = grad_err(g, ref.grad, nu)
+    ej = abs(r.J - ref.J) / abs(ref.J)
+    _say(f"  J={r.J:.15e} ref={ref.J:.15e} ej={ej:.2e} eg={eg:.2e}")
+    if x.shape[0] < 1000 and prec == "mixed":
+        assert abs(r.J - ref.J) <= eps * mu.sum() * 1e-7, (r.J, ref.J)
+    else:
+        assert ej <= tj, (ej, r.J, ref.J)
+    assert eg <= tg, eg
+    if check_L:
+        L = prob.lse().cpu().numpy()
+        fin = np.isfinite(ref.L)
+        assert np.array_equal(np.isfinite(L), fin)
+        el = np.max(np.abs(L[fin] - ref.L[fin]) / np.maximum(1.0, np.abs(ref.L[fin])))
+        assert el <= tl, el
+    return r, ref
+
+
+def _rand_problem(d, cells, n, seed, ragged=True):
+    rng = np.random.default_rng(seed)
+    mesh = W.square_mesh(cells) if d == 2 else W.cube_mesh(cells)
+    rho_v = rng.uniform(0.3, 1.7, size=mesh.verts.shape[0])
+    x, mu = W.quadrature(mesh, rho_v)
+    if ragged:                                   # drop a few points: ragged tail
+        keep = x.shape[0] - 37
+        x, mu = x[:keep], mu[:keep] / mu[:keep].sum()
+    y = rng.uniform(-0.05, 1.05, size=(n, d))
+    nu = rng.uniform(0.5, 1.5, size=n)
+    nu /= nu.sum()
+    return x, mu, y, nu
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("d,cells,n", [(2, 12, 77), (2, 20, 300), (3, 5, 130), (3, 7, 517)])
+def test_dense_parity_random(prec, d, cells, n):
+    _say(f"dense parity d={d} cells={cells} n={n} prec={prec}")
+    x, mu, y, nu = _rand_problem(d, cells, n, seed=100 * d + n)
+    eps = 0.01
+    psi = 0.02 * np.random.default_rng(n).standard_normal(n)
+    prob = _problem(x, mu, y, nu, precision=prec)
+    _check(prob, x, mu, y, nu, psi, eps, prec)
+    _check(prob, x, mu, y, nu, np.zeros(n), 0.003, prec)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_config1_parity(prec):
+    _say(f"config1 parity prec={prec}")
+    p = W.config1()
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec)
+    _check(prob, p.x, p.mu, p.y, p.nu, np.zeros(p.n), p.eps, prec)
+    psi = W.random_psi(9, p.n, p.eps)
+    _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, prec)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_cube_mixture_parity(prec):
+    """Config-2 family at a size the oracle finishes in seconds:
+    cube 12^3 x 24 = 41,472 points, 2,048 mixture targets, eps = 1e-3."""
+    _say(f"cube mixture parity prec={prec}")
+    p = W.cube_mixture(12, 2048, 1e-3)
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec)
+    _check(prob, p.x, p.mu, p.y, p.nu, np.zeros(p.n), p.eps, prec)
+    psi = W.random_psi(3, p.n, p.eps)
+    _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, prec)
+
+
+def test_edge_cases():
+    import torch
+    from paper_2507_23602_amd import rsot
+    _say("edge cases")
+    # one target: closed form J = -(1/2|y - 1/2|^2 + d/24), grad = 0
+    x, mu = W.quadrature(W.square_mesh(6))
+    y = np.array([[0.3, 0.8]])
+    prob = _problem(x, mu, y, np.ones(1))
+    r = prob.dual_eval(torch.zeros(1, dtype=torch.float64, device="cuda"), 0.01)
+    exact = -(0.5 * np.sum((y[0] - 0.5) ** 2) + 2 / 24.0)
+    assert abs(r.J - exact) < 1e-9 * abs(exact)
+    assert abs(float(r.grad[0])) < 2e-6          # e_g <= 1e-6 with nu = nu~ = 1
+    # one point, many targets
+    x1 = np.array([[0.4, 0.6, 0.5]])
+    y3 = np.random.default_rng(1).uniform(0, 1, (70, 3))
+    nu3 = np.full(70, 1 / 70)
+    prob = _problem(x1, np.ones(1), y3, nu3)
+    _check(prob, x1, np.ones(1), y3, nu3, np.zeros(70), 0.05, "mixed")
+    # non-finite psi is reported, outputs untouched
+    prob = _problem(x, mu, y, np.ones(1))
+    bad = torch.tensor([float("nan")], dtype=torch.float64, device="cuda")
+    out = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(rsot.RsotError) as e:
+        prob.dual_eval(bad, 0.01, out=out)
+    assert e.value.code == rsot.ERR_NONFINITE
+    assert float(out[0]) == 7.0
+    with pytest.raises(rsot.RsotError) as e:
+        prob.dual_eval(torch.zeros(1, dtype=torch.float64, device="cuda"), -1.0)
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    # invalid inputs at creation
+    with pytest.raises(rsot.RsotError) as e:
+        _problem(x, mu, y, -np.ones(1))
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    xn = x.copy()
+    xn[3, 0] = np.inf
+    with pytest.raises(rsot.RsotError) as e:
+        _problem(xn, mu, y, np.ones(1))
+    assert e.value.code == rsot.ERR_NONFINITE
+    # memory cap
+    with pytest.raises(rsot.RsotError) as e:
+        _problem(x, mu, y, np.ones(1), mem_limit_bytes=4096)
+    assert e.value.code == rsot.ERR_OOM
+
+
+def test_bitwise_repeatable():
+    import torch
+    _say("bitwise repeat")
+    p = W.cube_mixture(8, 1000, 2e-3)
+    prob = _problem(p.x, p.mu, p.y, p.nu)
+    psi = torch.as_tensor(W.random_psi(5, p.n, 2e-3), device="cuda")
+    a = prob.dual_eval(psi, p.eps)
+    ga = a.grad.clone()
+    b = prob.dual_eval(psi, p.eps)
+    assert a.J == b.J
+    assert torch.equal(ga, b.grad)
+
+
+def test_objective_only_matches():
+    import torch
+    p = W.config1()
+    prob = _problem(p.x, p.mu, p.y, p.nu)
+    psi = torch.as_tensor(W.random_psi(2, p.n, p.eps), device="cuda")
+    a = prob.dual_eval(psi, p.eps)
+    b = prob.dual_eval(psi, p.eps, want_grad=False)
+    assert a.J == b.J and b.grad is None
+
+
+# -- truncated rules ---------------------------------------------------------
+@pytest.mark.parametrize("rule", ["geom", "int", "pw"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_cutoff_rules_parity(rule, prec):
+    """Paper's cutoff rules (Eqs. truncation_cutoff_geom/int, cost_cutoff_delta):
+    the GPU's cutoff agrees with the oracle's formula, and the truncated J, grad
+    and kept-pair count agree with the oracle at that cutoff."""
+    import torch
+    _say(f"cutoff rule {rule} prec={prec}")
+    p = W.cube_mixture(10, 3000, 2e-3)
+    tau = {"geom": 1e-6, "int": 1e-6, "pw": None}[rule]
+    delta = 1e-8
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec, truncation=rule,
+                    tau=tau or 1e-12, delta_thr=delta)
+    psi = W.random_psi(4, p.n, p.eps)
+    dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps, want_L=True)
+    absJ = abs(dense.J)
+    C0 = oracle.covering_cost(p.x, p.y)
+    assert abs(prob.covering_cost() - C0) <= 1e-14 * C0
+    prob.set_reference(absJ)
+    psi_d = torch.as_tensor(psi, device="cuda")
+    if rule == "int":
+        r0 = prob.dual_eval(psi_d, p.eps)          # first call: dense, stores D
+        assert r0.info["dense_fallback"] == 1
+        D = oracle.integral_D(p.mu, dense.L)
+        # ln D is dominated by the points with the smallest sums, so it carries
+        # a single point's error (mixed: FP32 exponentials, not averaged)
+        assert abs(r0.info["log_D"] - math.log(D)) < (1e-8 if prec == "mixed" else 1e-12)
+        C_ref = oracle.cutoff_int(C0, psi, D, tau, absJ, p.eps)
+    elif rule == "geom":
+        C_ref = oracle.cutoff_geom(C0, psi, p.nu, tau, absJ, p.eps)
+    else:
+        C_ref = oracle.cutoff_pw(psi, p.nu, delta, p.eps)
+    r = prob.dual_eval(psi_d, p.eps)
+    C = r.info["cutoff"]
+    _say(f"  C={C:.15e} C_ref={C_ref:.15e} kept={r.info['kept_pairs']}")
+    # the INT cutoff carries the (mixed-precision) D of the previous evaluation
+    ctol = 1e-9 if (rule == "int" and prec == "mixed") else 1e-12
+    assert abs(C - C_ref) <= ctol * abs(C_ref)
+    ref = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps, cutoff=C, want_L=True)
+    assert r.info["kept_pairs"] == ref.kept
+    assert r.info["kept_pairs"] < p.nq * p.n
+    assert r.info["n_empty_qp"] == ref.nempty
+    _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, prec, ref=ref, r=r)
+    if rule != "pw":           # App. B bound, up to FP64 round-off of the two sums
+        assert -1e-13 * absJ <= dense.J - ref.J <= tau * absJ
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_tile_rule_parity(prec, d):
+    """Tile-local rule: GPU kept set, J and grad equal the oracle's rule
+    applied to the GPU's own tile/block partition; error bound holds."""
+    import torch
+    _say(f"tile rule d={d} prec={prec}")
+    if d == 3:
+        p = W.cube_mixture(10, 3000, 1e-3)
+    else:
+        p = W.square_uniform(48, 4000, seed=6, eps=1e-3)
+    tau = 1e-8
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec, truncation="tile", tau=tau)
+    psi = W.random_psi(8, p.n, p.eps)
+    dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    prob.set_reference(abs(dense.J))
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    tile_of, block_of, nt, nb = prob.partition()
+    ref = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of.cpu().numpy(), nt,
+                                block_of.cpu().numpy(), nb, tau, abs(dense.J), want_L=True)
+    _say(f"  kept gpu={r.info['kept_pairs']} oracle={ref.kept} of {p.nq * p.n}")
+    assert r.info["kept_pairs"] == ref.kept
+    assert ref.kept < p.nq * p.n
+    _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, prec, ref=ref, r=r)
+    assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
+
+
+def test_full_size_sampled_points():
+    """Full-size 3D workload (6.29M points x 65,536 targets) in the launch
+    configuration the benchmark times: the per-point L_q of 3,000 sampled
+    points equal the oracle's (L_q depends on that point only), and the
+    gradient sums to sum mu - sum nu."""
+    import torch
+    _say("full size sampled")
+    p = W.config2()
+    prob = _problem(torch.as_tensor(p.x, device="cuda"), torch.as_tensor(p.mu, device="cuda"),
+                    torch.as_tensor(p.y, device="cuda"), torch.as_tensor(p.nu, device="cuda"))
+    psi = W.random_psi(11, p.n, p.eps)
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    L = prob.lse().cpu().numpy()
+    idx = np.random.default_rng(0).choice(p.nq, 3000, replace=False)
+    ref = oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, want_L=True)
+    el = np.max(np.abs(L[idx] - ref.L) / np.maximum(1.0, np.abs(ref.L)))
+    _say(f"  sampled L err {el:.2e}")
+    assert el <= 1e-6
+    g = r.grad.cpu().numpy()
+    assert abs(g.sum() - (p.mu.sum() - p.nu.sum())) < 1e-9
+    assert r.info["kept_pairs"] == p.nq * p.n
