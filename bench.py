@@ -53,6 +53,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
+    ap.add_argument("--multilevel", action="store_true",
+                    help="also time the combined multilevel solve of the 2D disk workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
@@ -196,10 +198,39 @@ def main():
         pr1.close()
         out["extras"] = extras
 
+    if args.multilevel:
+        out.setdefault("extras", {})["multilevel"] = multilevel_leg()
+
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
                                            psi1 if not args.no_extras else None)
     print(json.dumps(out), flush=True)
+
+
+def multilevel_leg():
+    """Time to ||grad||_1 < 1e-6 of the combined multilevel solve (Sec. 5.3)
+    with the eps schedule, on the 2D disk workload; per-level breakdown."""
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+    c3 = W.config3()
+    log(f"[bench] multilevel workload {c3['name']}")
+    t0 = time.perf_counter()
+    levels = rsot.target_hierarchy(torch.as_tensor(c3["y"], device="cuda"),
+                                   torch.as_tensor(c3["nu"], device="cuda"),
+                                   c3["target_levels"], lloyd_iters=20, seed=6)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    ml = rsot.Multilevel(c3["sources"], levels, precision="mixed", truncation="tile", tau=1e-12)
+    t0 = time.perf_counter()
+    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5)
+    t_s = time.perf_counter() - t0
+    log(f"[bench] multilevel: hierarchy {t_h:.2f}s, solve {t_s:.2f}s, status {info['status']}, "
+        f"|g|_1 {info['grad_l1']:.2e}, iterations {info['iterations']}, "
+        f"seconds {[round(v, 3) for v in info['seconds']]}, "
+        f"refine {[round(v, 3) for v in info['refine_seconds']]}")
+    ml.close()
+    return {"workload": c3["name"], "hierarchy_seconds": t_h, "solve_seconds": t_s,
+            "target_sizes": [int(l[1].numel()) for l in levels], **info}
 
 
 def cpu_baseline(p, psi, psi_c1):

@@ -78,7 +78,7 @@ typedef struct {
     double delta_thr;         /* pointwise threshold (PW); default 1e-12           */
     int inputs_on_device;     /* 1: x, mu, y, nu passed to create are device ptrs  */
     int seg_tiles;            /* gradient pass: point tiles per work item; 0=auto  */
-    int chunk_log2;           /* reserved for the autotuner; 0 = default           */
+    int seg_blocks;           /* objective pass: target blocks per work item; 0=256 */
     int64_t mem_limit_bytes;  /* cap on library device memory; 0 = none            */
 } rsot_options;
 
@@ -163,6 +163,28 @@ rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi, doubl
                            double *grad_out, rsot_eval_info *info);
 
 /*
+ * Evaluates n problems in one call (same quantities as rsot_dual_eval for
+ * each): every problem's preparation and culling, one host synchronisation,
+ * then one persistent launch per pass in which wavefronts pull (problem, work
+ * item) pairs from a shared queue, problems in decreasing order of work.
+ * Problems with the FP64 arithmetic or a cutoff rule (GEOM/INT/PW) run their
+ * own passes inside the same call. All work is issued on ps[0]'s stream.
+ *   ps        n problem handles (distinct)
+ *   eps       HOST array of n eps values
+ *   psi       HOST array of n DEVICE pointers (each problem's n_target doubles)
+ *   J_out     HOST array of n doubles
+ *   grad_out  NULL, or HOST array of n DEVICE pointers (NULL entries allowed)
+ *   infos     NULL or HOST array of n infos (per-problem pass times are 0)
+ *   batch_ms  NULL or HOST: device time of the whole batch
+ * Results equal per-problem rsot_dual_eval calls up to the order of the
+ * floating-point sums (identical for the same segmentation).
+ */
+rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, const double *eps,
+                                   const double *const *psi, double *J_out,
+                                   double *const *grad_out, rsot_eval_info *infos,
+                                   double *batch_ms);
+
+/*
  * Per-point log-sum-exp L_q = ln sum_j nu_j exp((psi_j - c_qj)/eps) of the
  * last evaluation (the log of S_q in Alg. 2; -inf for a dropped point), in
  * the caller's point order. L_out: DEVICE pointer, n_quad doubles.
@@ -182,6 +204,22 @@ rsot_status rsot_covering_cost(rsot_problem *p, double *C0_out);
  */
 rsot_status rsot_get_partition(rsot_problem *p, int32_t *tile_of_point, int32_t *block_of_target,
                                int64_t *n_tiles, int64_t *n_blocks);
+
+/*
+ * Softmax potential refinement (Eq. softmax_refinement_formula, Sec. 5.2):
+ *   psi_fine_k = -eps ln( sum_q mu_q exp(-c(x_q, y_fine_k)/eps) / S_q ),
+ *   S_q = sum_j nu_j exp((psi_coarse_j - c(x_q, y_j))/eps)
+ * over the problem's points and (coarse) targets. Evaluated in the log
+ * domain; (point tile, fine block) pairs whose bound is below 1e-12 of the
+ * kept sum are skipped (psi moves by at most 1e-12 eps).
+ *   psi_coarse   DEVICE pointer, the problem's n_target doubles (caller order)
+ *   n_fine       number of fine targets (> 0)
+ *   y_fine       DEVICE pointer, n_fine x dim doubles
+ *   psi_fine_out DEVICE pointer, n_fine doubles
+ * Also leaves the coarse L_q readable through rsot_get_lse.
+ */
+rsot_status rsot_softmax_refine(rsot_problem *p, double eps, const double *psi_coarse,
+                                int64_t n_fine, const double *y_fine, double *psi_fine_out);
 
 /* ------------------------------------------------------------------------ */
 /* Solver (Alg. 1): L-BFGS on J with an eps schedule (Sec. 4.2).            */
@@ -236,6 +274,93 @@ void rsot_solve_params_default(rsot_solve_params *sp);
  */
 rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp, double *psi_inout,
                        rsot_solve_info *info);
+
+/* ------------------------------------------------------------------------ */
+/* Multilevel (Sec. 5): target hierarchy, combined source/target solve.      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Target-set hierarchy by k-means coarsening (Sec. 5.2): level l-1 is a
+ * k-means clustering of the points of level l; each non-empty cluster becomes
+ * one point at its centroid (mean of member points) with the summed mass of
+ * its members, so every level has the same total mass. Levels run from the
+ * coarsest (0) to the finest (n_levels-1 = the input).
+ *   y, nu          DEVICE pointers: n x dim targets and masses
+ *   n_per_level    HOST array: requested sizes, non-decreasing, last == n
+ *   lloyd_iters    Lloyd iterations per level (initial centroids: means of
+ *                  consecutive groups in Morton order)
+ *   seed           reserved (the construction is deterministic)
+ *   y_levels[l]    DEVICE buffers of n_per_level[l] x dim doubles (caller-owned)
+ *   nu_levels[l]   DEVICE buffers of n_per_level[l] doubles
+ *   parent_levels  NULL, or HOST array of DEVICE int32 buffers: parent_levels[l]
+ *                  (l >= 1, n_per_level[l] entries) receives, for every point of
+ *                  level l, the index of its cluster in level l-1; entry 0 unused
+ *   n_out[l]       HOST: realised sizes (empty clusters are dropped)
+ * The returned points are the means of their final clusters and carry the
+ * clusters' summed masses.
+ */
+rsot_status rsot_target_hierarchy(int dim, int64_t n, const double *y, const double *nu,
+                                  int n_levels, const int64_t *n_per_level, int lloyd_iters,
+                                  uint64_t seed, void *hip_stream, double *const *y_levels,
+                                  double *const *nu_levels, int32_t *const *parent_levels,
+                                  int64_t *n_out);
+
+#define RSOT_ML_MAX_LEVELS 16
+enum { RSOT_TRANSFER_SOFTMAX = 0 };
+
+typedef struct rsot_multilevel rsot_multilevel;
+
+/*
+ * Copies source levels T_0..T_{n_source_levels-1} (coarsest first: points
+ * x[l] and masses mu[l]) and target levels nu^(0)..nu^(n_target_levels-1)
+ * (coarsest first) into library memory. opt->inputs_on_device selects host or
+ * device pointers; problems for each (source level, target level) pair are
+ * created when first needed with opt.
+ */
+rsot_status rsot_multilevel_create(int dim, int n_source_levels, const int64_t *n_quad,
+                                   const double *const *x, const double *const *mu,
+                                   int n_target_levels, const int64_t *n_target,
+                                   const double *const *y, const double *const *nu,
+                                   const rsot_options *opt, void *hip_stream,
+                                   rsot_multilevel **out);
+void rsot_multilevel_destroy(rsot_multilevel *ml);
+
+/* Combined index rule of Sec. 5.3: is = max(0, l - (Lmax - Lmu)),
+ * it = max(0, l - (Lmax - Lnu)), Lmax = max(Lmu, Lnu). */
+void rsot_multilevel_indices(int n_source_levels, int n_target_levels, int l, int *is, int *it);
+
+typedef struct {
+    const double *eps;        /* HOST: eps of each stage                                 */
+    const int *level;         /* HOST: combined level l of each stage, non-decreasing    */
+    int n_stages;
+    rsot_solve_params base;   /* tol, max_iter, lbfgs_m, ... (eps_schedule ignored)      */
+    double level_tol;         /* ||grad||_1 target of non-final levels; 0 = base.tol     */
+    int transfer;             /* RSOT_TRANSFER_SOFTMAX (Eq. softmax_refinement_combined) */
+} rsot_ml_params;
+
+typedef struct {
+    int n_steps;                                  /* Lmax + 1                     */
+    int source_level[RSOT_ML_MAX_LEVELS];
+    int target_level[RSOT_ML_MAX_LEVELS];
+    int iterations[RSOT_ML_MAX_LEVELS];
+    int evaluations[RSOT_ML_MAX_LEVELS];
+    double seconds[RSOT_ML_MAX_LEVELS];           /* solve time of each step      */
+    double refine_seconds[RSOT_ML_MAX_LEVELS];    /* transfer time into each step */
+    int64_t refine_pairs[RSOT_ML_MAX_LEVELS];     /* pairs the refinement summed  */
+    double total_seconds;
+    double grad_l1;
+    int status;
+} rsot_ml_info;
+
+/*
+ * Combined multilevel solve (Sec. 5.3) with the eps stages of mp: step
+ * l = 0..Lmax solves on (T_is(l), nu^(it(l))); when it(l) = it(l-1)+1 the
+ * potential is transferred by softmax refinement at the eps of the last
+ * stage of step l-1 (Eq. softmax_refinement_formula_combined), otherwise it is
+ * kept. psi_out: HOST pointer, n_target of the finest level, centred.
+ */
+rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_params *mp, double *psi_out,
+                                  rsot_ml_info *info);
 
 #ifdef __cplusplus
 }

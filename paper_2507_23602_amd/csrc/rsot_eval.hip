@@ -32,6 +32,7 @@
 #define RSOT_LN2 0.69314718055994530942
 #define RSOT_LOG2E 1.44269504088896340736
 #define CH 8   // pairs per chunk between FP64 flushes
+#define RSOT_SEG1_DEFAULT 256   // target blocks per objective-pass work item
 
 // v_exp_f32 is accurate to < 1 ulp (max relative error 8.4e-8 measured on
 // gfx950) but its error has a nonzero mean: -3.40e-9 relative over
@@ -402,27 +403,84 @@ __device__ __forceinline__ void lse_block(const double4 *__restrict__ T,
     }
 }
 
+// Mixed-precision fast path for blocks whose pairs are all kept: the
+// reference m enters the FMA chain's initial value (B_j - m), so each pair
+// costs the FP64 argument, one rounding, one v_exp_f32 and one FP32 add.
+// m starts at ceil(t) of a kept target, so m <= max_j t_j + 1 always. The
+// reference must also stay close to the running maximum: the FP32-rounded
+// argument u = t - m carries an absolute error ~|u| 2^-24, so the largest
+// terms need |u| < 1. A chunk whose FP32 sum exceeds 2 and whose largest u is
+// positive raises m to ceil of that u and is recomputed from the FP64
+// records; without the trigger every u < 1. Spurious triggers (several terms
+// just below the reference) cost the max over the chunk only.
+template <int D>
+__device__ __forceinline__ void lse_block_fast(const double4 *__restrict__ T, double x0,
+                                               double x1, double x2, double &m, double &s) {
+    for (int k0 = 0; k0 < 64; k0 += CH) {
+        float u[CH];
+        float cs = 0.0f;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const double4 r = T[k0 + k];
+            double v = r.w - m;
+            v = fma(x0, r.x, v);
+            v = fma(x1, r.y, v);
+            if (D == 3) v = fma(x2, r.z, v);
+            u[k] = (float)v;
+            cs += __builtin_amdgcn_exp2f(u[k]);
+        }
+        if (!(cs <= 2.0f)) {
+            float mx = u[0];
+#pragma unroll
+            for (int k = 1; k < CH; ++k) mx = fmaxf(mx, u[k]);
+            if (!(mx > 0.0f)) {
+                s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+                continue;
+            }
+            const double dm = ceil((double)mx);
+            s = ldexp(s, -(int)fmin(dm, 2000.0));
+            m += dm;
+            cs = 0.0f;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const double4 r = T[k0 + k];
+                double v = r.w - m;
+                v = fma(x0, r.x, v);
+                v = fma(x1, r.y, v);
+                if (D == 3) v = fma(x2, r.z, v);
+                cs += __builtin_amdgcn_exp2f((float)v);
+            }
+        }
+        s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+    }
+}
+
+// Objective pass, one work item = (tile, segment of its block list): per
+// lane the partial log2-sum-exp of t_j = B_j + x.Y_j over the segment's
+// targets, and the number of pairs it summed. Rows of very different length
+// (a tile far from every target keeps many blocks) are split into segments,
+// so no wavefront carries a whole long row.
 template <int D, bool F64, int MODE>
-__global__ __launch_bounds__(256) void k_pass1(
-    double4 *__restrict__ qp, const double *__restrict__ qmu, const double *__restrict__ qlog2mu,
-    const int32_t *__restrict__ qperm, const double4 *__restrict__ trec,
+__device__ __forceinline__ void pass1_item(
+    const double4 *__restrict__ qp, const double4 *__restrict__ trec,
     const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
-    const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ row_idx, int64_t n_tiles,
-    int64_t n_blocks, double kcs, double *__restrict__ qH, double *__restrict__ qlse,
-    double *__restrict__ tile_part) {
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (t >= n_tiles) return;
+    const uint32_t *__restrict__ row_idx, int64_t t, int64_t e0, int64_t e1, double kcs,
+    int64_t w, int lane, double *__restrict__ part, double *__restrict__ partk) {
     const int64_t q = t * 64 + lane;
     const double4 xr = qp[q];
     const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
     const double A = -kcs * (x0 * x0 + x1 * x1 + x2 * x2);
-    int64_t e0 = 0, e1 = n_blocks;
-    if (MODE != MODE_DENSE) {
-        e0 = row_ptr[t];
-        e1 = row_ptr[t + 1];
-    }
     double m = -1e300, s = 0.0, kept = 0.0;
+    constexpr bool FAST = !F64 && MODE != MODE_MASK;
+    if (FAST && e1 > e0) {
+        // reference from the first target of the first block (a kept target)
+        const uint32_t ent0 = MODE == MODE_DENSE ? (uint32_t)e0 : row_idx[e0];
+        const double4 r = trec[(int64_t)(ent0 & ~RSOT_PARTIAL_BIT) * 64];
+        double v = x0 * r.x;
+        v = fma(x1, r.y, v);
+        if (D == 3) v = fma(x2, r.z, v);
+        m = ceil(v + r.w);
+    }
     for (int64_t e = e0; e < e1; ++e) {
         const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
@@ -430,17 +488,71 @@ __global__ __launch_bounds__(256) void k_pass1(
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
             lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
         } else {
-            lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
+            if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
+            else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
             kept += (double)blk_cnt[b];
         }
     }
+    part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
+    partk[w * 64 + lane] = kept;
+}
+
+template <int D, bool F64, int MODE>
+__global__ __launch_bounds__(256) void k_pass1(
+    const double4 *__restrict__ qp, const double4 *__restrict__ trec,
+    const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
+    const uint32_t *__restrict__ row_idx, const int32_t *__restrict__ wi_tile,
+    const int64_t *__restrict__ wi_range, int64_t n_items, int64_t n_blocks, int64_t seg1,
+    int64_t n_seg1, double kcs, double *__restrict__ part, double *__restrict__ partk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= n_items) return;
+    int64_t t, e0, e1;
+    if (MODE == MODE_DENSE) {
+        t = w / n_seg1;
+        e0 = (w % n_seg1) * seg1;
+        e1 = std::min<int64_t>(e0 + seg1, n_blocks);
+    } else {
+        t = wi_tile[w];
+        e0 = wi_range[2 * w];
+        e1 = wi_range[2 * w + 1];
+    }
+    pass1_item<D, F64, MODE>(qp, trec, tG, blk_cnt, row_idx, t, e0, e1, kcs, w, lane, part, partk);
+}
+
+// One wavefront per tile: merge the tile's partial log-sum-exps (FP64) into
+// Lt = log2 sum_j 2^(B_j + x.Y_j), then S_q = log2 mu_q - Lt (for the
+// gradient pass), L_q = (Lt + A_q) ln 2, and the tile's objective, ln D,
+// kept-pair and empty-point partials.
+__global__ __launch_bounds__(256) void k_pass1_combine(
+    double4 *__restrict__ qp, const double *__restrict__ qmu, const double *__restrict__ qlog2mu,
+    const int32_t *__restrict__ qperm, const double *__restrict__ part,
+    const double *__restrict__ partk, const int64_t *__restrict__ wi_ptr, int64_t n_seg1,
+    int64_t n_tiles, double kcs, int want_H, double *__restrict__ qH, double *__restrict__ qlse,
+    double *__restrict__ tile_part) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const int64_t q = t * 64 + lane;
+    const int64_t w0 = wi_ptr ? wi_ptr[t] : t * n_seg1;
+    const int64_t w1 = wi_ptr ? wi_ptr[t + 1] : w0 + n_seg1;
+    double mx = -INFINITY, kept = 0.0;
+    for (int64_t w = w0; w < w1; ++w) {
+        mx = fmax(mx, part[w * 64 + lane]);
+        kept += partk[w * 64 + lane];
+    }
+    double sum = 0.0;
+    if (mx > -INFINITY)
+        for (int64_t w = w0; w < w1; ++w) sum += exp2(part[w * 64 + lane] - mx);
+    const double4 xr = qp[q];
+    const double A = -kcs * (xr.x * xr.x + xr.y * xr.y + xr.z * xr.z);
     const bool real = qperm[q] >= 0;
-    const bool empty = !(s > 0.0);
-    const double Lt = empty ? -INFINITY : m + log2(s);
+    const bool empty = !(mx > -INFINITY);
+    const double Lt = empty ? -INFINITY : mx + log2(sum);
     const double lm = qlog2mu[q];
     const double S = empty ? -INFINITY : lm - Lt;
     reinterpret_cast<double *>(qp)[q * 4 + 3] = S;
-    if (MODE == MODE_MASK) qH[q] = S - A;
+    if (want_H) qH[q] = S - A;
     const double L2 = Lt + A;
     qlse[q] = empty ? -INFINITY : L2 * RSOT_LN2;
     const double jp = (real && !empty) ? qmu[q] * L2 : 0.0;
@@ -499,6 +611,30 @@ __device__ __forceinline__ double mass_tile(const double4 *__restrict__ Q,
 }
 
 template <int D, bool F64, int MODE>
+__device__ __forceinline__ void pass2_item(const double4 *__restrict__ qp,
+                                           const double *__restrict__ qH,
+                                           const double4 *__restrict__ trec,
+                                           const double *__restrict__ tG,
+                                           const uint32_t *__restrict__ col_idx, int64_t b,
+                                           int64_t e0, int64_t e1, int64_t w, int lane,
+                                           double *__restrict__ gpart) {
+    const int64_t j = b * 64 + lane;
+    const double4 rec = trec[j];
+    const double G = MODE == MODE_MASK ? tG[j] : 0.0;
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
+        const int64_t t = ent & ~RSOT_PARTIAL_BIT;
+        const double4 *__restrict__ Q = qp + t * 64;
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
+            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G);
+        else
+            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G);
+    }
+    gpart[w * 64 + lane] = acc;
+}
+
+template <int D, bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_pass2(
     const double4 *__restrict__ qp, const double *__restrict__ qH,
     const double4 *__restrict__ trec, const double *__restrict__ tG,
@@ -524,20 +660,136 @@ __global__ __launch_bounds__(256) void k_pass2(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    const int64_t j = b * 64 + lane;
-    const double4 rec = trec[j];
-    const double G = MODE == MODE_MASK ? tG[j] : 0.0;
-    double acc = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
-        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
-        const int64_t t = ent & ~RSOT_PARTIAL_BIT;
-        const double4 *__restrict__ Q = qp + t * 64;
-        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
-            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G);
-        else
-            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G);
+    pass2_item<D, F64, MODE>(qp, qH, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
+}
+
+// ---------------------------------------------------------------------------
+// batched evaluation: one persistent launch per pass over many problems
+// ---------------------------------------------------------------------------
+// Work descriptor of one problem in a batch (device memory).
+struct BatchDesc {
+    int dim, mode;
+    int64_t n_tiles, n_blocks;
+    const double4 *qp;
+    const double *qH;
+    const double4 *trec;
+    const double *tG;
+    const int32_t *blk_cnt;
+    const uint32_t *row_idx;
+    const int32_t *wi1_tile;
+    const int64_t *wi1_range;
+    int64_t n_items1, seg1, n_seg1;
+    double kcs;
+    double *part1, *part1k;
+    const uint32_t *col_idx;
+    const int32_t *wi_block;
+    const int64_t *wi_range;
+    int64_t n_wi, n_seg, seg;
+    double *gpart;
+};
+
+__global__ void k_zero_counter(unsigned long long *c) { *c = 0ull; }
+
+// next work item of the shared queue, same value in every lane
+__device__ inline uint64_t next_item(unsigned long long *counter, int lane) {
+    unsigned long long g = 0;
+    if (lane == 0) g = atomicAdd(counter, 1ull);
+    g = __shfl(g, 0, 64);
+    return (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(g & 0xffffffffu)) |
+           ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(g >> 32)) << 32);
+}
+
+// position k of the problem owning queue item g: begin[k] <= g < begin[k+1]
+__device__ inline int owner(const int64_t *__restrict__ begin, int n, uint64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)begin[mid] <= g) lo = mid;
+        else hi = mid - 1;
     }
-    gpart[w * 64 + lane] = acc;
+    return lo;
+}
+
+// Objective pass of every problem of the batch: waves pull items from one
+// queue (problems in decreasing cost order) until it is empty.
+__global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restrict__ descs,
+                                                       const int32_t *__restrict__ order,
+                                                       const int64_t *__restrict__ begin, int n,
+                                                       unsigned long long *counter) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = (uint64_t)begin[n];
+    for (;;) {
+        const uint64_t g = next_item(counter, lane);
+        if (g >= total) break;
+        const int k = owner(begin, n, g);
+        const BatchDesc &d = descs[order[k]];
+        const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
+        int64_t t, e0, e1, w;
+        if (d.mode == MODE_DENSE) {
+            // consecutive items share the block segment (target records)
+            const int64_t s1 = v / d.n_tiles;
+            t = v % d.n_tiles;
+            e0 = s1 * d.seg1;
+            e1 = std::min<int64_t>(e0 + d.seg1, d.n_blocks);
+            w = t * d.n_seg1 + s1;
+        } else {
+            w = v;
+            t = d.wi1_tile[w];
+            e0 = d.wi1_range[2 * w];
+            e1 = d.wi1_range[2 * w + 1];
+        }
+        if (d.dim == 3) {
+            if (d.mode == MODE_DENSE)
+                pass1_item<3, false, MODE_DENSE>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
+            else
+                pass1_item<3, false, MODE_LIST>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
+        } else {
+            if (d.mode == MODE_DENSE)
+                pass1_item<2, false, MODE_DENSE>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
+            else
+                pass1_item<2, false, MODE_LIST>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restrict__ descs,
+                                                       const int32_t *__restrict__ order,
+                                                       const int64_t *__restrict__ begin, int n,
+                                                       unsigned long long *counter) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = (uint64_t)begin[n];
+    for (;;) {
+        const uint64_t g = next_item(counter, lane);
+        if (g >= total) break;
+        const int k = owner(begin, n, g);
+        const BatchDesc &d = descs[order[k]];
+        const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
+        int64_t b, e0, e1, w;
+        if (d.mode == MODE_DENSE) {
+            // consecutive items share the point segment (point records)
+            const int64_t sgi = v / d.n_blocks;
+            b = v % d.n_blocks;
+            e0 = sgi * d.seg;
+            e1 = std::min<int64_t>(e0 + d.seg, d.n_tiles);
+            w = b * d.n_seg + sgi;
+        } else {
+            w = v;
+            b = d.wi_block[w];
+            e0 = d.wi_range[2 * w];
+            e1 = d.wi_range[2 * w + 1];
+        }
+        if (d.dim == 3) {
+            if (d.mode == MODE_DENSE)
+                pass2_item<3, false, MODE_DENSE>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
+            else
+                pass2_item<3, false, MODE_LIST>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
+        } else {
+            if (d.mode == MODE_DENSE)
+                pass2_item<2, false, MODE_DENSE>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
+            else
+                pass2_item<2, false, MODE_LIST>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
+        }
+    }
 }
 
 // per target: merge the work-item partials in order, un-permute, norms
@@ -663,12 +915,20 @@ static rsot_status grow(rsot_problem *p, T **ptr, size_t *cap, size_t count) {
     return RSOT_OK;
 }
 
+struct Pass1Work {
+    int64_t n_items, seg1, n_seg1;
+};
+
 template <int D, bool F64, int MODE>
-static void launch_pass1(rsot_problem *p, double kcs) {
-    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256),
-                       0, p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->trec, p->tG,
-                       p->blk_cnt, p->row_ptr, p->row_idx, p->n_tiles, p->n_blocks, kcs, p->qH,
-                       p->qlse, p->tile_part);
+static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
+    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3((unsigned)((pw.n_items + 3) / 4)), dim3(256),
+                       0, p->stream, p->qp, p->trec, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile,
+                       p->wi1_range, pw.n_items, p->n_blocks, pw.seg1, pw.n_seg1, kcs, p->part1,
+                       p->part1k);
+    hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
+                       p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
+                       MODE == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
+                       p->n_tiles, kcs, MODE == MODE_MASK ? 1 : 0, p->qH, p->qlse, p->tile_part);
 }
 
 template <int D, bool F64, int MODE>
@@ -685,10 +945,10 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
 
 template <int D, bool F64>
 static void launch_passes(rsot_problem *p, int mode, bool grad, double kcs, int64_t n_wi,
-                          int64_t n_seg, int64_t seg) {
-    if (mode == MODE_DENSE) launch_pass1<D, F64, MODE_DENSE>(p, kcs);
-    else if (mode == MODE_LIST) launch_pass1<D, F64, MODE_LIST>(p, kcs);
-    else launch_pass1<D, F64, MODE_MASK>(p, kcs);
+                          int64_t n_seg, int64_t seg, const Pass1Work &pw) {
+    if (mode == MODE_DENSE) launch_pass1<D, F64, MODE_DENSE>(p, kcs, pw);
+    else if (mode == MODE_LIST) launch_pass1<D, F64, MODE_LIST>(p, kcs, pw);
+    else launch_pass1<D, F64, MODE_MASK>(p, kcs, pw);
     (void)hipEventRecord(p->ev_mid, p->stream);
     if (!grad) return;
     if (mode == MODE_DENSE) launch_pass2<D, F64, MODE_DENSE>(p, n_wi, n_seg, seg);
@@ -704,166 +964,241 @@ static rsot_status ensure_cull_buffers(rsot_problem *p) {
     RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
     RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
     RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
+    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi1_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
     RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_cnt, sizeof(int32_t) * p->n_tiles));
     RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_cnt, sizeof(int32_t) * p->n_blocks));
     return RSOT_OK;
 }
 
-rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi, double *J_out,
-                           double *grad_out, rsot_eval_info *info) {
-    const int D = p->dim;
-    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
-    const bool grad = grad_out != nullptr;
-    const double cs = p->opt.cost_scale;
-    const double kappa = RSOT_LOG2E / eps;
-    int rule = p->opt.truncation;
-    int dense_fallback = 0;
-    if ((rule == RSOT_TRUNC_GEOM || rule == RSOT_TRUNC_TILE || rule == RSOT_TRUNC_INT) &&
-        !(p->absJ_ref > 0.0)) {
-        rule = RSOT_TRUNC_DENSE;
-        dense_fallback = 1;
-    }
-    if (rule == RSOT_TRUNC_INT && !p->have_D) {
-        rule = RSOT_TRUNC_DENSE;
-        dense_fallback = 1;
-    }
-    if (rule == RSOT_TRUNC_GEOM || rule == RSOT_TRUNC_INT) RSOT_TRY(rsot_compute_covering_cost(p));
+// One evaluation in stages, so that a batch of problems can share host
+// synchronisations and persistent launches:
+//   plan_begin  target records, psi statistics, cutoff, culling and counts
+//   plan_lists  (after a sync when culling ran) list and work-item fills
+//   plan_passes objective + gradient passes of this problem alone
+//   plan_finish gradient merge, J, statistics, copy of the scalars to host
+//   plan_result (after a sync) outputs and problem state
+struct EvalPlan {
+    rsot_problem *p = nullptr;
+    hipStream_t st = nullptr;
+    double eps = 0, kappa = 0, kcs = 0;
+    const double *psi = nullptr;
+    double *grad = nullptr;
+    int rule = 0, mode = MODE_DENSE, dense_fallback = 0;
+    bool culled = false;
+    int64_t n_wi = 0, n_seg = 1, seg = 1;
+    Pass1Work pw{0, 0, 1};
+    int64_t seg1_cfg = RSOT_SEG1_DEFAULT;
+};
 
-    RSOT_HIP(hipEventRecord(p->ev0, p->stream));
+static rsot_status plan_begin(EvalPlan &e) {
+    rsot_problem *p = e.p;
+    const hipStream_t st = e.st;
+    const int D = p->dim;
+    const double cs = p->opt.cost_scale, eps = e.eps;
+    e.kappa = RSOT_LOG2E / eps;
+    e.kcs = e.kappa * cs;
+    e.rule = p->opt.truncation;
+    if ((e.rule == RSOT_TRUNC_GEOM || e.rule == RSOT_TRUNC_TILE || e.rule == RSOT_TRUNC_INT) &&
+        !(p->absJ_ref > 0.0)) {
+        e.rule = RSOT_TRUNC_DENSE;
+        e.dense_fallback = 1;
+    }
+    if (e.rule == RSOT_TRUNC_INT && !p->have_D) {
+        e.rule = RSOT_TRUNC_DENSE;
+        e.dense_fallback = 1;
+    }
+    if (e.rule == RSOT_TRUNC_GEOM || e.rule == RSOT_TRUNC_INT) {
+        const hipStream_t keep = p->stream;
+        p->stream = st;
+        rsot_status s = rsot_compute_covering_cost(p);
+        p->stream = keep;
+        RSOT_TRY(s);
+    }
+    RSOT_HIP(hipEventRecord(p->ev0, st));
     const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
     const dim3 gtile((unsigned)((p->n_tiles + 3) / 4));
     if (D == 2)
-        hipLaunchKernelGGL(k_prep_targets<2>, gblk, dim3(256), 0, p->stream, psi, p->tperm, p->ty,
-                           p->tnu, p->tlog2nu, p->n_blocks, kappa, cs, p->trec, p->tpsi,
+        hipLaunchKernelGGL(k_prep_targets<2>, gblk, dim3(256), 0, st, e.psi, p->tperm, p->ty,
+                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->tpsi,
                            p->blk_stat);
     else
-        hipLaunchKernelGGL(k_prep_targets<3>, gblk, dim3(256), 0, p->stream, psi, p->tperm, p->ty,
-                           p->tnu, p->tlog2nu, p->n_blocks, kappa, cs, p->trec, p->tpsi,
+        hipLaunchKernelGGL(k_prep_targets<3>, gblk, dim3(256), 0, st, e.psi, p->tperm, p->ty,
+                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->tpsi,
                            p->blk_stat);
-    hipLaunchKernelGGL(k_pre_scalars, dim3(1), dim3(256), 0, p->stream, p->blk_stat, p->n_blocks,
-                       rule, eps, p->C0 < 0 ? 0.0 : p->C0, p->nu_min, p->nu_max, p->opt.tau,
+    hipLaunchKernelGGL(k_pre_scalars, dim3(1), dim3(256), 0, st, p->blk_stat, p->n_blocks, e.rule,
+                       eps, p->C0 < 0 ? 0.0 : p->C0, p->nu_min, p->nu_max, p->opt.tau,
                        p->absJ_ref, p->log_D_prev, p->opt.delta_thr, p->dscal);
-
-    int mode = MODE_DENSE;
-    int64_t n_wi = 0, n_seg = 1, seg = 1;
     const int64_t seg_cfg = p->opt.seg_tiles;
-    if (rule == RSOT_TRUNC_DENSE) {
-        n_seg = std::max<int64_t>(1, (32768 + p->n_blocks - 1) / p->n_blocks);
+    e.seg1_cfg = p->opt.seg_blocks > 0 ? p->opt.seg_blocks : RSOT_SEG1_DEFAULT;
+    if (e.rule == RSOT_TRUNC_DENSE) {
+        e.mode = MODE_DENSE;
+        e.pw.seg1 = std::min<int64_t>(e.seg1_cfg, p->n_blocks);
+        e.pw.n_seg1 = (p->n_blocks + e.pw.seg1 - 1) / e.pw.seg1;
+        e.pw.n_items = p->n_tiles * e.pw.n_seg1;
+        int64_t n_seg = std::max<int64_t>(1, (32768 + p->n_blocks - 1) / p->n_blocks);
         if (seg_cfg > 0) n_seg = (p->n_tiles + seg_cfg - 1) / seg_cfg;
         n_seg = std::min<int64_t>(n_seg, p->n_tiles);
-        seg = (p->n_tiles + n_seg - 1) / n_seg;
-        n_seg = (p->n_tiles + seg - 1) / seg;
-        n_wi = p->n_blocks * n_seg;
+        e.seg = (p->n_tiles + n_seg - 1) / n_seg;
+        e.n_seg = (p->n_tiles + e.seg - 1) / e.seg;
+        e.n_wi = p->n_blocks * e.n_seg;
+        return RSOT_OK;
+    }
+    RSOT_TRY(ensure_cull_buffers(p));
+    e.culled = true;
+    e.mode = e.rule == RSOT_TRUNC_TILE ? MODE_LIST : MODE_MASK;
+    if (e.rule == RSOT_TRUNC_TILE) {
+        const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
+                                 std::log((double)p->n_blocks);
+        if (D == 2)
+            hipLaunchKernelGGL(k_flags_tile<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
+                               p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
+                               p->flags_rm);
+        else
+            hipLaunchKernelGGL(k_flags_tile<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
+                               p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
+                               p->flags_rm);
     } else {
-        RSOT_TRY(ensure_cull_buffers(p));
-        mode = rule == RSOT_TRUNC_TILE ? MODE_LIST : MODE_MASK;
-        if (rule == RSOT_TRUNC_TILE) {
-            const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
-                                     std::log((double)p->n_blocks);
-            if (D == 2)
-                hipLaunchKernelGGL(k_flags_tile<2>, gtile, dim3(256), 0, p->stream, p->tile_lo,
-                                   p->tile_hi, p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat,
-                                   p->blk_cnt, p->ty, p->tnu, p->tpsi, p->n_tiles, p->n_blocks,
-                                   cs, eps, ln_eta_nb, p->flags_rm);
-            else
-                hipLaunchKernelGGL(k_flags_tile<3>, gtile, dim3(256), 0, p->stream, p->tile_lo,
-                                   p->tile_hi, p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat,
-                                   p->blk_cnt, p->ty, p->tnu, p->tpsi, p->n_tiles, p->n_blocks,
-                                   cs, eps, ln_eta_nb, p->flags_rm);
-        } else {
-            hipLaunchKernelGGL(k_target_G, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0,
-                               p->stream, p->tpsi, p->tlog2nu, p->tperm, p->n_pad, kappa, p->dscal,
-                               p->tG);
-            if (D == 2)
-                hipLaunchKernelGGL(k_flags_cutoff<2>, gtile, dim3(256), 0, p->stream, p->tile_lo,
-                                   p->tile_hi, p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs,
-                                   p->dscal, p->flags_rm);
-            else
-                hipLaunchKernelGGL(k_flags_cutoff<3>, gtile, dim3(256), 0, p->stream, p->tile_lo,
-                                   p->tile_hi, p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs,
-                                   p->dscal, p->flags_rm);
-        }
-        hipLaunchKernelGGL(k_transpose_u8,
-                           dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
-                           dim3(256), 0, p->stream, p->flags_rm, p->n_tiles, p->n_blocks,
-                           p->flags_cm);
-        hipLaunchKernelGGL(k_count_rows, gtile, dim3(256), 0, p->stream, p->flags_rm, p->n_tiles,
-                           p->n_blocks, p->row_cnt);
-        hipLaunchKernelGGL(k_count_rows, gblk, dim3(256), 0, p->stream, p->flags_cm, p->n_blocks,
-                           p->n_tiles, p->col_cnt);
-        seg = seg_cfg > 0 ? seg_cfg : 64;
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->row_cnt, p->n_tiles, 0,
-                           p->row_ptr, p->dscal + SC_ROWTOT);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->col_cnt, p->n_blocks, 0,
-                           p->col_ptr, p->dscal + SC_COLTOT);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, p->col_cnt, p->n_blocks,
-                           (int)seg, p->wi_ptr, p->dscal + SC_NWI);
-        RSOT_HIP(hipGetLastError());
-        RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT,
-                                hipMemcpyDeviceToHost, p->stream));
-        RSOT_HIP(hipStreamSynchronize(p->stream));
+        hipLaunchKernelGGL(k_target_G, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0, st,
+                           p->tpsi, p->tlog2nu, p->tperm, p->n_pad, e.kappa, p->dscal, p->tG);
+        if (D == 2)
+            hipLaunchKernelGGL(k_flags_cutoff<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs, p->dscal,
+                               p->flags_rm);
+        else
+            hipLaunchKernelGGL(k_flags_cutoff<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs, p->dscal,
+                               p->flags_rm);
+    }
+    hipLaunchKernelGGL(k_transpose_u8,
+                       dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
+                       dim3(256), 0, st, p->flags_rm, p->n_tiles, p->n_blocks, p->flags_cm);
+    hipLaunchKernelGGL(k_count_rows, gtile, dim3(256), 0, st, p->flags_rm, p->n_tiles, p->n_blocks,
+                       p->row_cnt);
+    hipLaunchKernelGGL(k_count_rows, gblk, dim3(256), 0, st, p->flags_cm, p->n_blocks, p->n_tiles,
+                       p->col_cnt);
+    e.seg = seg_cfg > 0 ? seg_cfg : 64;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->row_cnt, p->n_tiles, 0, p->row_ptr,
+                       p->dscal + SC_ROWTOT);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->col_cnt, p->n_blocks, 0, p->col_ptr,
+                       p->dscal + SC_COLTOT);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->col_cnt, p->n_blocks, (int)e.seg,
+                       p->wi_ptr, p->dscal + SC_NWI);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->row_cnt, p->n_tiles,
+                       (int)e.seg1_cfg, p->wi1_ptr, p->dscal + SC_NWI1);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                            st));
+    return RSOT_OK;
+}
+
+// after plan_begin's stream work completed (only needed when culled)
+static rsot_status plan_lists(EvalPlan &e) {
+    rsot_problem *p = e.p;
+    const hipStream_t st = e.st;
+    const bool grad = e.grad != nullptr;
+    if (e.culled) {
         if (p->hscal[SC_NONFINITE] != 0.0) return RSOT_ERR_NONFINITE;
         const int64_t rtot = (int64_t)p->hscal[SC_ROWTOT];
         const int64_t ctot = (int64_t)p->hscal[SC_COLTOT];
-        n_wi = (int64_t)p->hscal[SC_NWI];
+        e.n_wi = (int64_t)p->hscal[SC_NWI];
         size_t cap_r = p->list_cap, cap_c = p->list_cap;
         RSOT_TRY(grow(p, &p->row_idx, &cap_r, (size_t)std::max<int64_t>(rtot, 1)));
         RSOT_TRY(grow(p, &p->col_idx, &cap_c, (size_t)std::max<int64_t>(ctot, 1)));
         p->list_cap = std::min(cap_r, cap_c);
         size_t cap_b = p->wi_cap, cap_rg = p->wi_cap;
-        RSOT_TRY(grow(p, &p->wi_block, &cap_b, (size_t)std::max<int64_t>(n_wi, 1)));
-        RSOT_TRY(grow(p, &p->wi_range, &cap_rg, (size_t)std::max<int64_t>(2 * n_wi, 2)));
+        RSOT_TRY(grow(p, &p->wi_block, &cap_b, (size_t)std::max<int64_t>(e.n_wi, 1)));
+        RSOT_TRY(grow(p, &p->wi_range, &cap_rg, (size_t)std::max<int64_t>(2 * e.n_wi, 2)));
         p->wi_cap = std::min(cap_b, cap_rg / 2);
-        hipLaunchKernelGGL(k_fill_rows, gtile, dim3(256), 0, p->stream, p->flags_rm, p->n_tiles,
+        e.pw.n_items = (int64_t)p->hscal[SC_NWI1];
+        e.pw.seg1 = e.seg1_cfg;
+        size_t cap_t = p->wi1_cap, cap_tr = p->wi1_cap;
+        RSOT_TRY(grow(p, &p->wi1_tile, &cap_t, (size_t)std::max<int64_t>(e.pw.n_items, 1)));
+        RSOT_TRY(grow(p, &p->wi1_range, &cap_tr, (size_t)std::max<int64_t>(2 * e.pw.n_items, 2)));
+        p->wi1_cap = std::min(cap_t, cap_tr / 2);
+        const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
+        const dim3 gtile((unsigned)((p->n_tiles + 3) / 4));
+        hipLaunchKernelGGL(k_fill_rows, gtile, dim3(256), 0, st, p->flags_rm, p->n_tiles,
                            p->n_blocks, p->row_ptr, p->row_idx);
-        hipLaunchKernelGGL(k_fill_rows, gblk, dim3(256), 0, p->stream, p->flags_cm, p->n_blocks,
+        hipLaunchKernelGGL(k_fill_rows, gblk, dim3(256), 0, st, p->flags_cm, p->n_blocks,
                            p->n_tiles, p->col_ptr, p->col_idx);
         hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((p->n_blocks + 255) / 256)), dim3(256), 0,
-                           p->stream, p->col_ptr, p->wi_ptr, p->n_blocks, (int)seg, p->wi_block,
+                           st, p->col_ptr, p->wi_ptr, p->n_blocks, (int)e.seg, p->wi_block,
                            p->wi_range);
+        hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((p->n_tiles + 255) / 256)), dim3(256), 0,
+                           st, p->row_ptr, p->wi1_ptr, p->n_tiles, (int)e.seg1_cfg, p->wi1_tile,
+                           p->wi1_range);
     }
-    if (grad) RSOT_TRY(grow(p, &p->gpart, &p->gpart_cap, (size_t)std::max<int64_t>(n_wi, 1) * 64));
+    size_t c1 = p->part1_cap, c2 = p->part1_cap;
+    RSOT_TRY(grow(p, &p->part1, &c1, (size_t)std::max<int64_t>(e.pw.n_items, 1) * 64));
+    RSOT_TRY(grow(p, &p->part1k, &c2, (size_t)std::max<int64_t>(e.pw.n_items, 1) * 64));
+    p->part1_cap = std::min(c1, c2);
+    if (grad) RSOT_TRY(grow(p, &p->gpart, &p->gpart_cap, (size_t)std::max<int64_t>(e.n_wi, 1) * 64));
+    return RSOT_OK;
+}
 
-    const double kcs = kappa * cs;
-    RSOT_HIP(hipEventRecord(p->ev_p1, p->stream));
-    if (D == 2) {
-        if (f64) launch_passes<2, true>(p, mode, grad, kcs, n_wi, n_seg, seg);
-        else launch_passes<2, false>(p, mode, grad, kcs, n_wi, n_seg, seg);
+static void plan_passes(EvalPlan &e) {
+    rsot_problem *p = e.p;
+    const hipStream_t keep = p->stream;
+    p->stream = e.st;
+    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
+    const bool grad = e.grad != nullptr;
+    (void)hipEventRecord(p->ev_p1, e.st);
+    if (p->dim == 2) {
+        if (f64) launch_passes<2, true>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
+        else launch_passes<2, false>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
     } else {
-        if (f64) launch_passes<3, true>(p, mode, grad, kcs, n_wi, n_seg, seg);
-        else launch_passes<3, false>(p, mode, grad, kcs, n_wi, n_seg, seg);
+        if (f64) launch_passes<3, true>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
+        else launch_passes<3, false>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
     }
-    RSOT_HIP(hipEventRecord(p->ev_p2, p->stream));
+    (void)hipEventRecord(p->ev_p2, e.st);
+    p->stream = keep;
+}
+
+static rsot_status plan_finish(EvalPlan &e) {
+    rsot_problem *p = e.p;
+    const hipStream_t st = e.st;
+    const bool grad = e.grad != nullptr;
+    const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
     if (grad)
-        hipLaunchKernelGGL(k_grad_reduce, gblk, dim3(256), 0, p->stream, p->gpart,
-                           mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi_ptr, n_seg, p->tnu,
-                           p->tperm, p->n_blocks, p->dscal, grad_out, p->blk_gpart);
-    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, p->stream, p->tile_part, p->n_tiles,
-                       eps, p->dscal);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, p->stream, p->tile_part, p->n_tiles,
+        hipLaunchKernelGGL(k_grad_reduce, gblk, dim3(256), 0, st, p->gpart,
+                           e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi_ptr, e.n_seg,
+                           p->tnu, p->tperm, p->n_blocks, p->dscal, e.grad, p->blk_gpart);
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, st, p->tile_part, p->n_tiles, e.eps,
+                       p->dscal);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, p->tile_part, p->n_tiles,
                        p->blk_gpart, p->n_blocks, grad ? 1 : 0, p->dscal);
     RSOT_HIP(hipGetLastError());
-    RSOT_HIP(hipEventRecord(p->ev1, p->stream));
+    RSOT_HIP(hipEventRecord(p->ev1, st));
     RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
-                            p->stream));
-    RSOT_HIP(hipStreamSynchronize(p->stream));
+                            st));
+    return RSOT_OK;
+}
+
+static rsot_status plan_result(EvalPlan &e, bool timed_passes, double *J_out,
+                               rsot_eval_info *info) {
+    rsot_problem *p = e.p;
+    const bool grad = e.grad != nullptr;
     const double *h = p->hscal;
     if (h[SC_NONFINITE] != 0.0) return RSOT_ERR_NONFINITE;
-    float ms = 0.0f, ms_pre = 0.0f, ms_passes = 0.0f;
+    float ms = 0.0f, ms_pre = 0.0f, ms_passes = 0.0f, ms_p1 = 0.0f, ms_p2 = 0.0f;
     RSOT_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    RSOT_HIP(hipEventElapsedTime(&ms_pre, p->ev0, p->ev_p1));
-    RSOT_HIP(hipEventElapsedTime(&ms_passes, p->ev_p1, p->ev_p2));
-    float ms_p1 = 0.0f, ms_p2 = 0.0f;
-    RSOT_HIP(hipEventElapsedTime(&ms_p1, p->ev_p1, p->ev_mid));
-    RSOT_HIP(hipEventElapsedTime(&ms_p2, p->ev_mid, p->ev_p2));
+    if (timed_passes) {
+        RSOT_HIP(hipEventElapsedTime(&ms_pre, p->ev0, p->ev_p1));
+        RSOT_HIP(hipEventElapsedTime(&ms_passes, p->ev_p1, p->ev_p2));
+        RSOT_HIP(hipEventElapsedTime(&ms_p1, p->ev_p1, p->ev_mid));
+        RSOT_HIP(hipEventElapsedTime(&ms_p2, p->ev_mid, p->ev_p2));
+    }
     *J_out = h[SC_J];
-    if (rule == RSOT_TRUNC_INT || p->opt.truncation == RSOT_TRUNC_INT) {
+    if (e.rule == RSOT_TRUNC_INT || p->opt.truncation == RSOT_TRUNC_INT) {
         p->log_D_prev = h[SC_LOGD];
         p->have_D = 1;
     }
-    if (dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
+    if (e.dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
     p->last_eval_valid = 1;
     if (info) {
+        const int rule = e.rule;
         info->total_pairs = p->nq * p->n;
         info->kept_pairs = (int64_t)h[SC_KEPT];
         info->n_empty_qp = (int64_t)h[SC_EMPTY];
@@ -879,9 +1214,26 @@ rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi, doubl
         info->passes_ms = ms_passes;
         info->pass1_ms = ms_p1;
         info->pass2_ms = grad ? ms_p2 : 0.0;
-        info->dense_fallback = dense_fallback;
+        info->dense_fallback = e.dense_fallback;
     }
     return RSOT_OK;
+}
+
+rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi, double *J_out,
+                           double *grad_out, rsot_eval_info *info) {
+    EvalPlan e;
+    e.p = p;
+    e.st = p->stream;
+    e.eps = eps;
+    e.psi = psi;
+    e.grad = grad_out;
+    RSOT_TRY(plan_begin(e));
+    if (e.culled) RSOT_HIP(hipStreamSynchronize(e.st));
+    RSOT_TRY(plan_lists(e));
+    plan_passes(e);
+    RSOT_TRY(plan_finish(e));
+    RSOT_HIP(hipStreamSynchronize(e.st));
+    return plan_result(e, true, J_out, info);
 }
 
 extern "C" rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi,
@@ -889,6 +1241,153 @@ extern "C" rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double 
     if (!p || !psi || !J_out) return RSOT_ERR_INVALID_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
     return rsot_eval_impl(p, eps, psi, J_out, grad_out, info);
+}
+
+// Batched evaluation: every problem's preparation and culling, one host
+// synchronisation, one persistent launch per pass for the problems that run
+// mixed precision with the dense or tile rule (others run their own passes in
+// the same stream), one final synchronisation. Work goes on ps[0]'s stream.
+extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, const double *eps,
+                                              const double *const *psi, double *J_out,
+                                              double *const *grad_out, rsot_eval_info *infos,
+                                              double *batch_ms) {
+    if (!ps || n < 1 || !eps || !psi || !J_out) return RSOT_ERR_INVALID_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!ps[i] || !psi[i] || !(eps[i] > 0.0) || !std::isfinite(eps[i]))
+            return RSOT_ERR_INVALID_ARG;
+    rsot_problem *p0 = ps[0];
+    const hipStream_t st = p0->stream;
+    std::vector<EvalPlan> plans((size_t)n);
+    RSOT_HIP(hipEventRecord(p0->ev_b0, st));
+    bool any_cull = false;
+    for (int i = 0; i < n; ++i) {
+        EvalPlan &e = plans[(size_t)i];
+        e.p = ps[i];
+        e.st = st;
+        e.eps = eps[i];
+        e.psi = psi[i];
+        e.grad = grad_out ? grad_out[i] : nullptr;
+        RSOT_TRY(plan_begin(e));
+        any_cull = any_cull || e.culled;
+    }
+    if (any_cull) RSOT_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) RSOT_TRY(plan_lists(plans[(size_t)i]));
+
+    // problems for the persistent kernels, in decreasing order of work
+    std::vector<BatchDesc> descs;
+    std::vector<int> members;
+    std::vector<double> cost;
+    for (int i = 0; i < n; ++i) {
+        EvalPlan &e = plans[(size_t)i];
+        rsot_problem *p = e.p;
+        const bool batchable = p->opt.precision == RSOT_PREC_MIXED &&
+                               (e.mode == MODE_DENSE || e.mode == MODE_LIST);
+        if (!batchable) {
+            plan_passes(e);
+            continue;
+        }
+        BatchDesc d{};
+        d.dim = p->dim;
+        d.mode = e.mode;
+        d.n_tiles = p->n_tiles;
+        d.n_blocks = p->n_blocks;
+        d.qp = p->qp;
+        d.qH = p->qH;
+        d.trec = p->trec;
+        d.tG = p->tG;
+        d.blk_cnt = p->blk_cnt;
+        d.row_idx = p->row_idx;
+        d.wi1_tile = p->wi1_tile;
+        d.wi1_range = p->wi1_range;
+        d.n_items1 = e.pw.n_items;
+        d.seg1 = e.pw.seg1;
+        d.n_seg1 = e.pw.n_seg1;
+        d.kcs = e.kcs;
+        d.part1 = p->part1;
+        d.part1k = p->part1k;
+        d.col_idx = p->col_idx;
+        d.wi_block = p->wi_block;
+        d.wi_range = p->wi_range;
+        d.n_wi = e.grad ? e.n_wi : 0;
+        d.n_seg = e.n_seg;
+        d.seg = e.seg;
+        d.gpart = p->gpart;
+        descs.push_back(d);
+        members.push_back(i);
+        cost.push_back((double)(e.culled ? p->hscal[SC_ROWTOT] : (double)p->n_tiles * p->n_blocks));
+    }
+    const int nb = (int)descs.size();
+    if (nb > 0) {
+        std::vector<int32_t> order((size_t)nb);
+        for (int k = 0; k < nb; ++k) order[(size_t)k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return cost[(size_t)a] > cost[(size_t)b]; });
+        std::vector<int64_t> begin1((size_t)nb + 1, 0), begin2((size_t)nb + 1, 0);
+        for (int k = 0; k < nb; ++k) {
+            const BatchDesc &d = descs[(size_t)order[(size_t)k]];
+            begin1[(size_t)k + 1] = begin1[(size_t)k] + d.n_items1;
+            begin2[(size_t)k + 1] = begin2[(size_t)k] + d.n_wi;
+        }
+        // scratch of the batch lives with the first problem
+        const size_t bytes = sizeof(BatchDesc) * nb + sizeof(int32_t) * nb +
+                             2 * sizeof(int64_t) * (nb + 1) + 2 * sizeof(unsigned long long) + 256 * 4;
+        size_t cap = p0->batch_cap;
+        RSOT_TRY(grow(p0, &p0->batch_buf, &cap, bytes));
+        p0->batch_cap = cap;
+        char *base = p0->batch_buf;
+        BatchDesc *d_desc = (BatchDesc *)base;
+        size_t off = (sizeof(BatchDesc) * nb + 255) & ~size_t(255);
+        int32_t *d_order = (int32_t *)(base + off);
+        off += (sizeof(int32_t) * nb + 255) & ~size_t(255);
+        int64_t *d_b1 = (int64_t *)(base + off);
+        off += (sizeof(int64_t) * (nb + 1) + 255) & ~size_t(255);
+        int64_t *d_b2 = (int64_t *)(base + off);
+        off += (sizeof(int64_t) * (nb + 1) + 255) & ~size_t(255);
+        unsigned long long *d_cnt = (unsigned long long *)(base + off);
+        // host staging (pinned) for the descriptors
+        std::vector<char> stage(off);
+        std::memcpy(stage.data(), descs.data(), sizeof(BatchDesc) * nb);
+        std::memcpy(stage.data() + ((char *)d_order - base), order.data(), sizeof(int32_t) * nb);
+        std::memcpy(stage.data() + ((char *)d_b1 - base), begin1.data(), sizeof(int64_t) * (nb + 1));
+        std::memcpy(stage.data() + ((char *)d_b2 - base), begin2.data(), sizeof(int64_t) * (nb + 1));
+        RSOT_HIP(hipMemcpyAsync(base, stage.data(), off, hipMemcpyHostToDevice, st));
+        for (int k = 0; k < nb; ++k) (void)hipEventRecord(ps[members[(size_t)k]]->ev_p1, st);
+        const unsigned grid = 256u * 8u;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, d_cnt);
+        hipLaunchKernelGGL(k_pass1_batched, dim3(grid), dim3(256), 0, st, d_desc, d_order, d_b1, nb,
+                           d_cnt);
+        for (int k = 0; k < nb; ++k) {
+            EvalPlan &e = plans[(size_t)members[(size_t)k]];
+            rsot_problem *p = e.p;
+            hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256),
+                               0, st, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
+                               e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr,
+                               e.pw.n_seg1, p->n_tiles, e.kcs, 0, p->qH, p->qlse, p->tile_part);
+        }
+        if (begin2[(size_t)nb] > 0) {
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, d_cnt + 1);
+            hipLaunchKernelGGL(k_pass2_batched, dim3(grid), dim3(256), 0, st, d_desc, d_order, d_b2,
+                               nb, d_cnt + 1);
+        }
+        RSOT_HIP(hipGetLastError());
+        // the staging buffer must outlive the asynchronous copy
+        RSOT_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < nb; ++k) (void)hipEventRecord(ps[members[(size_t)k]]->ev_p2, st);
+    }
+    for (int i = 0; i < n; ++i) RSOT_TRY(plan_finish(plans[(size_t)i]));
+    RSOT_HIP(hipEventRecord(p0->ev_b1, st));
+    RSOT_HIP(hipStreamSynchronize(st));
+    rsot_status status = RSOT_OK;
+    for (int i = 0; i < n; ++i) {
+        rsot_status s = plan_result(plans[(size_t)i], false, &J_out[i], infos ? &infos[i] : nullptr);
+        if (s != RSOT_OK && status == RSOT_OK) status = s;
+    }
+    if (batch_ms) {
+        float ms = 0.0f;
+        RSOT_HIP(hipEventElapsedTime(&ms, p0->ev_b0, p0->ev_b1));
+        *batch_ms = ms;
+    }
+    return status;
 }
 
 __global__ void k_unpermute_lse(const double *__restrict__ qlse, const int32_t *__restrict__ qperm,
@@ -906,4 +1405,300 @@ extern "C" rsot_status rsot_get_lse(rsot_problem *p, double *L_out) {
     RSOT_HIP(hipGetLastError());
     RSOT_HIP(hipStreamSynchronize(p->stream));
     return RSOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// softmax potential refinement (Eq. softmax_refinement_formula)
+//   psi_k = -eps ln sum_q mu_q exp(-L_q) exp(-c(x_q, y_k)/eps)
+// with L_q the log-sum-exp of the coarse targets at the current points. In
+// base 2 the summand is 2^(B_k + S_q + x_q.Y_k) with B_k = -kappa cs |y_k|^2,
+// Y_k = 2 kappa cs y_k and S_q = log2 mu_q - Lt_q from the objective pass, so
+// the gradient pass's loop applies with fine-target records; the terms span
+// far more than FP32's range at small eps, so the sum is a log-sum-exp.
+// ---------------------------------------------------------------------------
+
+// fine-target records (psi = 0, nu = 1) and block boxes
+__global__ __launch_bounds__(256) void k_refine_targets(
+    const double *__restrict__ yf, const int32_t *__restrict__ order, int64_t nf, int64_t nf_pad,
+    int dim, double s0, double s1, double s2, double kappa, double cs,
+    double4 *__restrict__ rec, int32_t *__restrict__ fperm, double *__restrict__ fy,
+    double *__restrict__ blo, double *__restrict__ bhi, int32_t *__restrict__ bcnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = j / 64;
+    if (b * 64 >= nf_pad) return;
+    const bool real = j < nf;
+    const int32_t src = order[real ? j : nf - 1];
+    const double y0 = yf[(int64_t)src * dim + 0] - s0;
+    const double y1 = yf[(int64_t)src * dim + 1] - s1;
+    const double y2 = dim == 3 ? yf[(int64_t)src * dim + 2] - s2 : 0.0;
+    double4 r;
+    r.x = 2.0 * kappa * cs * y0;
+    r.y = 2.0 * kappa * cs * y1;
+    r.z = 2.0 * kappa * cs * y2;
+    r.w = real ? -kappa * cs * (y0 * y0 + y1 * y1 + y2 * y2) : -INFINITY;
+    rec[j] = r;
+    fperm[j] = real ? src : -1;
+    fy[j * 3 + 0] = y0;
+    fy[j * 3 + 1] = y1;
+    fy[j * 3 + 2] = y2;
+    const double v[3] = {y0, y1, y2};
+    for (int k = 0; k < 3; ++k) {
+        const double a = wave_min(v[k]), c = wave_max(v[k]);
+        if (lane == 0) {
+            blo[b * 3 + k] = a;
+            bhi[b * 3 + k] = c;
+        }
+    }
+    const double n = wave_sum(real ? 1.0 : 0.0);
+    if (lane == 0) bcnt[b] = (int32_t)n;
+}
+
+// Culling for the refinement, one wavefront per fine block F:
+//   ln U_TF = ln D_T - cs dmin^2(T,F)/eps bounds the tile's contribution to
+//   every target of F (D_T = sum_{q in T} mu_q e^{-L_q});
+//   T* = argmax_T ln U_TF; L_F = min_{k in F} max_{q in T*} (ln mu_q - L_q -
+//   c(x_q,y_k)/eps) bounds every target's kept sum from below;
+//   keep (T,F) iff T = T* or ln U_TF > L_F + ln(eta / n_tiles).
+// Neglected mass <= eta * kept mass, so psi_k moves by at most eps ln(1+eta).
+template <int D>
+__global__ __launch_bounds__(256) void k_flags_refine(
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ tile_part, const double4 *__restrict__ qp,
+    const double *__restrict__ qlog2mu, const double *__restrict__ qlse,
+    const double *__restrict__ fblo, const double *__restrict__ fbhi,
+    const int32_t *__restrict__ fbcnt, const double *__restrict__ fy, int64_t n_tiles,
+    int64_t n_fblocks, double cs, double eps, double ln_eta_nt, uint8_t *__restrict__ flags_cm) {
+    const int lane = threadIdx.x & 63;
+    const int64_t F = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (F >= n_fblocks) return;
+    double fl[3], fh[3];
+    for (int k = 0; k < 3; ++k) {
+        fl[k] = fblo[F * 3 + k];
+        fh[k] = fbhi[F * 3 + k];
+    }
+    double best = -INFINITY;
+    int64_t bt = INT64_MAX;
+    for (int64_t t = lane; t < n_tiles; t += 64) {
+        double dmin2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double g = box_gap(tile_lo[t * 3 + k], tile_hi[t * 3 + k], fl[k], fh[k]);
+            dmin2 += g * g;
+        }
+        const double lnU = tile_part[t * 4 + 1] - cs * dmin2 / eps;
+        if (lnU > best) {
+            best = lnU;
+            bt = t;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int64_t oi = __shfl_xor(bt, o, 64);
+        if (ob > best || (ob == best && oi < bt)) {
+            best = ob;
+            bt = oi;
+        }
+    }
+    double lb = INFINITY;
+    if (bt != INT64_MAX && lane < fbcnt[F]) {
+        const int64_t k = F * 64 + lane;
+        const double y0 = fy[k * 3], y1 = fy[k * 3 + 1], y2 = fy[k * 3 + 2];
+        double mx = -INFINITY;
+        for (int i = 0; i < 64; ++i) {
+            const int64_t q = bt * 64 + i;
+            const double lq = qlse[q];
+            const double lm = qlog2mu[q];
+            if (!(lq > -INFINITY) || !(lm > -INFINITY)) continue;
+            const double4 r = qp[q];
+            const double e0 = r.x - y0, e1 = r.y - y1, e2 = D == 3 ? r.z - y2 : 0.0;
+            const double v = lm * RSOT_LN2 - lq - cs * (e0 * e0 + e1 * e1 + e2 * e2) / eps;
+            mx = fmax(mx, v);
+        }
+        lb = mx;
+    }
+    const double thr = wave_min(lb) + ln_eta_nt;
+    for (int64_t t = lane; t < n_tiles; t += 64) {
+        double dmin2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            const double g = box_gap(tile_lo[t * 3 + k], tile_hi[t * 3 + k], fl[k], fh[k]);
+            dmin2 += g * g;
+        }
+        const double lnU = tile_part[t * 4 + 1] - cs * dmin2 / eps;
+        flags_cm[F * n_tiles + t] = (t == bt || lnU > thr) ? PAIR_FULL : PAIR_SKIP;
+    }
+}
+
+// one 64-point tile into a lane's running (m, s): s = sum 2^(v - m), m an
+// integer that only grows (the objective pass's scheme, transposed)
+template <int D, bool F64>
+__device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y0, double Y1,
+                                         double Y2, double B, double &m, double &s) {
+    for (int i0 = 0; i0 < 64; i0 += CH) {
+        double tv[CH];
+        double cm = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const double4 r = Q[i0 + k];
+            double v = B + r.w;
+            v = fma(r.x, Y0, v);
+            v = fma(r.y, Y1, v);
+            if (D == 3) v = fma(r.z, Y2, v);
+            tv[k] = v;
+            cm = fmax(cm, v);
+        }
+        if (cm > m) {
+            const double mn = ceil(cm);
+            s = ldexp(s, (int)fmax(m - mn, -2000.0));
+            m = mn;
+        }
+        if (F64) {
+            double cs = 0.0;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) cs += exp2(tv[k] - m);
+            s += cs;
+        } else {
+            float cs = 0.0f;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
+            s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+        }
+    }
+}
+
+// per work item and lane: log2 of the partial sum (or -inf)
+template <int D, bool F64>
+__global__ __launch_bounds__(256) void k_pass2_lse(
+    const double4 *__restrict__ qp, const double4 *__restrict__ frec,
+    const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
+    const uint32_t *__restrict__ col_idx, int64_t n_wi, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= n_wi) return;
+    const int64_t F = wi_block[w];
+    const double4 rec = frec[F * 64 + lane];
+    double m = -1e300, s = 0.0;
+    for (int64_t e = wi_range[2 * w]; e < wi_range[2 * w + 1]; ++e) {
+        const int64_t t = col_idx[e] & ~RSOT_PARTIAL_BIT;
+        lse_tile<D, F64>(qp + t * 64, rec.x, rec.y, rec.z, rec.w, m, s);
+    }
+    out[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
+}
+
+__global__ __launch_bounds__(256) void k_refine_reduce(const double *__restrict__ part,
+                                                       const int64_t *__restrict__ wi_ptr,
+                                                       const int32_t *__restrict__ fperm,
+                                                       int64_t n_fblocks, double eps,
+                                                       double *__restrict__ psi_out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t F = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (F >= n_fblocks) return;
+    const int64_t w0 = wi_ptr[F], w1 = wi_ptr[F + 1];
+    double mx = -INFINITY;
+    for (int64_t w = w0; w < w1; ++w) mx = fmax(mx, part[w * 64 + lane]);
+    double s = 0.0;
+    if (mx > -INFINITY)
+        for (int64_t w = w0; w < w1; ++w) s += exp2(part[w * 64 + lane] - mx);
+    const int32_t dst = fperm[F * 64 + lane];
+    if (dst >= 0) psi_out[dst] = -eps * RSOT_LN2 * (mx + log2(s));
+}
+
+rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse,
+                             int64_t nf, const double *yf, double eta, double *psi_out) {
+    // 1. coarse log-sum-exp L_q at the current points (objective pass only)
+    double J = 0.0;
+    rsot_eval_info info{};
+    RSOT_TRY(rsot_eval_impl(p, eps, psi_coarse, &J, nullptr, &info));
+    // 2. fine targets: Morton order, records, block boxes
+    int32_t *order = nullptr;
+    RSOT_TRY(rsot_morton_order(p, yf, nf, &order));
+    const int64_t nf_pad = (nf + 63) / 64 * 64, nfb = nf_pad / 64;
+    const double kappa = RSOT_LOG2E / eps, cs = p->opt.cost_scale;
+    std::vector<void *> tmp;
+    auto A = [&](size_t bytes) -> void * {
+        void *q = nullptr;
+        if (rsot_dev_alloc(p, &q, bytes) != RSOT_OK) return nullptr;
+        tmp.push_back(q);
+        return q;
+    };
+    auto cleanup = [&]() {
+        for (void *q : tmp) rsot_dev_free(p, q);
+        rsot_dev_free(p, order);
+    };
+    double4 *frec = (double4 *)A(sizeof(double4) * nf_pad);
+    int32_t *fperm = (int32_t *)A(sizeof(int32_t) * nf_pad);
+    double *fy = (double *)A(sizeof(double) * nf_pad * 3);
+    double *fblo = (double *)A(sizeof(double) * nfb * 3);
+    double *fbhi = (double *)A(sizeof(double) * nfb * 3);
+    int32_t *fbcnt = (int32_t *)A(sizeof(int32_t) * nfb);
+    uint8_t *flags = (uint8_t *)A((size_t)nfb * (size_t)p->n_tiles);
+    int32_t *cnt = (int32_t *)A(sizeof(int32_t) * nfb);
+    int64_t *cptr = (int64_t *)A(sizeof(int64_t) * (nfb + 1));
+    int64_t *wptr = (int64_t *)A(sizeof(int64_t) * (nfb + 1));
+    if (!frec || !fperm || !fy || !fblo || !fbhi || !fbcnt || !flags || !cnt || !cptr || !wptr) {
+        cleanup();
+        return RSOT_ERR_OOM;
+    }
+    hipLaunchKernelGGL(k_refine_targets, dim3((unsigned)(nf_pad / 64)), dim3(64), 0, p->stream,
+                       yf, order, nf, nf_pad, p->dim, p->shift[0], p->shift[1], p->shift[2], kappa,
+                       cs, frec, fperm, fy, fblo, fbhi, fbcnt);
+    // 3. culling and lists
+    const double ln_eta_nt = std::log(eta) - std::log((double)p->n_tiles);
+    const dim3 gfb((unsigned)((nfb + 3) / 4));
+    if (p->dim == 2)
+        hipLaunchKernelGGL(k_flags_refine<2>, gfb, dim3(256), 0, p->stream, p->tile_lo,
+                           p->tile_hi, p->tile_part, p->qp, p->qlog2mu, p->qlse, fblo, fbhi,
+                           fbcnt, fy, p->n_tiles, nfb, cs, eps, ln_eta_nt, flags);
+    else
+        hipLaunchKernelGGL(k_flags_refine<3>, gfb, dim3(256), 0, p->stream, p->tile_lo,
+                           p->tile_hi, p->tile_part, p->qp, p->qlog2mu, p->qlse, fblo, fbhi,
+                           fbcnt, fy, p->n_tiles, nfb, cs, eps, ln_eta_nt, flags);
+    hipLaunchKernelGGL(k_count_rows, gfb, dim3(256), 0, p->stream, flags, nfb, p->n_tiles, cnt);
+    const int seg = 64;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cnt, nfb, 0, cptr,
+                       p->dscal + SC_COLTOT);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cnt, nfb, seg, wptr,
+                       p->dscal + SC_NWI);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                            p->stream));
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    const int64_t ctot = (int64_t)p->hscal[SC_COLTOT], n_wi = (int64_t)p->hscal[SC_NWI];
+    uint32_t *cidx = (uint32_t *)A(sizeof(uint32_t) * std::max<int64_t>(ctot, 1));
+    int32_t *wblk = (int32_t *)A(sizeof(int32_t) * std::max<int64_t>(n_wi, 1));
+    int64_t *wrng = (int64_t *)A(sizeof(int64_t) * 2 * std::max<int64_t>(n_wi, 1));
+    double *part = (double *)A(sizeof(double) * 64 * std::max<int64_t>(n_wi, 1));
+    if (!cidx || !wblk || !wrng || !part) {
+        cleanup();
+        return RSOT_ERR_OOM;
+    }
+    hipLaunchKernelGGL(k_fill_rows, gfb, dim3(256), 0, p->stream, flags, nfb, p->n_tiles, cptr,
+                       cidx);
+    hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((nfb + 255) / 256)), dim3(256), 0, p->stream,
+                       cptr, wptr, nfb, seg, wblk, wrng);
+    // 4. log-sum-exp gradient-pass loop and merge
+    const dim3 gw((unsigned)((n_wi + 3) / 4));
+    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
+    if (p->dim == 2) {
+        if (f64) hipLaunchKernelGGL((k_pass2_lse<2, true>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+        else hipLaunchKernelGGL((k_pass2_lse<2, false>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_pass2_lse<3, true>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+        else hipLaunchKernelGGL((k_pass2_lse<3, false>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+    }
+    hipLaunchKernelGGL(k_refine_reduce, gfb, dim3(256), 0, p->stream, part, wptr, fperm, nfb, eps,
+                       psi_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    p->last_refine_pairs = ctot * 64 * 64;
+    cleanup();
+    return RSOT_OK;
+}
+
+extern "C" rsot_status rsot_softmax_refine(rsot_problem *p, double eps, const double *psi_coarse,
+                                           int64_t n_fine, const double *y_fine,
+                                           double *psi_fine_out) {
+    if (!p || !psi_coarse || !y_fine || !psi_fine_out || n_fine <= 0) return RSOT_ERR_INVALID_ARG;
+    if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
+    return rsot_refine_impl(p, eps, psi_coarse, n_fine, y_fine, 1e-12, psi_fine_out);
 }

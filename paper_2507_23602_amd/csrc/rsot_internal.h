@@ -90,6 +90,15 @@ struct rsot_problem {
     int64_t *wi_ptr = nullptr;   // [n_blocks+1] first work item of each block
     size_t wi_cap = 0;
 
+    // objective pass work items (tile, segment of its block list) and partials
+    int32_t *wi1_tile = nullptr;
+    int64_t *wi1_range = nullptr;
+    int64_t *wi1_ptr = nullptr;  // [n_tiles+1]
+    size_t wi1_cap = 0;
+    double *part1 = nullptr;     // [items*64] partial log2-sum-exp
+    double *part1k = nullptr;    // [items*64] kept pairs
+    size_t part1_cap = 0;
+
     // culling (truncated rules)
     uint8_t *flags_rm = nullptr; // [n_tiles*n_blocks]
     uint8_t *flags_cm = nullptr; // [n_blocks*n_tiles]
@@ -108,7 +117,11 @@ struct rsot_problem {
     double log_D_prev = 0.0;     // ln D of the previous evaluation (INT rule)
     int have_D = 0;
     int last_eval_valid = 0;
+    int64_t last_refine_pairs = 0;   // (tile, fine block) pairs x 64 x 64 of the last refinement
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
+    hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // batched call
+    char *batch_buf = nullptr;                      // batched call: descriptors, queues
+    size_t batch_cap = 0;
 };
 
 // ---- helpers --------------------------------------------------------------
@@ -127,10 +140,16 @@ void rsot_dev_free(rsot_problem *p, void *ptr);
         if (s_ != RSOT_OK) return s_;                                     \
     } while (0)
 
+// Morton order of n device points (problem's dim); caller frees *order_out
+rsot_status rsot_morton_order(rsot_problem *p, const double *x, int64_t n, int32_t **order_out);
+
 // kernels launched from the evaluation driver
 rsot_status rsot_compute_covering_cost(rsot_problem *p);
 rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi_dev, double *J_out,
                            double *grad_dev, rsot_eval_info *info);
+
+rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse, int64_t nf,
+                             const double *yf, double eta, double *psi_out);
 
 // device scalar slots
 enum {
@@ -150,5 +169,6 @@ enum {
     SC_ROWTOT,       // total row entries (culling)
     SC_COLTOT,
     SC_NWI,          // work items of the gradient pass
+    SC_NWI1,         // work items of the objective pass
     SC_COUNT
 };

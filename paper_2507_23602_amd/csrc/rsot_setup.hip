@@ -146,6 +146,11 @@ __global__ __launch_bounds__(64) void k_point_stats_final(const PointStats *__re
     *out = r;
 }
 
+__global__ void k_fill_value(double *__restrict__ v, int64_t n, double val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = val;
+}
+
 __device__ inline uint32_t spread2(uint32_t v) {  // 16 bits -> even positions
     v &= 0xffffu;
     v = (v | (v << 8)) & 0x00ff00ffu;
@@ -496,7 +501,33 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_HIP(hipEventCreate(&p->ev_p1));
     RSOT_HIP(hipEventCreate(&p->ev_mid));
     RSOT_HIP(hipEventCreate(&p->ev_p2));
+    RSOT_HIP(hipEventCreate(&p->ev_b0));
+    RSOT_HIP(hipEventCreate(&p->ev_b1));
     return RSOT_OK;
+}
+
+// Morton order of n device points (dim of the problem) over their own box;
+// *order_out (device, n int32) is allocated here and owned by the caller.
+rsot_status rsot_morton_order(rsot_problem *p, const double *x, int64_t n, int32_t **order_out) {
+    const int nwg = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    PointStats *part = nullptr, *fin = nullptr;
+    RSOT_TRY(dalloc(p, &part, nwg));
+    RSOT_TRY(dalloc(p, &fin, 1));
+    double *ones = nullptr;
+    RSOT_TRY(dalloc(p, &ones, n));
+    hipLaunchKernelGGL(k_fill_value, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p->stream,
+                       ones, n, 1.0);
+    hipLaunchKernelGGL(k_point_stats, dim3(nwg), dim3(256), 0, p->stream, x, ones, n, p->dim, 0,
+                       part);
+    hipLaunchKernelGGL(k_point_stats_final, dim3(1), dim3(64), 0, p->stream, part, nwg, fin);
+    PointStats st;
+    RSOT_HIP(hipMemcpyAsync(&st, fin, sizeof(PointStats), hipMemcpyDeviceToHost, p->stream));
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    rsot_dev_free(p, part);
+    rsot_dev_free(p, fin);
+    rsot_dev_free(p, ones);
+    if (st.nonfinite > 0) return RSOT_ERR_NONFINITE;
+    return sort_points(p, x, n, st, order_out);
 }
 
 rsot_status rsot_compute_covering_cost(rsot_problem *p) {
@@ -556,7 +587,7 @@ static bool options_valid(const rsot_options &o) {
     if (o.precision != RSOT_PREC_MIXED && o.precision != RSOT_PREC_FP64) return false;
     if (o.truncation < RSOT_TRUNC_DENSE || o.truncation > RSOT_TRUNC_TILE) return false;
     if (!(o.tau > 0.0) || !(o.delta_thr > 0.0)) return false;
-    if (o.seg_tiles < 0 || o.mem_limit_bytes < 0) return false;
+    if (o.seg_tiles < 0 || o.seg_blocks < 0 || o.mem_limit_bytes < 0) return false;
     return true;
 }
 
@@ -602,6 +633,8 @@ extern "C" void rsot_problem_destroy(rsot_problem *p) {
     if (p->ev_p1) (void)hipEventDestroy(p->ev_p1);
     if (p->ev_mid) (void)hipEventDestroy(p->ev_mid);
     if (p->ev_p2) (void)hipEventDestroy(p->ev_p2);
+    if (p->ev_b0) (void)hipEventDestroy(p->ev_b0);
+    if (p->ev_b1) (void)hipEventDestroy(p->ev_b1);
     delete p;
 }
 

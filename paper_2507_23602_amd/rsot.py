@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
     _fields_ = [("cost_scale", ctypes.c_double), ("precision", ctypes.c_int),
                 ("truncation", ctypes.c_int), ("tau", ctypes.c_double),
                 ("delta_thr", ctypes.c_double), ("inputs_on_device", ctypes.c_int),
-                ("seg_tiles", ctypes.c_int), ("chunk_log2", ctypes.c_int),
+                ("seg_tiles", ctypes.c_int), ("seg_blocks", ctypes.c_int),
                 ("mem_limit_bytes", ctypes.c_int64)]
 
 
@@ -98,6 +98,33 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+ML_MAX = 16
+
+
+class MLParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.POINTER(ctypes.c_double)), ("level", ctypes.POINTER(ctypes.c_int)),
+                ("n_stages", ctypes.c_int), ("base", SolveParams), ("level_tol", ctypes.c_double),
+                ("transfer", ctypes.c_int)]
+
+
+class MLInfo(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int), ("source_level", ctypes.c_int * ML_MAX),
+                ("target_level", ctypes.c_int * ML_MAX), ("iterations", ctypes.c_int * ML_MAX),
+                ("evaluations", ctypes.c_int * ML_MAX), ("seconds", ctypes.c_double * ML_MAX),
+                ("refine_seconds", ctypes.c_double * ML_MAX),
+                ("refine_pairs", ctypes.c_int64 * ML_MAX), ("total_seconds", ctypes.c_double),
+                ("grad_l1", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        n = self.n_steps
+        d = {k: list(getattr(self, k))[:n] for k in ["source_level", "target_level", "iterations",
+                                                     "evaluations", "seconds", "refine_seconds",
+                                                     "refine_pairs"]}
+        d.update(n_steps=n, total_seconds=self.total_seconds, grad_l1=self.grad_l1,
+                 status=self.status)
+        return d
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
@@ -116,10 +143,24 @@ SIGNATURES = {
     "rsot_set_precision": (_I, [_P, _I]),
     "rsot_set_reference": (_I, [_P, _D]),
     "rsot_dual_eval": (_I, [_P, _D, _P, ctypes.POINTER(_D), _P, ctypes.POINTER(EvalInfo)]),
+    "rsot_dual_eval_batched": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_D), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_D), ctypes.POINTER(_P),
+                                    ctypes.POINTER(EvalInfo), ctypes.POINTER(_D)]),
     "rsot_get_lse": (_I, [_P, _P]),
     "rsot_covering_cost": (_I, [_P, ctypes.POINTER(_D)]),
     "rsot_get_partition": (_I, [_P, _P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "rsot_softmax_refine": (_I, [_P, _D, _P, _I64, _P, _P]),
     "rsot_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
+    "rsot_target_hierarchy": (_I, [_I, _I64, _P, _P, _I, ctypes.POINTER(_I64), _I, ctypes.c_uint64,
+                                   _P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                   ctypes.POINTER(_I64)]),
+    "rsot_multilevel_create": (_I, [_I, _I, ctypes.POINTER(_I64), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P), _I, ctypes.POINTER(_I64),
+                                    ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]),
+    "rsot_multilevel_destroy": (None, [_P]),
+    "rsot_multilevel_indices": (None, [_I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "rsot_solve_multilevel": (_I, [_P, ctypes.POINTER(MLParams), _P, ctypes.POINTER(MLInfo)]),
     "rsot_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, ctypes.POINTER(SolveInfo)]),
 }
 
@@ -194,7 +235,8 @@ class Problem:
     tensors (float64); the library copies them."""
 
     def __init__(self, x, mu, y, nu, *, cost_scale=0.5, precision="mixed", truncation="dense",
-                 tau=1e-12, delta_thr=1e-12, seg_tiles=0, mem_limit_bytes=0, stream=None):
+                 tau=1e-12, delta_thr=1e-12, seg_tiles=0, seg_blocks=0, mem_limit_bytes=0,
+                 stream=None):
         torch = _torch()
         lib = load_library()
         on_dev = isinstance(x, torch.Tensor) and x.is_cuda
@@ -210,7 +252,8 @@ class Problem:
         nq, n = xs.shape[0], ys.shape[0]
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
                               tau=tau, delta_thr=delta_thr, inputs_on_device=int(on_dev),
-                              seg_tiles=seg_tiles, mem_limit_bytes=mem_limit_bytes)
+                              seg_tiles=seg_tiles, seg_blocks=seg_blocks,
+                              mem_limit_bytes=mem_limit_bytes)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -271,6 +314,19 @@ class Problem:
         _check(load_library().rsot_get_lse(self._h, out.data_ptr()), "rsot_get_lse")
         return out
 
+    def softmax_refine(self, psi_coarse, eps, y_fine):
+        """Eq. softmax_refinement_formula: potentials of y_fine from this
+        problem's (coarse) targets and psi_coarse at its points."""
+        torch = _torch()
+        pc = _dev_f64(psi_coarse, self.n)
+        yf = _dev_f64(y_fine)
+        nf = yf.numel() // self.dim
+        out = torch.empty(nf, dtype=torch.float64, device="cuda")
+        _check(load_library().rsot_softmax_refine(self._h, float(eps), pc.data_ptr(), nf,
+                                                  yf.data_ptr(), out.data_ptr()),
+               "rsot_softmax_refine")
+        return out
+
     def covering_cost(self) -> float:
         c = _D(0.0)
         _check(load_library().rsot_covering_cost(self._h, ctypes.byref(c)), "rsot_covering_cost")
@@ -313,3 +369,118 @@ class Problem:
         if rc not in (OK, ERR_NOT_CONVERGED):
             raise RsotError(rc, "rsot_solve")
         return psi, info.as_dict()
+
+
+def multilevel_indices(n_source_levels: int, n_target_levels: int, l: int):
+    a, b = _I(0), _I(0)
+    load_library().rsot_multilevel_indices(n_source_levels, n_target_levels, l, ctypes.byref(a),
+                                           ctypes.byref(b))
+    return a.value, b.value
+
+
+def target_hierarchy(y, nu, n_per_level, lloyd_iters=20, seed=6, with_parents=False):
+    """k-means coarsening (Sec. 5.2); returns [(y_l, nu_l)] coarsest first, as
+    CUDA float64 tensors (and the parent maps when asked)."""
+    torch = _torch()
+    y_t = _dev_f64(y)
+    dim = y_t.shape[1] if y_t.dim() == 2 else int(np.asarray(y).shape[1])
+    nu_t = _dev_f64(nu)
+    n = nu_t.numel()
+    L = len(n_per_level)
+    ys = [torch.empty((int(k), dim), dtype=torch.float64, device="cuda") for k in n_per_level]
+    ns = [torch.empty(int(k), dtype=torch.float64, device="cuda") for k in n_per_level]
+    npl = (_I64 * L)(*[int(k) for k in n_per_level])
+    nout = (_I64 * L)()
+    par = [torch.full((int(k),), -1, dtype=torch.int32, device="cuda") for k in n_per_level]
+    yp = (_P * L)(*[t.data_ptr() for t in ys])
+    npp = (_P * L)(*[t.data_ptr() for t in ns])
+    pp = (_P * L)(*[t.data_ptr() for t in par])
+    stream = torch.cuda.current_stream().cuda_stream
+    _check(load_library().rsot_target_hierarchy(dim, n, y_t.data_ptr(), nu_t.data_ptr(), L, npl,
+                                                int(lloyd_iters), int(seed), _P(stream), yp, npp,
+                                                pp, nout), "rsot_target_hierarchy")
+    levels = [(ys[l][:nout[l]], ns[l][:nout[l]]) for l in range(L)]
+    if with_parents:
+        return levels, [par[l][:nout[l]] for l in range(L)]
+    return levels
+
+
+class Multilevel:
+    """Combined source/target multilevel solver (Sec. 5.3)."""
+
+    def __init__(self, sources, targets, *, cost_scale=0.5, precision="mixed",
+                 truncation="tile", tau=1e-12):
+        torch = _torch()
+        lib = load_library()
+        self._src = [(_dev_f64(x).reshape(len(m) if not isinstance(m, torch.Tensor) else m.numel(), -1),
+                      _dev_f64(m)) for x, m in sources]
+        self._tgt = [(_dev_f64(y).reshape(len(v) if not isinstance(v, torch.Tensor) else v.numel(), -1),
+                      _dev_f64(v)) for y, v in targets]
+        dim = self._src[0][0].shape[1]
+        ns, nt = len(self._src), len(self._tgt)
+        nq = (_I64 * ns)(*[m.numel() for _, m in self._src])
+        ntg = (_I64 * nt)(*[v.numel() for _, v in self._tgt])
+        xp = (_P * ns)(*[x.data_ptr() for x, _ in self._src])
+        mp = (_P * ns)(*[m.data_ptr() for _, m in self._src])
+        yp = (_P * nt)(*[y.data_ptr() for y, _ in self._tgt])
+        vp = (_P * nt)(*[v.data_ptr() for _, v in self._tgt])
+        opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
+                              tau=tau, inputs_on_device=1)
+        h = _P()
+        _check(lib.rsot_multilevel_create(dim, ns, nq, xp, mp, nt, ntg, yp, vp, ctypes.byref(opt),
+                                          _P(torch.cuda.current_stream().cuda_stream),
+                                          ctypes.byref(h)), "rsot_multilevel_create")
+        self._h = h
+        self.n_final = self._tgt[-1][1].numel()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().rsot_multilevel_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000):
+        lib = load_library()
+        e = np.ascontiguousarray(eps, dtype=np.float64)
+        lv = np.ascontiguousarray(level, dtype=np.int32)
+        mp = MLParams()
+        lib.rsot_solve_params_default(ctypes.byref(mp.base))
+        mp.base.tol = tol
+        mp.base.max_iter = max_iter
+        mp.eps = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        mp.level = lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        mp.n_stages = len(e)
+        mp.level_tol = level_tol
+        mp.transfer = 0
+        psi = np.zeros(self.n_final)
+        info = MLInfo()
+        rc = lib.rsot_solve_multilevel(self._h, ctypes.byref(mp), psi.ctypes.data,
+                                       ctypes.byref(info))
+        if rc not in (OK, ERR_NOT_CONVERGED):
+            raise RsotError(rc, "rsot_solve_multilevel")
+        return psi, info.as_dict()
+
+
+def dual_eval_batched(problems, eps, psis, want_grad=True):
+    """rsot_dual_eval_batched over Problem objects; returns (J list, grads,
+    infos, batch_ms)."""
+    torch = _torch()
+    n = len(problems)
+    hs = (_P * n)(*[pr.handle for pr in problems])
+    e = (_D * n)(*[float(v) for v in eps])
+    ps = [_dev_f64(v, pr.n) for v, pr in zip(psis, problems)]
+    pp = (_P * n)(*[t.data_ptr() for t in ps])
+    J = (_D * n)()
+    grads = [torch.empty(pr.n, dtype=torch.float64, device="cuda") for pr in problems] \
+        if want_grad else None
+    gp = (_P * n)(*[g.data_ptr() for g in grads]) if want_grad else None
+    infos = (EvalInfo * n)()
+    ms = _D(0.0)
+    _check(load_library().rsot_dual_eval_batched(hs, n, e, pp, J, gp, infos, ctypes.byref(ms)),
+           "rsot_dual_eval_batched")
+    return list(J), grads, [i.as_dict() for i in infos], ms.value

@@ -369,3 +369,23 @@ def blob_targets_disk(n: int, seed: int = 5, k: int = 5, sigma: float = 0.08,
 
 def random_psi(seed: int, n: int, scale: float) -> np.ndarray:
     return scale * np.random.default_rng(seed).standard_normal(n)
+
+
+def config3(rings: int = 60, levels: int = 4, n_targets: int = 1 << 20,
+            target_levels=(1 << 14, 1 << 16, 1 << 18, 1 << 20)):
+    """Multilevel workload: unit disk from hexagonal rings (6 r^2 triangles),
+    red-refined levels L0..L(levels-1) (60 rings: 21,600 -> 1,382,400
+    triangles, 4,147,200 points at L3), uniform density; 2^20 targets from an
+    equal-weight 5-blob mixture (means uniform in the disk of radius 0.6,
+    sigma 0.08, seed 5), nu uniform; target hierarchy sizes (coarsest first);
+    eps halved from 1e-1 (k = 0..9) then 1e-4, stages {0-3}, {4-6}, {7-8},
+    {9, final} on the four combined levels."""
+    meshes = disk_hierarchy(rings, levels)
+    sources = [quadrature(m) for m in meshes]
+    y = blob_targets_disk(n_targets, seed=5)
+    nu = np.full(n_targets, 1.0 / n_targets)
+    eps = [0.1 * 2.0 ** (-k) for k in range(10)] + [1e-4]
+    level = [0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 3]
+    return {"sources": sources, "y": y, "nu": nu, "target_levels": list(target_levels),
+            "eps": eps, "level": level,
+            "name": f"disk{rings}r_L{levels}_nq{sources[-1][0].shape[0]}_n{n_targets}"}

@@ -45,3 +45,13 @@ def test_binding_covers_header_and_loads():
     assert lib.rsot_status_string(rsot.ERR_NONFINITE).decode() == "non-finite input"
     o = rsot.default_options()
     assert o.cost_scale == 0.5 and o.tau == 1e-12 and o.truncation == rsot.TRUNC_DENSE
+
+
+def test_multilevel_index_rule():
+    """Combined index rule of Sec. 5.3: the hierarchy with fewer levels stays at
+    its coarsest level for the first Lnu - Lmu steps, then both advance."""
+    table = [rsot.multilevel_indices(2, 4, l) for l in range(4)]
+    assert table == [(0, 0), (0, 1), (0, 2), (1, 3)]
+    table = [rsot.multilevel_indices(3, 1, l) for l in range(3)]
+    assert table == [(0, 0), (1, 0), (2, 0)]
+    assert [rsot.multilevel_indices(4, 4, l) for l in range(4)] == [(l, l) for l in range(4)]
