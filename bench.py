@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
     ap.add_argument("--multilevel", action="store_true",
                     help="also time the combined multilevel solve of the 2D disk workload")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also time N uneven 3D instances: one batched call vs single calls")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
     args = ap.parse_args()
@@ -200,11 +202,81 @@ def main():
 
     if args.multilevel:
         out.setdefault("extras", {})["multilevel"] = multilevel_leg()
+    if args.batched:
+        out.setdefault("extras", {})["batched"] = batched_leg(args.batched)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
                                            psi1 if not args.no_extras else None)
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(k):
+    """k uneven 3D instances (points logU[1e5,4e6], targets logU[4096,262144],
+    eps logU[1e-4,1e-2], mixture sources/targets), tile rule tau = 1e-12,
+    mixed precision: one persistent batched call against k single calls, with
+    the library defaults and with autotuned work granularity."""
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+    t0 = time.perf_counter()
+    insts = [W.config5_instance(i) for i in range(k)]
+    log(f"[bench] batched: generated {k} instances in {time.perf_counter()-t0:.1f}s, "
+        f"points {sum(p.nq for p in insts)}, targets {sum(p.n for p in insts)}")
+    probs, psis = [], []
+    for i, p in enumerate(insts):
+        pr = rsot.Problem(torch.as_tensor(p.x, device="cuda"), torch.as_tensor(p.mu, device="cuda"),
+                          torch.as_tensor(p.y, device="cuda"), torch.as_tensor(p.nu, device="cuda"),
+                          truncation="tile", tau=1e-12)
+        ps = torch.as_tensor(W.random_psi(100 + i, p.n, p.eps), device="cuda")
+        pr.dual_eval(ps, p.eps)                       # dense: |J_ref| for the tile rule
+        probs.append(pr)
+        psis.append(ps)
+    eps = [p.eps for p in insts]
+    dense_pairs = sum(p.nq * p.n for p in insts)
+
+    def singles():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        kept = 0
+        for pr, ps, e in zip(probs, psis, eps):
+            kept += pr.dual_eval(ps, e).info["kept_pairs"]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, kept
+
+    def batch():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        J, g, infos, ms = rsot.dual_eval_batched(probs, eps, psis)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, sum(i["kept_pairs"] for i in infos), ms
+
+    singles()
+    batch()
+    res = {}
+    ts, kept = singles()
+    tb, kept_b, ms = batch()
+    assert kept == kept_b
+    res["untuned"] = {"singles_s": ts, "batched_s": tb, "batched_device_ms": ms,
+                      "kept_pairs": kept, "kept_pairs_s_batched": kept / tb,
+                      "kept_pairs_s_singles": kept / ts}
+    t0 = time.perf_counter()
+    for pr, ps, e in zip(probs, psis, eps):
+        pr.autotune(ps, e, reps=1)
+    t_tune = time.perf_counter() - t0
+    singles()
+    ts, kept = singles()
+    tb, kept_b, ms = batch()
+    res["tuned"] = {"singles_s": ts, "batched_s": tb, "batched_device_ms": ms,
+                    "kept_pairs_s_batched": kept / tb, "kept_pairs_s_singles": kept / ts,
+                    "tune_seconds": t_tune}
+    res.update(instances=k, dense_pairs=dense_pairs, kept_frac=kept / dense_pairs,
+               effective_pairs_s_batched=dense_pairs / tb)
+    log(f"[bench] batched {k}: kept {kept/dense_pairs:.4f} of {dense_pairs:.3e}; untuned singles "
+        f"{res['untuned']['singles_s']*1e3:.1f} ms, batched {res['untuned']['batched_s']*1e3:.1f} ms; "
+        f"tuned singles {ts*1e3:.1f} ms, batched {tb*1e3:.1f} ms (tuning {t_tune:.1f}s)")
+    for pr in probs:
+        pr.close()
+    return res
 
 
 def multilevel_leg():

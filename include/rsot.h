@@ -185,6 +185,24 @@ rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, const double 
                                    double *batch_ms);
 
 /*
+ * Autotuner: picks the work granularity of both passes for this problem by
+ * timing evaluations at (eps, psi): objective-pass segment in
+ * {64,128,256,512,1024} target blocks, then gradient-pass segment in
+ * {16,...,4096} point tiles (0 = library default), each the best of `reps`
+ * device timings. The problem keeps the fastest pair.
+ *   psi             DEVICE pointer (n_target doubles)
+ *   seg_*_out       HOST, chosen values (0 = default); may be NULL
+ *   best_ms_out     HOST, time of the chosen configuration; may be NULL
+ *   default_ms_out  HOST, time of the default configuration; may be NULL
+ */
+rsot_status rsot_autotune(rsot_problem *p, double eps, const double *psi, int reps,
+                          int *seg_blocks_out, int *seg_tiles_out, double *best_ms_out,
+                          double *default_ms_out);
+
+/* Sets the work granularity directly (e.g. from a cache of autotuner results). */
+rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles);
+
+/*
  * Per-point log-sum-exp L_q = ln sum_j nu_j exp((psi_j - c_qj)/eps) of the
  * last evaluation (the log of S_q in Alg. 2; -inf for a dropped point), in
  * the caller's point order. L_out: DEVICE pointer, n_quad doubles.
@@ -258,6 +276,10 @@ typedef struct {
     double J, grad_l1, grad_linf;
     double seconds;             /* wall time of the solve                           */
     double eval_ms;             /* device time spent in evaluations                */
+    double cull_ms;             /* of which: target records, cutoff, culling       */
+    double pass1_ms;            /* of which: objective passes                      */
+    double pass2_ms;            /* of which: gradient passes                       */
+    double kept_frac;           /* mean fraction of pairs summed per evaluation    */
     int status;                 /* rsot_status of the solve                         */
 } rsot_solve_info;
 
@@ -347,6 +369,8 @@ typedef struct {
     double seconds[RSOT_ML_MAX_LEVELS];           /* solve time of each step      */
     double refine_seconds[RSOT_ML_MAX_LEVELS];    /* transfer time into each step */
     int64_t refine_pairs[RSOT_ML_MAX_LEVELS];     /* pairs the refinement summed  */
+    double eval_ms[RSOT_ML_MAX_LEVELS];           /* device time in evaluations   */
+    double kept_frac[RSOT_ML_MAX_LEVELS];         /* mean kept-pair fraction      */
     double total_seconds;
     double grad_l1;
     int status;

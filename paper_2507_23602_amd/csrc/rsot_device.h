@@ -24,6 +24,15 @@ __device__ inline int wave_sum_int(int v) {
     return v;
 }
 
+// Lane 0's value of a 64-bit quantity, in scalar registers. The builtin
+// returns a signed int, so each half is widened through uint32_t: a plain
+// (uint64_t) cast would sign-extend the low half into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
 // least distance between the intervals [a0,a1] and [b0,b1] along one axis
 __device__ inline double box_gap(double a0, double a1, double b0, double b1) {
     if (b0 > a1) return b0 - a1;

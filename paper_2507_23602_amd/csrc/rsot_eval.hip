@@ -46,6 +46,21 @@
 
 enum { MODE_DENSE = 0, MODE_LIST = 1, MODE_MASK = 2 };
 
+// constant (read-only) address space: loads at uniform addresses through it
+// may use the scalar cache
+#define RSOT_CAS __attribute__((address_space(4)))
+
+__device__ __forceinline__ double4 ld4(const double4 *p) { return *p; }
+__device__ __forceinline__ double4 ld4(const RSOT_CAS double4 *p) {
+    const RSOT_CAS double *q = (const RSOT_CAS double *)p;
+    double4 r;
+    r.x = q[0];
+    r.y = q[1];
+    r.z = q[2];
+    r.w = q[3];
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // per-target records and block statistics
 // ---------------------------------------------------------------------------
@@ -361,17 +376,15 @@ __global__ void k_fill_work(const int64_t *__restrict__ col_ptr, const int64_t *
 // Accumulates one 64-target block into the running (m, s) of this lane's point:
 // s = sum 2^(t_j - m) with t_j = B_j + x.Y_j. m is an integer that only grows;
 // when a chunk's max exceeds it, s is rescaled by an exact power of two.
-template <int D, bool F64, bool MASK>
-__device__ __forceinline__ void lse_block(const double4 *__restrict__ T,
-                                          const double *__restrict__ G, double x0, double x1,
-                                          double x2, double A, double &m, double &s,
-                                          double &kept) {
+template <int D, bool F64, bool MASK, typename RP, typename GP>
+__device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, double x2, double A,
+                                          double &m, double &s, double &kept) {
     for (int k0 = 0; k0 < 64; k0 += CH) {
         double tv[CH];
         double cm = -INFINITY;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = T[k0 + k];
+            const double4 r = ld4(T + k0 + k);
             double v = x0 * r.x;
             v = fma(x1, r.y, v);
             if (D == 3) v = fma(x2, r.z, v);
@@ -413,15 +426,15 @@ __device__ __forceinline__ void lse_block(const double4 *__restrict__ T,
 // positive raises m to ceil of that u and is recomputed from the FP64
 // records; without the trigger every u < 1. Spurious triggers (several terms
 // just below the reference) cost the max over the chunk only.
-template <int D>
-__device__ __forceinline__ void lse_block_fast(const double4 *__restrict__ T, double x0,
-                                               double x1, double x2, double &m, double &s) {
+template <int D, typename RP>
+__device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, double x2, double &m,
+                                               double &s) {
     for (int k0 = 0; k0 < 64; k0 += CH) {
         float u[CH];
         float cs = 0.0f;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = T[k0 + k];
+            const double4 r = ld4(T + k0 + k);
             double v = r.w - m;
             v = fma(x0, r.x, v);
             v = fma(x1, r.y, v);
@@ -443,7 +456,7 @@ __device__ __forceinline__ void lse_block_fast(const double4 *__restrict__ T, do
             cs = 0.0f;
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const double4 r = T[k0 + k];
+                const double4 r = ld4(T + k0 + k);
                 double v = r.w - m;
                 v = fma(x0, r.x, v);
                 v = fma(x1, r.y, v);
@@ -460,12 +473,11 @@ __device__ __forceinline__ void lse_block_fast(const double4 *__restrict__ T, do
 // targets, and the number of pairs it summed. Rows of very different length
 // (a tile far from every target keeps many blocks) are split into segments,
 // so no wavefront carries a whole long row.
-template <int D, bool F64, int MODE>
-__device__ __forceinline__ void pass1_item(
-    const double4 *__restrict__ qp, const double4 *__restrict__ trec,
-    const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
-    const uint32_t *__restrict__ row_idx, int64_t t, int64_t e0, int64_t e1, double kcs,
-    int64_t w, int lane, double *__restrict__ part, double *__restrict__ partk) {
+template <int D, bool F64, int MODE, typename RP, typename GP, typename CP, typename IP>
+__device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP trec, GP tG,
+                                           CP blk_cnt, IP row_idx, int64_t t, int64_t e0,
+                                           int64_t e1, double kcs, int64_t w, int lane,
+                                           double *__restrict__ part, double *__restrict__ partk) {
     const int64_t q = t * 64 + lane;
     const double4 xr = qp[q];
     const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
@@ -475,7 +487,7 @@ __device__ __forceinline__ void pass1_item(
     if (FAST && e1 > e0) {
         // reference from the first target of the first block (a kept target)
         const uint32_t ent0 = MODE == MODE_DENSE ? (uint32_t)e0 : row_idx[e0];
-        const double4 r = trec[(int64_t)(ent0 & ~RSOT_PARTIAL_BIT) * 64];
+        const double4 r = ld4(trec + (int64_t)(ent0 & ~RSOT_PARTIAL_BIT) * 64);
         double v = x0 * r.x;
         v = fma(x1, r.y, v);
         if (D == 3) v = fma(x2, r.z, v);
@@ -484,7 +496,7 @@ __device__ __forceinline__ void pass1_item(
     for (int64_t e = e0; e < e1; ++e) {
         const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
-        const double4 *__restrict__ T = trec + b * 64;
+        const auto T = trec + b * 64;
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
             lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
         } else {
@@ -573,17 +585,16 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
 // ---------------------------------------------------------------------------
 // gradient pass
 // ---------------------------------------------------------------------------
-template <int D, bool F64, bool MASK>
-__device__ __forceinline__ double mass_tile(const double4 *__restrict__ Q,
-                                            const double *__restrict__ H, double Y0, double Y1,
-                                            double Y2, double B, double G) {
+template <int D, bool F64, bool MASK, typename QP, typename HP>
+__device__ __forceinline__ double mass_tile(QP Q, HP H, double Y0, double Y1, double Y2, double B,
+                                            double G) {
     double acc = 0.0;
     for (int i0 = 0; i0 < 64; i0 += CH) {
         if (F64) {
             double cs = 0.0;
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const double4 r = Q[i0 + k];
+                const double4 r = ld4(Q + i0 + k);
                 double v = B + r.w;
                 v = fma(r.x, Y0, v);
                 v = fma(r.y, Y1, v);
@@ -596,7 +607,7 @@ __device__ __forceinline__ double mass_tile(const double4 *__restrict__ Q,
             float cs = 0.0f;
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const double4 r = Q[i0 + k];
+                const double4 r = ld4(Q + i0 + k);
                 double v = B + r.w;
                 v = fma(r.x, Y0, v);
                 v = fma(r.y, Y1, v);
@@ -610,12 +621,9 @@ __device__ __forceinline__ double mass_tile(const double4 *__restrict__ Q,
     return acc;
 }
 
-template <int D, bool F64, int MODE>
-__device__ __forceinline__ void pass2_item(const double4 *__restrict__ qp,
-                                           const double *__restrict__ qH,
-                                           const double4 *__restrict__ trec,
-                                           const double *__restrict__ tG,
-                                           const uint32_t *__restrict__ col_idx, int64_t b,
+template <int D, bool F64, int MODE, typename QP, typename HP, typename IP>
+__device__ __forceinline__ void pass2_item(QP qp, HP qH, const double4 *__restrict__ trec,
+                                           const double *__restrict__ tG, IP col_idx, int64_t b,
                                            int64_t e0, int64_t e1, int64_t w, int lane,
                                            double *__restrict__ gpart) {
     const int64_t j = b * 64 + lane;
@@ -625,7 +633,7 @@ __device__ __forceinline__ void pass2_item(const double4 *__restrict__ qp,
     for (int64_t e = e0; e < e1; ++e) {
         const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
         const int64_t t = ent & ~RSOT_PARTIAL_BIT;
-        const double4 *__restrict__ Q = qp + t * 64;
+        const auto Q = qp + t * 64;
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
             acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G);
         else
@@ -695,8 +703,7 @@ __device__ inline uint64_t next_item(unsigned long long *counter, int lane) {
     unsigned long long g = 0;
     if (lane == 0) g = atomicAdd(counter, 1ull);
     g = __shfl(g, 0, 64);
-    return (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(g & 0xffffffffu)) |
-           ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(g >> 32)) << 32);
+    return uniform_u64((uint64_t)g);
 }
 
 // position k of the problem owning queue item g: begin[k] <= g < begin[k+1]
@@ -710,8 +717,17 @@ __device__ inline int owner(const int64_t *__restrict__ begin, int n, uint64_t g
     return lo;
 }
 
-// Objective pass of every problem of the batch: waves pull items from one
-// queue (problems in decreasing cost order) until it is empty.
+// A pointer read from a descriptor, made wave-uniform and marked read-only
+// (constant address space) so its loads can go through the scalar cache.
+template <typename T>
+__device__ __forceinline__ const RSOT_CAS T *uniform_const(const T *p) {
+    return (const RSOT_CAS T *)uniform_u64((uint64_t)p);
+}
+
+// Objective pass of every problem of one (dimension, rule) group of the
+// batch: waves pull items from one queue (problems in decreasing cost
+// order) until it is empty.
+template <int D, int MODE>
 __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restrict__ descs,
                                                        const int32_t *__restrict__ order,
                                                        const int64_t *__restrict__ begin, int n,
@@ -725,7 +741,7 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
         const BatchDesc &d = descs[order[k]];
         const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
         int64_t t, e0, e1, w;
-        if (d.mode == MODE_DENSE) {
+        if (MODE == MODE_DENSE) {
             // consecutive items share the block segment (target records)
             const int64_t s1 = v / d.n_tiles;
             t = v % d.n_tiles;
@@ -734,24 +750,17 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
             w = t * d.n_seg1 + s1;
         } else {
             w = v;
-            t = d.wi1_tile[w];
-            e0 = d.wi1_range[2 * w];
-            e1 = d.wi1_range[2 * w + 1];
+            t = uniform_const(d.wi1_tile)[w];
+            e0 = uniform_const(d.wi1_range)[2 * w];
+            e1 = uniform_const(d.wi1_range)[2 * w + 1];
         }
-        if (d.dim == 3) {
-            if (d.mode == MODE_DENSE)
-                pass1_item<3, false, MODE_DENSE>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
-            else
-                pass1_item<3, false, MODE_LIST>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
-        } else {
-            if (d.mode == MODE_DENSE)
-                pass1_item<2, false, MODE_DENSE>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
-            else
-                pass1_item<2, false, MODE_LIST>(d.qp, d.trec, d.tG, d.blk_cnt, d.row_idx, t, e0, e1, d.kcs, w, lane, d.part1, d.part1k);
-        }
+        pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.tG),
+                                   uniform_const(d.blk_cnt), uniform_const(d.row_idx), t, e0, e1,
+                                   d.kcs, w, lane, d.part1, d.part1k);
     }
 }
 
+template <int D, int MODE>
 __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restrict__ descs,
                                                        const int32_t *__restrict__ order,
                                                        const int64_t *__restrict__ begin, int n,
@@ -765,7 +774,7 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
         const BatchDesc &d = descs[order[k]];
         const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
         int64_t b, e0, e1, w;
-        if (d.mode == MODE_DENSE) {
+        if (MODE == MODE_DENSE) {
             // consecutive items share the point segment (point records)
             const int64_t sgi = v / d.n_blocks;
             b = v % d.n_blocks;
@@ -774,21 +783,12 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
             w = b * d.n_seg + sgi;
         } else {
             w = v;
-            b = d.wi_block[w];
-            e0 = d.wi_range[2 * w];
-            e1 = d.wi_range[2 * w + 1];
+            b = uniform_const(d.wi_block)[w];
+            e0 = uniform_const(d.wi_range)[2 * w];
+            e1 = uniform_const(d.wi_range)[2 * w + 1];
         }
-        if (d.dim == 3) {
-            if (d.mode == MODE_DENSE)
-                pass2_item<3, false, MODE_DENSE>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
-            else
-                pass2_item<3, false, MODE_LIST>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
-        } else {
-            if (d.mode == MODE_DENSE)
-                pass2_item<2, false, MODE_DENSE>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
-            else
-                pass2_item<2, false, MODE_LIST>(d.qp, d.qH, d.trec, d.tG, d.col_idx, b, e0, e1, w, lane, d.gpart);
-        }
+        pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH), d.trec, d.tG,
+                                   uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
     }
 }
 
@@ -1318,44 +1318,76 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
     }
     const int nb = (int)descs.size();
     if (nb > 0) {
+        // group members by (dimension, rule): one persistent launch per group
+        // and pass; within a group, problems in decreasing order of work
         std::vector<int32_t> order((size_t)nb);
         for (int k = 0; k < nb; ++k) order[(size_t)k] = k;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return cost[(size_t)a] > cost[(size_t)b]; });
-        std::vector<int64_t> begin1((size_t)nb + 1, 0), begin2((size_t)nb + 1, 0);
-        for (int k = 0; k < nb; ++k) {
-            const BatchDesc &d = descs[(size_t)order[(size_t)k]];
-            begin1[(size_t)k + 1] = begin1[(size_t)k] + d.n_items1;
-            begin2[(size_t)k + 1] = begin2[(size_t)k] + d.n_wi;
+        auto gkey = [&](int k) { return descs[(size_t)k].dim * 4 + descs[(size_t)k].mode; };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            if (gkey(a) != gkey(b)) return gkey(a) < gkey(b);
+            return cost[(size_t)a] > cost[(size_t)b];
+        });
+        std::vector<int> gstart;
+        for (int k = 0; k < nb; ++k)
+            if (k == 0 || gkey(order[(size_t)k]) != gkey(order[(size_t)k - 1])) gstart.push_back(k);
+        gstart.push_back(nb);
+        const int ng = (int)gstart.size() - 1;
+        // per group: queue offsets of its problems (count + 1 entries each)
+        std::vector<int64_t> begin1, begin2;
+        std::vector<size_t> goff;
+        for (int gi = 0; gi < ng; ++gi) {
+            goff.push_back(begin1.size());
+            int64_t a1 = 0, a2 = 0;
+            for (int k = gstart[(size_t)gi]; k < gstart[(size_t)gi + 1]; ++k) {
+                begin1.push_back(a1);
+                begin2.push_back(a2);
+                const BatchDesc &d = descs[(size_t)order[(size_t)k]];
+                a1 += d.n_items1;
+                a2 += d.n_wi;
+            }
+            begin1.push_back(a1);
+            begin2.push_back(a2);
         }
-        // scratch of the batch lives with the first problem
-        const size_t bytes = sizeof(BatchDesc) * nb + sizeof(int32_t) * nb +
-                             2 * sizeof(int64_t) * (nb + 1) + 2 * sizeof(unsigned long long) + 256 * 4;
+        const size_t nbeg = begin1.size();
+        const size_t s_desc = (sizeof(BatchDesc) * nb + 255) & ~size_t(255);
+        const size_t s_ord = (sizeof(int32_t) * nb + 255) & ~size_t(255);
+        const size_t s_beg = (sizeof(int64_t) * nbeg + 255) & ~size_t(255);
+        const size_t s_cnt = sizeof(unsigned long long) * 2 * ng;
+        const size_t bytes = s_desc + s_ord + 2 * s_beg + s_cnt + 256;
         size_t cap = p0->batch_cap;
         RSOT_TRY(grow(p0, &p0->batch_buf, &cap, bytes));
         p0->batch_cap = cap;
         char *base = p0->batch_buf;
         BatchDesc *d_desc = (BatchDesc *)base;
-        size_t off = (sizeof(BatchDesc) * nb + 255) & ~size_t(255);
-        int32_t *d_order = (int32_t *)(base + off);
-        off += (sizeof(int32_t) * nb + 255) & ~size_t(255);
-        int64_t *d_b1 = (int64_t *)(base + off);
-        off += (sizeof(int64_t) * (nb + 1) + 255) & ~size_t(255);
-        int64_t *d_b2 = (int64_t *)(base + off);
-        off += (sizeof(int64_t) * (nb + 1) + 255) & ~size_t(255);
-        unsigned long long *d_cnt = (unsigned long long *)(base + off);
-        // host staging (pinned) for the descriptors
-        std::vector<char> stage(off);
+        int32_t *d_order = (int32_t *)(base + s_desc);
+        int64_t *d_b1 = (int64_t *)(base + s_desc + s_ord);
+        int64_t *d_b2 = (int64_t *)(base + s_desc + s_ord + s_beg);
+        unsigned long long *d_cnt = (unsigned long long *)(base + s_desc + s_ord + 2 * s_beg);
+        const size_t stage_bytes = s_desc + s_ord + 2 * s_beg;
+        std::vector<char> stage(stage_bytes);
         std::memcpy(stage.data(), descs.data(), sizeof(BatchDesc) * nb);
-        std::memcpy(stage.data() + ((char *)d_order - base), order.data(), sizeof(int32_t) * nb);
-        std::memcpy(stage.data() + ((char *)d_b1 - base), begin1.data(), sizeof(int64_t) * (nb + 1));
-        std::memcpy(stage.data() + ((char *)d_b2 - base), begin2.data(), sizeof(int64_t) * (nb + 1));
-        RSOT_HIP(hipMemcpyAsync(base, stage.data(), off, hipMemcpyHostToDevice, st));
+        std::memcpy(stage.data() + s_desc, order.data(), sizeof(int32_t) * nb);
+        std::memcpy(stage.data() + s_desc + s_ord, begin1.data(), sizeof(int64_t) * nbeg);
+        std::memcpy(stage.data() + s_desc + s_ord + s_beg, begin2.data(), sizeof(int64_t) * nbeg);
+        RSOT_HIP(hipMemcpyAsync(base, stage.data(), stage_bytes, hipMemcpyHostToDevice, st));
         for (int k = 0; k < nb; ++k) (void)hipEventRecord(ps[members[(size_t)k]]->ev_p1, st);
         const unsigned grid = 256u * 8u;
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, d_cnt);
-        hipLaunchKernelGGL(k_pass1_batched, dim3(grid), dim3(256), 0, st, d_desc, d_order, d_b1, nb,
-                           d_cnt);
+        for (int gi = 0; gi < ng; ++gi) {
+            const int k0 = gstart[(size_t)gi], cnt = gstart[(size_t)gi + 1] - k0;
+            const BatchDesc &d0 = descs[(size_t)order[(size_t)k0]];
+            const int32_t *o = d_order + k0;
+            const int64_t *b1 = d_b1 + goff[(size_t)gi];
+            unsigned long long *c = d_cnt + 2 * gi;
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, c);
+            if (d0.dim == 3 && d0.mode == MODE_DENSE)
+                hipLaunchKernelGGL((k_pass1_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+            else if (d0.dim == 3)
+                hipLaunchKernelGGL((k_pass1_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+            else if (d0.mode == MODE_DENSE)
+                hipLaunchKernelGGL((k_pass1_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+            else
+                hipLaunchKernelGGL((k_pass1_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+        }
         for (int k = 0; k < nb; ++k) {
             EvalPlan &e = plans[(size_t)members[(size_t)k]];
             rsot_problem *p = e.p;
@@ -1364,13 +1396,25 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
                                e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr,
                                e.pw.n_seg1, p->n_tiles, e.kcs, 0, p->qH, p->qlse, p->tile_part);
         }
-        if (begin2[(size_t)nb] > 0) {
-            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, d_cnt + 1);
-            hipLaunchKernelGGL(k_pass2_batched, dim3(grid), dim3(256), 0, st, d_desc, d_order, d_b2,
-                               nb, d_cnt + 1);
+        for (int gi = 0; gi < ng; ++gi) {
+            const int k0 = gstart[(size_t)gi], cnt = gstart[(size_t)gi + 1] - k0;
+            if (begin2[goff[(size_t)gi] + (size_t)cnt] == 0) continue;
+            const BatchDesc &d0 = descs[(size_t)order[(size_t)k0]];
+            const int32_t *o = d_order + k0;
+            const int64_t *b2 = d_b2 + goff[(size_t)gi];
+            unsigned long long *c = d_cnt + 2 * gi + 1;
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, c);
+            if (d0.dim == 3 && d0.mode == MODE_DENSE)
+                hipLaunchKernelGGL((k_pass2_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+            else if (d0.dim == 3)
+                hipLaunchKernelGGL((k_pass2_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+            else if (d0.mode == MODE_DENSE)
+                hipLaunchKernelGGL((k_pass2_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+            else
+                hipLaunchKernelGGL((k_pass2_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
         }
         RSOT_HIP(hipGetLastError());
-        // the staging buffer must outlive the asynchronous copy
+        // the host staging buffer must outlive the asynchronous copy
         RSOT_HIP(hipStreamSynchronize(st));
         for (int k = 0; k < nb; ++k) (void)hipEventRecord(ps[members[(size_t)k]]->ev_p2, st);
     }
@@ -1539,7 +1583,7 @@ __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y
         double cm = -INFINITY;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = Q[i0 + k];
+            const double4 r = ld4(Q + i0 + k);
             double v = B + r.w;
             v = fma(r.x, Y0, v);
             v = fma(r.y, Y1, v);
@@ -1701,4 +1745,75 @@ extern "C" rsot_status rsot_softmax_refine(rsot_problem *p, double eps, const do
     if (!p || !psi_coarse || !y_fine || !psi_fine_out || n_fine <= 0) return RSOT_ERR_INVALID_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
     return rsot_refine_impl(p, eps, psi_coarse, n_fine, y_fine, 1e-12, psi_fine_out);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: work granularity of both passes, by timing the live problem
+// ---------------------------------------------------------------------------
+// Coordinate search: objective-pass segment (target blocks per work item),
+// then gradient-pass segment (point tiles per work item), each candidate
+// timed as the best of `reps` evaluations with HIP events. The problem keeps
+// the fastest pair; the default configuration's time is reported beside it.
+static rsot_status time_config(rsot_problem *p, double eps, const double *psi, int sb, int stl,
+                               int reps, double *ms_out) {
+    p->opt.seg_blocks = sb;
+    p->opt.seg_tiles = stl;
+    double best = INFINITY, J = 0.0;
+    rsot_eval_info info{};
+    for (int r = 0; r < reps; ++r) {
+        RSOT_TRY(rsot_eval_impl(p, eps, psi, &J, p->dgrad, &info));
+        best = std::min(best, info.kernel_ms);
+    }
+    *ms_out = best;
+    return RSOT_OK;
+}
+
+extern "C" rsot_status rsot_autotune(rsot_problem *p, double eps, const double *psi, int reps,
+                                     int *seg_blocks_out, int *seg_tiles_out, double *best_ms_out,
+                                     double *default_ms_out) {
+    if (!p || !psi || !(eps > 0.0) || reps < 1) return RSOT_ERR_INVALID_ARG;
+    static const int SB[] = {64, 128, 256, 512, 1024};
+    static const int ST[] = {16, 32, 64, 128, 256, 512, 1024, 4096};
+    const rsot_options keep = p->opt;
+    double J = 0.0;
+    rsot_eval_info info{};
+    RSOT_TRY(rsot_eval_impl(p, eps, psi, &J, p->dgrad, &info));   // state (|J_ref|), warm-up
+    double t_def = 0.0;
+    rsot_status s = time_config(p, eps, psi, 0, 0, reps, &t_def);
+    int best_sb = 0, best_st = 0;
+    double best = t_def;
+    for (int sb : SB) {
+        if (s != RSOT_OK) break;
+        double t = 0.0;
+        s = time_config(p, eps, psi, sb, best_st, reps, &t);
+        if (s == RSOT_OK && t < best) {
+            best = t;
+            best_sb = sb;
+        }
+    }
+    for (int st : ST) {
+        if (s != RSOT_OK) break;
+        double t = 0.0;
+        s = time_config(p, eps, psi, best_sb, st, reps, &t);
+        if (s == RSOT_OK && t < best) {
+            best = t;
+            best_st = st;
+        }
+    }
+    p->opt = keep;
+    if (s != RSOT_OK) return s;
+    p->opt.seg_blocks = best_sb;
+    p->opt.seg_tiles = best_st;
+    if (seg_blocks_out) *seg_blocks_out = best_sb;
+    if (seg_tiles_out) *seg_tiles_out = best_st;
+    if (best_ms_out) *best_ms_out = best;
+    if (default_ms_out) *default_ms_out = t_def;
+    return RSOT_OK;
+}
+
+extern "C" rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles) {
+    if (!p || seg_blocks < 0 || seg_tiles < 0) return RSOT_ERR_INVALID_ARG;
+    p->opt.seg_blocks = seg_blocks;
+    p->opt.seg_tiles = seg_tiles;
+    return RSOT_OK;
 }

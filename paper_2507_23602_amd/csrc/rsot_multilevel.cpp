@@ -197,6 +197,8 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
             rsot_status s = rsot_solve(p, &sp, psi.data(), &si);
             inf.iterations[l] = si.iterations;
             inf.evaluations[l] = si.evaluations;
+            inf.eval_ms[l] = si.eval_ms;
+            inf.kept_frac[l] = si.kept_frac;
             inf.grad_l1 = si.grad_l1;
             if (s != RSOT_OK && !(s == RSOT_ERR_NOT_CONVERGED && !last)) status = s;
             eps_prev = eps_l.back();

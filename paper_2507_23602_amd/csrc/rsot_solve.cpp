@@ -29,7 +29,7 @@ struct Evaluator {
     rsot_problem *p;
     double eps;
     int evals = 0;
-    double eval_ms = 0.0;
+    double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept = 0.0;
     volatile int *cancel = nullptr;
     rsot_eval_info last{};
 
@@ -46,6 +46,10 @@ struct Evaluator {
         std::memcpy(g.data(), p->hgrad, n * sizeof(double));
         ++evals;
         eval_ms += last.kernel_ms;
+        cull_ms += last.setup_ms;
+        p1_ms += last.pass1_ms;
+        p2_ms += last.pass2_ms;
+        kept += (double)last.kept_pairs / (double)last.total_pairs;
         return RSOT_OK;
     }
 };
@@ -201,7 +205,7 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
     rsot_solve_info inf{};
     rsot_status status = RSOT_OK;
     double J = 0.0;
-    double eval_ms = 0.0;
+    double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept_sum = 0.0;
     int total_it = 0, total_ev = 0;
     const double saved_ref = p->absJ_ref;
 
@@ -215,6 +219,10 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         inf.J = J;
         inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         inf.eval_ms = eval_ms;
+        inf.cull_ms = cull_ms;
+        inf.pass1_ms = p1_ms;
+        inf.pass2_ms = p2_ms;
+        inf.kept_frac = total_ev > 0 ? kept_sum / total_ev : 0.0;
         inf.status = st;
         if (info) *info = inf;
         return st;
@@ -231,6 +239,10 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         if (s != RSOT_OK) {
             total_ev += ev.evals;
             eval_ms += ev.eval_ms;
+            cull_ms += ev.cull_ms;
+            p1_ms += ev.p1_ms;
+            p2_ms += ev.p2_ms;
+            kept_sum += ev.kept;
             return finish(s);
         }
         double gl1 = ev.last.grad_l1, glinf = ev.last.grad_linf;
@@ -332,6 +344,10 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         total_it += it;
         total_ev += ev.evals;
         eval_ms += ev.eval_ms;
+        cull_ms += ev.cull_ms;
+        p1_ms += ev.p1_ms;
+        p2_ms += ev.p2_ms;
+        kept_sum += ev.kept;
         inf.grad_l1 = gl1;
         inf.grad_linf = glinf;
         inf.stages = stage + 1;

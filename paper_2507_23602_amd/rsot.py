@@ -92,7 +92,9 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int),
                 ("stages", ctypes.c_int), ("J", ctypes.c_double), ("grad_l1", ctypes.c_double),
                 ("grad_linf", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("eval_ms", ctypes.c_double), ("status", ctypes.c_int)]
+                ("eval_ms", ctypes.c_double), ("cull_ms", ctypes.c_double),
+                ("pass1_ms", ctypes.c_double), ("pass2_ms", ctypes.c_double),
+                ("kept_frac", ctypes.c_double), ("status", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -112,23 +114,35 @@ class MLInfo(ctypes.Structure):
                 ("target_level", ctypes.c_int * ML_MAX), ("iterations", ctypes.c_int * ML_MAX),
                 ("evaluations", ctypes.c_int * ML_MAX), ("seconds", ctypes.c_double * ML_MAX),
                 ("refine_seconds", ctypes.c_double * ML_MAX),
-                ("refine_pairs", ctypes.c_int64 * ML_MAX), ("total_seconds", ctypes.c_double),
+                ("refine_pairs", ctypes.c_int64 * ML_MAX), ("eval_ms", ctypes.c_double * ML_MAX),
+                ("kept_frac", ctypes.c_double * ML_MAX), ("total_seconds", ctypes.c_double),
                 ("grad_l1", ctypes.c_double), ("status", ctypes.c_int)]
 
     def as_dict(self):
         n = self.n_steps
         d = {k: list(getattr(self, k))[:n] for k in ["source_level", "target_level", "iterations",
                                                      "evaluations", "seconds", "refine_seconds",
-                                                     "refine_pairs"]}
+                                                     "refine_pairs", "eval_ms", "kept_frac"]}
         d.update(n_steps=n, total_seconds=self.total_seconds, grad_l1=self.grad_l1,
                  status=self.status)
         return d
 
 
+class LearnedInfo(ctypes.Structure):
+    _fields_ = [("used_learned", ctypes.c_int), ("predict_ms", ctypes.c_double),
+                ("J_pred", ctypes.c_double), ("J_zero", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
+_F = ctypes.c_float
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
+
+MLP_NPARAMS = 199425
 
 # name -> (restype, argtypes); every symbol declared in include/rsot.h
 SIGNATURES = {
@@ -146,6 +160,9 @@ SIGNATURES = {
     "rsot_dual_eval_batched": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_D), ctypes.POINTER(_P),
                                     ctypes.POINTER(_D), ctypes.POINTER(_P),
                                     ctypes.POINTER(EvalInfo), ctypes.POINTER(_D)]),
+    "rsot_autotune": (_I, [_P, _D, _P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                           ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "rsot_set_tuning": (_I, [_P, _I, _I]),
     "rsot_get_lse": (_I, [_P, _P]),
     "rsot_covering_cost": (_I, [_P, ctypes.POINTER(_D)]),
     "rsot_get_partition": (_I, [_P, _P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -162,6 +179,22 @@ SIGNATURES = {
     "rsot_multilevel_indices": (None, [_I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "rsot_solve_multilevel": (_I, [_P, ctypes.POINTER(MLParams), _P, ctypes.POINTER(MLInfo)]),
     "rsot_solve": (_I, [_P, ctypes.POINTER(SolveParams), _P, ctypes.POINTER(SolveInfo)]),
+    # include/rsot_mlp.h
+    "rsot_mlp_create": (_I, [_P, _P, ctypes.POINTER(_P)]),
+    "rsot_mlp_destroy": (None, [_P]),
+    "rsot_mlp_get_params": (_I, [_P, _I, _P]),
+    "rsot_mlp_set_params": (_I, [_P, _P]),
+    "rsot_mlp_set_normalization": (_I, [_P, _P, _P, _F, _F]),
+    "rsot_mlp_get_normalization": (_I, [_P, _P, _P, ctypes.POINTER(_F), ctypes.POINTER(_F)]),
+    "rsot_mlp_fit_normalization": (_I, [_P, _P, _P, _I64]),
+    "rsot_mlp_features": (_I, [_I64, _P, _P, _P, _P]),
+    "rsot_mlp_forward": (_I, [_P, _P, _I64, _P]),
+    "rsot_mlp_backward": (_I, [_P, _P, _I64, _P, _P]),
+    "rsot_mlp_adam_step": (_I, [_P, _P, _F, _F, _F, _F]),
+    "rsot_mlp_train_step": (_I, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, ctypes.POINTER(_D)]),
+    "rsot_mlp_predict_psi": (_I, [_P, _I64, _P, _P, _P, _P]),
+    "rsot_solve_learned": (_I, [_P, _P, _P, ctypes.POINTER(SolveParams), _P,
+                                ctypes.POINTER(SolveInfo), ctypes.POINTER(LearnedInfo)]),
 }
 
 _lib = None
@@ -308,6 +341,21 @@ class Problem:
                                              ctypes.byref(info)), "rsot_dual_eval")
         return EvalResult(J.value, grad, info.as_dict())
 
+    def autotune(self, psi, eps, reps=2):
+        """rsot_autotune: returns dict(seg_blocks, seg_tiles, best_ms, default_ms)."""
+        pt = _dev_f64(psi, self.n)
+        sb, st = _I(0), _I(0)
+        best, dflt = _D(0), _D(0)
+        _check(load_library().rsot_autotune(self._h, float(eps), pt.data_ptr(), int(reps),
+                                            ctypes.byref(sb), ctypes.byref(st), ctypes.byref(best),
+                                            ctypes.byref(dflt)), "rsot_autotune")
+        return {"seg_blocks": sb.value, "seg_tiles": st.value, "best_ms": best.value,
+                "default_ms": dflt.value}
+
+    def set_tuning(self, seg_blocks, seg_tiles):
+        _check(load_library().rsot_set_tuning(self._h, int(seg_blocks), int(seg_tiles)),
+               "rsot_set_tuning")
+
     def lse(self):
         torch = _torch()
         out = torch.empty(self.nq, dtype=torch.float64, device="cuda")
@@ -342,15 +390,10 @@ class Problem:
                "rsot_get_partition")
         return t, b, nt.value, nb.value
 
-    def solve(self, eps_schedule, psi0=None, tol=1e-6, max_iter=10000, lbfgs_m=10,
-              stage_tol=0.0, callback=None, max_ls=20):
-        """rsot_solve: returns (psi numpy array, info dict). Raises on error
-        codes other than NOT_CONVERGED (reported in info['status'])."""
-        lib = load_library()
-        eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
-        psi = np.zeros(self.n) if psi0 is None else np.array(psi0, dtype=np.float64)
+    @staticmethod
+    def _solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback, max_ls):
         sp = SolveParams()
-        lib.rsot_solve_params_default(ctypes.byref(sp))
+        load_library().rsot_solve_params_default(ctypes.byref(sp))
         sp.eps_schedule = eps_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         sp.n_eps = eps_arr.shape[0]
         sp.tol = tol
@@ -364,11 +407,38 @@ class Problem:
                 return int(bool(callback(ptr.contents)))
             cb = CALLBACK(_cb)
             sp.callback = cb
+        return sp, cb
+
+    def solve(self, eps_schedule, psi0=None, tol=1e-6, max_iter=10000, lbfgs_m=10,
+              stage_tol=0.0, callback=None, max_ls=20):
+        """rsot_solve: returns (psi numpy array, info dict). Raises on error
+        codes other than NOT_CONVERGED (reported in info['status'])."""
+        eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
+        psi = np.zeros(self.n) if psi0 is None else np.array(psi0, dtype=np.float64)
+        sp, _keep = self._solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback,
+                                       max_ls)
         info = SolveInfo()
-        rc = lib.rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data, ctypes.byref(info))
+        rc = load_library().rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data,
+                                       ctypes.byref(info))
         if rc not in (OK, ERR_NOT_CONVERGED):
             raise RsotError(rc, "rsot_solve")
         return psi, info.as_dict()
+
+    def solve_learned(self, mlp, cond, eps_schedule, tol=1e-6, max_iter=10000, lbfgs_m=10,
+                      stage_tol=0.0, max_ls=20):
+        """rsot_solve_learned: returns (psi, solve info dict, learned info
+        dict). cond = (c0, c1, s, eps) of the instance."""
+        eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
+        c = np.ascontiguousarray(cond, dtype=np.float64)
+        psi = np.zeros(self.n)
+        sp, _keep = self._solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, None, max_ls)
+        info, linfo = SolveInfo(), LearnedInfo()
+        rc = load_library().rsot_solve_learned(self._h, mlp.handle, c.ctypes.data,
+                                               ctypes.byref(sp), psi.ctypes.data,
+                                               ctypes.byref(info), ctypes.byref(linfo))
+        if rc not in (OK, ERR_NOT_CONVERGED):
+            raise RsotError(rc, "rsot_solve_learned")
+        return psi, info.as_dict(), linfo.as_dict()
 
 
 def multilevel_indices(n_source_levels: int, n_target_levels: int, l: int):
@@ -484,3 +554,165 @@ def dual_eval_batched(problems, eps, psis, want_grad=True):
     _check(load_library().rsot_dual_eval_batched(hs, n, e, pp, J, gp, infos, ctypes.byref(ms)),
            "rsot_dual_eval_batched")
     return list(J), grads, [i.as_dict() for i in infos], ms.value
+
+
+def shape_class(dim, nq, n, eps, truncation):
+    """Key of the autotuner cache: dimension, log2 sizes, decade of eps, rule."""
+    import math
+    return f"d{dim}_q{int(round(math.log2(nq)))}_n{int(round(math.log2(n)))}" \
+           f"_e{int(math.floor(math.log10(eps)))}_{truncation}"
+
+
+def tuned(problem, psi, eps, truncation, cache_path, reps=2):
+    """Applies cached tuning for the problem's shape class, or runs the
+    autotuner and stores the result in the JSON cache."""
+    import json
+    key = shape_class(problem.dim, problem.nq, problem.n, eps, truncation)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if key in cache:
+        problem.set_tuning(cache[key]["seg_blocks"], cache[key]["seg_tiles"])
+        return dict(cache[key], cached=True)
+    res = problem.autotune(psi, eps, reps=reps)
+    cache[key] = res
+    if cache_path:
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return dict(res, cached=False)
+
+
+def _dev_f32(t, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t, dtype=np.float32), device="cuda")
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+class MLP:
+    """Owns an rsot_mlp handle (include/rsot_mlp.h): the warm-start network,
+    its training kernels and its prediction. Device arrays are CUDA tensors."""
+
+    def __init__(self, params, stream=0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAMS,):
+            raise ValueError(f"expected {MLP_NPARAMS} parameters")
+        h = _P()
+        _check(load_library().rsot_mlp_create(p.ctypes.data, stream, ctypes.byref(h)),
+               "rsot_mlp_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().rsot_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self, which=0):
+        out = np.empty(MLP_NPARAMS, dtype=np.float32)
+        _check(load_library().rsot_mlp_get_params(self._h, int(which), out.ctypes.data),
+               "rsot_mlp_get_params")
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load_library().rsot_mlp_set_params(self._h, p.ctypes.data), "rsot_mlp_set_params")
+
+    def set_normalization(self, feat_mean, feat_std, out_mean, out_std):
+        fm = np.ascontiguousarray(feat_mean, dtype=np.float32)
+        fs = np.ascontiguousarray(feat_std, dtype=np.float32)
+        _check(load_library().rsot_mlp_set_normalization(self._h, fm.ctypes.data, fs.ctypes.data,
+                                                         float(out_mean), float(out_std)),
+               "rsot_mlp_set_normalization")
+
+    def normalization(self):
+        fm, fs = np.empty(6, dtype=np.float32), np.empty(6, dtype=np.float32)
+        om, osd = _F(), _F()
+        _check(load_library().rsot_mlp_get_normalization(self._h, fm.ctypes.data, fs.ctypes.data,
+                                                         ctypes.byref(om), ctypes.byref(osd)),
+               "rsot_mlp_get_normalization")
+        return fm, fs, om.value, osd.value
+
+    def fit_normalization(self, feats, target):
+        f = _dev_f32(feats)
+        t = _dev_f32(target)
+        rows = t.numel()
+        if f.numel() != 6 * rows:
+            raise ValueError("feature rows and targets differ in count")
+        _check(load_library().rsot_mlp_fit_normalization(self._h, f.data_ptr(), t.data_ptr(),
+                                                         rows), "rsot_mlp_fit_normalization")
+
+    def forward(self, feats):
+        torch = _torch()
+        f = _dev_f32(feats)
+        rows = f.numel() // 6
+        out = torch.empty(rows, dtype=torch.float32, device="cuda")
+        _check(load_library().rsot_mlp_forward(self._h, f.data_ptr(), rows, out.data_ptr()),
+               "rsot_mlp_forward")
+        return out
+
+    def backward(self, feats, dout):
+        torch = _torch()
+        f = _dev_f32(feats)
+        rows = f.numel() // 6
+        d = _dev_f32(dout, rows)
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        _check(load_library().rsot_mlp_backward(self._h, f.data_ptr(), rows, d.data_ptr(),
+                                                g.data_ptr()), "rsot_mlp_backward")
+        return g
+
+    def adam_step(self, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        g = _dev_f32(grad, MLP_NPARAMS)
+        _check(load_library().rsot_mlp_adam_step(self._h, g.data_ptr(), lr, b1, b2, eps),
+               "rsot_mlp_adam_step")
+
+    def train_step(self, feats, target, idx=None, rows=None, lr=1e-3, b1=0.9, b2=0.999,
+                   eps=1e-8, want_loss=True):
+        """One fused step on the device tables feats (N x 6) / target (N); idx
+        (int64 CUDA tensor of row numbers) selects the batch."""
+        if rows is None:
+            rows = idx.numel() if idx is not None else target.numel()
+        loss = _D(0.0)
+        _check(load_library().rsot_mlp_train_step(
+            self._h, feats.data_ptr(), target.data_ptr(),
+            idx.data_ptr() if idx is not None else None, int(rows), lr, b1, b2, eps,
+            ctypes.byref(loss) if want_loss else None), "rsot_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def predict_psi(self, y, nu, cond):
+        torch = _torch()
+        yt = _dev_f64(y)
+        n = yt.numel() // 2
+        nt = _dev_f64(nu, n)
+        c = np.ascontiguousarray(cond, dtype=np.float64)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(load_library().rsot_mlp_predict_psi(self._h, n, yt.data_ptr(), nt.data_ptr(),
+                                                   c.ctypes.data, out.data_ptr()),
+               "rsot_mlp_predict_psi")
+        return out
+
+
+def mlp_features(y, cond):
+    """rsot_mlp_features: (y0, y1, c0, c1, s, log eps) rows on the device."""
+    torch = _torch()
+    yt = _dev_f64(y)
+    n = yt.numel() // 2
+    c = np.ascontiguousarray(cond, dtype=np.float64)
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    _check(load_library().rsot_mlp_features(n, yt.data_ptr(), c.ctypes.data, out.data_ptr(),
+                                            None), "rsot_mlp_features")
+    return out

@@ -1,6 +1,7 @@
 """CPU-side checks of the C ABI: the library builds, loads and exports every
-symbol include/rsot.h declares; the Python binding binds the same names.
-No compute call is made (there is no GPU here)."""
+symbol the headers under include/ declare; the Python binding binds the same
+names. No compute call is made (there is no GPU here)."""
+import glob
 import os
 import re
 import subprocess
@@ -8,20 +9,22 @@ import subprocess
 from paper_2507_23602_amd import rsot
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rsot.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_symbols():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"\b(rsot_[a-z_0-9]+)\s*\(", src))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rsot_[a-z_0-9]+)\s*\(", src))
     return {n for n in names if not n.endswith("_t")}
 
 
 def test_header_declares_expected_calls():
     names = declared_symbols()
     for n in ["rsot_problem_create", "rsot_dual_eval", "rsot_solve", "rsot_problem_destroy",
-              "rsot_status_string", "rsot_options_default"]:
+              "rsot_status_string", "rsot_options_default", "rsot_mlp_train_step",
+              "rsot_solve_learned"]:
         assert n in names
 
 

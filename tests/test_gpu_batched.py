@@ -66,3 +66,28 @@ def test_batched_against_oracle():
         ej = abs(J[k] - ref.J) / abs(ref.J)
         _say(f"  instance {k}: nq={p.nq} n={p.n} eps={p.eps:.2e} ej={ej:.2e} eg={eg:.2e}")
         assert ej <= 1e-9 and eg <= 1e-6
+
+
+def test_autotune_choice_is_valid_and_equivalent():
+    import torch
+    from paper_2507_23602_amd import rsot
+    _say("autotune")
+    p = W.cube_mixture(16, 8192, 2e-3)
+    pr = rsot.Problem(p.x, p.mu, p.y, p.nu, truncation="tile", tau=1e-10)
+    psi = torch.as_tensor(W.random_psi(2, p.n, p.eps), device="cuda")
+    r0 = pr.dual_eval(psi, p.eps)                     # dense, sets |J_ref|
+    r1 = pr.dual_eval(psi, p.eps)
+    res = pr.autotune(psi, p.eps, reps=2)
+    _say(f"  {res}")
+    assert res["seg_blocks"] in (0, 64, 128, 256, 512, 1024)
+    assert res["seg_tiles"] in (0, 16, 32, 64, 128, 256, 512, 1024, 4096)
+    assert res["best_ms"] <= res["default_ms"]
+    r2 = pr.dual_eval(psi, p.eps)
+    assert r2.info["kept_pairs"] == r1.info["kept_pairs"]
+    # Another objective-pass segmentation gives each work item another
+    # reference exponent for its FP32 chunk sums, so the two evaluations
+    # round differently; both must stay inside the mixed-precision bounds
+    # (objective 1e-9 relative, gradient 1e-6), checked against each other.
+    assert abs(r2.J - r1.J) <= 1e-9 * abs(r1.J)
+    g1, g2 = r1.grad.cpu().numpy(), r2.grad.cpu().numpy()
+    assert np.max(np.abs(g1 - g2) / (p.nu + g1 + p.nu)) < 1e-6
