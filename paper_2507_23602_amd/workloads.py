@@ -389,3 +389,16 @@ def config3(rings: int = 60, levels: int = 4, n_targets: int = 1 << 20,
     return {"sources": sources, "y": y, "nu": nu, "target_levels": list(target_levels),
             "eps": eps, "level": level,
             "name": f"disk{rings}r_L{levels}_nq{sources[-1][0].shape[0]}_n{n_targets}"}
+
+
+def mlp_init_params(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the 6-256x4-1 warm-start network, flat
+    FP32 in the library's order (W0[6][256] b0 W1[256][256] b1 W2 b2 W3 b3
+    W4[256] b4): every weight and bias ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in))."""
+    rng = np.random.default_rng(seed)
+    blocks = []
+    for fan_in, fan_out in [(6, 256), (256, 256), (256, 256), (256, 256), (256, 1)]:
+        a = 1.0 / np.sqrt(fan_in)
+        blocks.append(rng.uniform(-a, a, size=fan_in * fan_out))
+        blocks.append(rng.uniform(-a, a, size=fan_out))
+    return np.concatenate(blocks).astype(np.float32)
