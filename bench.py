@@ -59,6 +59,12 @@ def main():
                     help="also time N uneven 3D instances: one batched call vs single calls")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
+    ap.add_argument("--mlp", type=str, default="",
+                    help="time the warm-start network kernels: 'ROWS,STEPS' training steps "
+                         "and forward passes on synthetic rows (e.g. 65536,20)")
+    ap.add_argument("--learned", type=str, default="",
+                    help="learned warm start on the blob family: 'TRAIN,TEST,EPOCHS' "
+                         "(e.g. 448,64,20): dataset from the solver, training, comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -204,11 +210,97 @@ def main():
         out.setdefault("extras", {})["multilevel"] = multilevel_leg()
     if args.batched:
         out.setdefault("extras", {})["batched"] = batched_leg(args.batched)
+    if args.mlp:
+        rows, steps = (int(v) for v in args.mlp.split(","))
+        out.setdefault("extras", {})["mlp"] = mlp_leg(rows, steps)
+    if args.learned:
+        n_train, n_test, epochs = (int(v) for v in args.learned.split(","))
+        out.setdefault("extras", {})["learned"] = learned_leg(n_train, n_test, epochs)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
                                            psi1 if not args.no_extras else None)
     print(json.dumps(out), flush=True)
+
+
+MLP_FWD_FLOP_PER_ROW = 2 * (6 * 256 + 3 * 256 * 256 + 256)      # multiply-adds x 2
+MLP_TRAIN_FLOP_PER_ROW = 3 * MLP_FWD_FLOP_PER_ROW                # forward + data and weight grads
+
+
+def mlp_leg(rows, steps):
+    """Warm-start network kernels on synthetic rows: fused training steps
+    (forward, MSE, backward, Adam) and forward passes, device time per call
+    with HIP events on the library's stream, against the dense bf16 MFMA peak."""
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+    rng = np.random.default_rng(3)
+    f = np.empty((rows, 6), dtype=np.float32)
+    f[:, :2] = rng.uniform(0, 1, (rows, 2))
+    f[:, 2:4] = rng.uniform(0.2, 0.8, (rows, 2))
+    f[:, 4] = rng.uniform(0.05, 0.2, rows)
+    f[:, 5] = np.log(rng.uniform(1e-3, 1e-1, rows))
+    t = (0.05 * np.sin(4 * f[:, 0]) * np.cos(3 * f[:, 1])).astype(np.float32)
+    ft, tt = torch.as_tensor(f, device="cuda"), torch.as_tensor(t, device="cuda")
+    m = rsot.MLP(W.mlp_init_params(0))
+    m.fit_normalization(ft, tt)
+    for _ in range(2):
+        m.train_step(ft, tt, None, want_loss=False)
+        m.forward(ft)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        m.train_step(ft, tt, None, want_loss=False)
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / steps
+    e0.record()
+    for _ in range(steps):
+        m.forward(ft)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / steps
+    peak = 2.5e15
+    tr = MLP_TRAIN_FLOP_PER_ROW * rows / (t_train * 1e-3)
+    fw = MLP_FWD_FLOP_PER_ROW * rows / (t_fwd * 1e-3)
+    log(f"[bench] mlp: {rows} rows, train step {t_train:.3f} ms ({tr / 1e12:.1f} TFLOP/s), "
+        f"forward {t_fwd:.3f} ms ({fw / 1e12:.1f} TFLOP/s); bf16 dense peak 2500 TFLOP/s")
+    return {"rows": rows, "steps": steps, "train_step_ms": t_train, "forward_ms": t_fwd,
+            "train_tflops": tr / 1e12, "forward_tflops": fw / 1e12, "peak_tflops": peak / 1e12,
+            "train_frac": tr / peak, "forward_frac": fw / peak}
+
+
+def learned_leg(n_train, n_test, epochs):
+    """Learned warm start (blob family: 128x128 mesh x 3 points = 98,304
+    quadrature points, 65,536 fixed uniform targets, eps logU[1e-3,1e-1]):
+    instances 0..n_train-1 are solved from zero to make the dataset, the
+    network is trained on it with the library's kernels, and the next n_test
+    instances are solved from zero, from the learned start and from the
+    multilevel start, to ||grad||_1 < 1e-6."""
+    import torch
+    from paper_2507_23602_amd import warmstart as WS
+    t0 = time.perf_counter()
+    train_ids = list(range(n_train))
+    test_ids = list(range(n_train, n_train + n_test))
+    feats, target, drecs = WS.build_dataset(train_ids)
+    t_data = time.perf_counter() - t0
+    tf, tt, _ = WS.build_dataset(test_ids[:min(8, n_test)], every=8)   # held-out loss only
+    t1 = time.perf_counter()
+    m, tlog = WS.train(feats, target, epochs=epochs, test=(tf, tt))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    rows = target.numel()
+    del feats, target
+    recs = WS.compare(m, test_ids)
+    summ = WS.summarize(recs)
+    log(f"[bench] learned: dataset {t_data:.1f}s ({n_train} solves), training {t_train:.1f}s "
+        f"({epochs} epochs x {rows} rows); test {summ}")
+    return {"workload": "blob_square128_tri3_nq98304_n65536", "train_instances": n_train,
+            "test_instances": n_test, "dataset_seconds": t_data, "train_seconds": t_train,
+            "train_rows": rows, "epochs": epochs, "train_log": tlog, "summary": summ,
+            "dataset_mean_iterations": float(np.mean([r["iterations"] for r in drecs])),
+            "dataset_mean_seconds": float(np.mean([r["seconds"] for r in drecs])),
+            "per_instance": recs}
 
 
 def batched_leg(k):

@@ -608,29 +608,32 @@ struct rsot_mlp {
     double *dloss = nullptr, *dmom = nullptr;
     int *dflag = nullptr;
     int64_t step = 0;
-    // workspace, sized for cap rows
-    int64_t cap = 0;
-    bool cap_train = false;
+    // training workspace, sized for cap_tr rows
+    int64_t cap_tr = 0;
     float *Z[4] = {nullptr, nullptr, nullptr, nullptr};
     uint16_t *H[4] = {nullptr, nullptr, nullptr, nullptr};
     uint16_t *HT[3] = {nullptr, nullptr, nullptr};
     uint16_t *dZ[2] = {nullptr, nullptr};
     uint16_t *dZT = nullptr;
-    float *F = nullptr, *outb = nullptr, *partW = nullptr, *partS = nullptr;
+    float *F = nullptr, *partW = nullptr, *partS = nullptr;
     double *lossp = nullptr;
+    std::vector<void *> ws_tr;
+    // inference workspace, sized for cap_inf rows
+    int64_t cap_inf = 0;
+    uint16_t *Hi[2] = {nullptr, nullptr};
+    float *outb = nullptr;
+    std::vector<void *> ws_inf;
     float *featb = nullptr;                             // feature rows of predictions
     int64_t featb_cap = 0;
-    std::vector<void *> ws;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 
-    void free_ws() {
-        for (void *p : ws) (void)hipFree(p);
-        ws.clear();
-        cap = 0;
-        cap_train = false;
+    static void free_list(std::vector<void *> &v) {
+        for (void *p : v) (void)hipFree(p);
+        v.clear();
     }
     ~rsot_mlp() {
-        free_ws();
+        free_list(ws_tr);
+        free_list(ws_inf);
         for (void *p : {(void *)P, (void *)Mm, (void *)Vv, (void *)W0b, (void *)Wb, (void *)WTb,
                         (void *)w4b, (void *)norm, (void *)grad, (void *)dloss, (void *)dmom,
                         (void *)dflag, (void *)featb})
@@ -643,40 +646,51 @@ struct rsot_mlp {
 static int64_t padded_rows(int64_t R) { return (R + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
 
 template <typename T>
-static rsot_status ws_alloc(rsot_mlp *m, T **p, size_t count) {
+static rsot_status ws_alloc(std::vector<void *> &list, T **p, size_t count) {
     void *q = nullptr;
     if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
         (void)hipGetLastError();
         return RSOT_ERR_OOM;
     }
-    m->ws.push_back(q);
+    list.push_back(q);
     *p = (T *)q;
     return RSOT_OK;
 }
 
-static rsot_status ensure_ws(rsot_mlp *m, int64_t RP, bool train) {
-    if (RP <= m->cap && (!train || m->cap_train)) return RSOT_OK;
-    const int64_t cap = std::max(RP, m->cap);
+// Training and inference keep separate workspaces, each grown to the largest
+// padded row count it has seen, so that alternating the two (a held-out
+// forward between training steps) reallocates nothing.
+static rsot_status ensure_train_ws(rsot_mlp *m, int64_t RP) {
+    if (RP <= m->cap_tr) return RSOT_OK;
     RSOT_HIP(hipStreamSynchronize(m->stream));
-    m->free_ws();
-    const size_t rw = (size_t)cap * WID;
-    if (train) {
-        for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(m, &m->Z[l], rw));
-        for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(m, &m->H[l], rw));
-        for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(m, &m->HT[l], rw));
-        for (int l = 0; l < 2; ++l) RSOT_TRY(ws_alloc(m, &m->dZ[l], rw));
-        RSOT_TRY(ws_alloc(m, &m->dZT, rw));
-        RSOT_TRY(ws_alloc(m, &m->F, (size_t)cap * 8));
-        RSOT_TRY(ws_alloc(m, &m->partW, (size_t)(cap / CHUNK_DW) * 3 * WID * WID));
-        RSOT_TRY(ws_alloc(m, &m->partS, (size_t)(cap / SLOT) * S_N));
-        RSOT_TRY(ws_alloc(m, &m->lossp, (size_t)(cap / SLOT)));
-    } else {
-        RSOT_TRY(ws_alloc(m, &m->H[0], rw));
-        RSOT_TRY(ws_alloc(m, &m->H[1], rw));
-    }
-    RSOT_TRY(ws_alloc(m, &m->outb, (size_t)cap));
-    m->cap = cap;
-    m->cap_train = train;
+    rsot_mlp::free_list(m->ws_tr);
+    m->cap_tr = 0;
+    auto &L = m->ws_tr;
+    const size_t rw = (size_t)RP * WID;
+    for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(L, &m->Z[l], rw));
+    for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(L, &m->H[l], rw));
+    for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(L, &m->HT[l], rw));
+    for (int l = 0; l < 2; ++l) RSOT_TRY(ws_alloc(L, &m->dZ[l], rw));
+    RSOT_TRY(ws_alloc(L, &m->dZT, rw));
+    RSOT_TRY(ws_alloc(L, &m->F, (size_t)RP * 8));
+    RSOT_TRY(ws_alloc(L, &m->partW, (size_t)(RP / CHUNK_DW) * 3 * WID * WID));
+    RSOT_TRY(ws_alloc(L, &m->partS, (size_t)(RP / SLOT) * S_N));
+    RSOT_TRY(ws_alloc(L, &m->lossp, (size_t)(RP / SLOT)));
+    m->cap_tr = RP;
+    return RSOT_OK;
+}
+
+static rsot_status ensure_inf_ws(rsot_mlp *m, int64_t RP) {
+    if (RP <= m->cap_inf) return RSOT_OK;
+    RSOT_HIP(hipStreamSynchronize(m->stream));
+    rsot_mlp::free_list(m->ws_inf);
+    m->cap_inf = 0;
+    auto &L = m->ws_inf;
+    const size_t rw = (size_t)RP * WID;
+    RSOT_TRY(ws_alloc(L, &m->Hi[0], rw));
+    RSOT_TRY(ws_alloc(L, &m->Hi[1], rw));
+    RSOT_TRY(ws_alloc(L, &m->outb, (size_t)RP));
+    m->cap_inf = RP;
     return RSOT_OK;
 }
 
@@ -698,11 +712,11 @@ static rsot_status run_forward(rsot_mlp *m, const float *feats, const int64_t *i
     } else {
         hipLaunchKernelGGL(k_mlp_in<false>, dim3((unsigned)(RP / 16)), dim3(256), 0, st, feats, idx,
                            R, RP, m->norm, m->W0b, bias[0], (float *)nullptr, (float *)nullptr,
-                           m->H[0], (uint16_t *)nullptr);
+                           m->Hi[0], (uint16_t *)nullptr);
         for (int l = 1; l < 4; ++l)
             hipLaunchKernelGGL((k_mlp_gemm<EPI_FWD, false>), dim3(gemm_grid(RP)), dim3(256), 0,
-                               st, m->H[(l - 1) & 1], m->WTb + (size_t)(l - 1) * WID * WID,
-                               bias[l], (const float *)nullptr, RP, (float *)nullptr, m->H[l & 1],
+                               st, m->Hi[(l - 1) & 1], m->WTb + (size_t)(l - 1) * WID * WID,
+                               bias[l], (const float *)nullptr, RP, (float *)nullptr, m->Hi[l & 1],
                                (uint16_t *)nullptr);
     }
     return hipGetLastError() == hipSuccess ? RSOT_OK : RSOT_ERR_DEVICE;
@@ -896,10 +910,10 @@ extern "C" rsot_status rsot_mlp_forward(rsot_mlp *m, const float *feats, int64_t
     if (!m || rows < 0 || (rows > 0 && (!feats || !out))) return RSOT_ERR_INVALID_ARG;
     if (rows == 0) return RSOT_OK;
     const int64_t RP = padded_rows(rows);
-    RSOT_TRY(ensure_ws(m, RP, false));
+    RSOT_TRY(ensure_inf_ws(m, RP));
     RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, false));
     hipLaunchKernelGGL(k_mlp_out<0>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->H[1], (const float *)nullptr, m->w4b,
+                       m->Hi[1], (const float *)nullptr, m->w4b,
                        m->P + OFF_B4, m->norm, (const float *)nullptr, (const float *)nullptr,
                        (const int64_t *)nullptr, rows, RP, out, (uint16_t *)nullptr,
                        (uint16_t *)nullptr, (float *)nullptr, (double *)nullptr);
@@ -911,10 +925,10 @@ extern "C" rsot_status rsot_mlp_forward(rsot_mlp *m, const float *feats, int64_t
 // prediction of `rows` feature rows into m->outb (no synchronisation)
 static rsot_status predict_rows(rsot_mlp *m, const float *feats, int64_t rows) {
     const int64_t RP = padded_rows(rows);
-    RSOT_TRY(ensure_ws(m, RP, false));
+    RSOT_TRY(ensure_inf_ws(m, RP));
     RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, false));
     hipLaunchKernelGGL(k_mlp_out<0>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->H[1], (const float *)nullptr, m->w4b, m->P + OFF_B4, m->norm,
+                       m->Hi[1], (const float *)nullptr, m->w4b, m->P + OFF_B4, m->norm,
                        (const float *)nullptr, (const float *)nullptr, (const int64_t *)nullptr,
                        rows, RP, m->outb, (uint16_t *)nullptr, (uint16_t *)nullptr,
                        (float *)nullptr, (double *)nullptr);
@@ -940,11 +954,11 @@ extern "C" rsot_status rsot_mlp_backward(rsot_mlp *m, const float *feats, int64_
                                          const float *dout, float *grad) {
     if (!m || rows < 1 || !feats || !dout || !grad) return RSOT_ERR_INVALID_ARG;
     const int64_t RP = padded_rows(rows);
-    RSOT_TRY(ensure_ws(m, RP, true));
+    RSOT_TRY(ensure_train_ws(m, RP));
     RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, true));
     hipLaunchKernelGGL(k_mlp_out<2>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
                        m->H[3], m->Z[3], m->w4b, m->P + OFF_B4, m->norm, (const float *)nullptr,
-                       dout, (const int64_t *)nullptr, rows, RP, m->outb, m->dZ[0], m->dZT,
+                       dout, (const int64_t *)nullptr, rows, RP, (float *)nullptr, m->dZ[0], m->dZT,
                        m->partS, m->lossp);
     RSOT_HIP(hipGetLastError());
     RSOT_TRY(run_backward(m, rows, RP, grad, nullptr));
@@ -983,11 +997,11 @@ extern "C" rsot_status rsot_mlp_train_step(rsot_mlp *m, const float *feats, cons
     if (!m || rows < 1 || !feats || !target || !adam_args_ok(lr, b1, b2, eps))
         return RSOT_ERR_INVALID_ARG;
     const int64_t RP = padded_rows(rows);
-    RSOT_TRY(ensure_ws(m, RP, true));
+    RSOT_TRY(ensure_train_ws(m, RP));
     RSOT_TRY(run_forward(m, feats, idx, rows, RP, true));
     hipLaunchKernelGGL(k_mlp_out<1>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
                        m->H[3], m->Z[3], m->w4b, m->P + OFF_B4, m->norm, target,
-                       (const float *)nullptr, idx, rows, RP, m->outb, m->dZ[0], m->dZT, m->partS,
+                       (const float *)nullptr, idx, rows, RP, (float *)nullptr, m->dZ[0], m->dZT, m->partS,
                        m->lossp);
     RSOT_HIP(hipGetLastError());
     RSOT_TRY(run_backward(m, rows, RP, m->grad, m->dloss));

@@ -1,0 +1,200 @@
+"""Learned warm start on the Gaussian-blob family: dataset, training and the
+comparison against the paper's starts.
+
+Python only orders the calls: the dataset is made by the library's solver
+(Alg. 1 with the eps schedule of Sec. 4.2), the network is trained with the
+library's fused forward/backward/Adam kernels, and every comparison solve is
+a library call. Instances: ``workloads.config4_instance`` (blob centre c,
+width s, eps; fixed cloud of uniform targets).
+"""
+from __future__ import annotations
+
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import rsot
+from . import workloads as W
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def eps_schedule(eps: float, eps0: float = 0.1):
+    """eps * 2^K, ..., 2 eps, eps with eps * 2^K <= eps0 (Sec. 4.2)."""
+    K = max(0, int(math.floor(math.log2(eps0 / eps) + 1e-12)))
+    return [eps * 2.0 ** k for k in range(K, 0, -1)] + [eps]
+
+
+def cond_of(p):
+    return (float(p.meta["c"][0]), float(p.meta["c"][1]), float(p.meta["s"]), float(p.eps))
+
+
+def make_problem(p, truncation="tile"):
+    return rsot.Problem(p.x, p.mu, p.y, p.nu, truncation=truncation, tau=1e-12)
+
+
+def build_dataset(ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile", every=16):
+    """Solves every instance from zero with its eps schedule and returns the
+    device tables (features [rows, 6] float32, centred psi* [rows] float32)
+    plus per-instance records."""
+    import torch
+    n_rows = len(ids) * n_targets
+    feats = torch.empty((n_rows, 6), dtype=torch.float32, device="cuda")
+    target = torch.empty(n_rows, dtype=torch.float32, device="cuda")
+    recs = []
+    t0 = time.perf_counter()
+    for k, i in enumerate(ids):
+        p = W.config4_instance(i, n_cells=n_cells, n_targets=n_targets)
+        pr = make_problem(p, truncation)
+        ts = time.perf_counter()
+        psi, info = pr.solve(eps_schedule(p.eps), tol=tol)
+        dt = time.perf_counter() - ts
+        pr.close()
+        sl = slice(k * n_targets, (k + 1) * n_targets)
+        feats[sl] = rsot.mlp_features(torch.as_tensor(p.y, device="cuda"), cond_of(p))
+        target[sl] = torch.as_tensor(psi, device="cuda").float()
+        recs.append({"id": i, "eps": p.eps, "iterations": info["iterations"],
+                     "seconds": dt, "status": info["status"]})
+        if (k + 1) % every == 0 or k + 1 == len(ids):
+            _log(f"[warmstart] dataset {k + 1}/{len(ids)} ({time.perf_counter() - t0:.1f}s, "
+                 f"last: eps {p.eps:.2e}, {info['iterations']} it, {dt:.2f}s)")
+    return feats, target, recs
+
+
+def train(feats, target, epochs=20, batch=32768, lr=1e-3, lr_end=1e-5, seed=0, init_seed=0,
+          test=None):
+    """Adam with a cosine learning-rate decay over shuffled mini-batches;
+    returns the model and the per-epoch log. ``test`` = (feats, target)
+    tables for a held-out loss."""
+    import torch
+    m = rsot.MLP(W.mlp_init_params(init_seed))
+    m.fit_normalization(feats, target)
+    _, _, om, osd = m.normalization()
+    N = target.numel()
+    steps_per_epoch = (N + batch - 1) // batch
+    total = epochs * steps_per_epoch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    log = []
+    step = 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=gen, device="cuda")
+        loss = 0.0
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            cur = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * step / max(1, total)))
+            last = b == steps_per_epoch - 1
+            r = m.train_step(feats, target, idx, lr=cur, want_loss=last)
+            if last:
+                loss = r
+            step += 1
+        torch.cuda.synchronize()
+        rec = {"epoch": ep + 1, "train_batch_loss": loss, "seconds": time.perf_counter() - t0}
+        if test is not None:
+            pred = m.forward(test[0])
+            rec["test_loss"] = float((((pred - test[1]) / osd) ** 2).mean())
+        log.append(rec)
+        _log(f"[warmstart] epoch {ep + 1}/{epochs}: batch loss {loss:.3e}"
+             + (f", test loss {rec['test_loss']:.3e}" if test is not None else "")
+             + f" ({rec['seconds']:.1f}s)")
+    return m, log
+
+
+def _ml_stages(eps):
+    E = eps_schedule(eps)
+    while len(E) < 3:
+        E = [E[0]] + E
+    level = [0] * (len(E) - 2) + [1, 2]
+    return E, level
+
+
+def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
+            multilevel=True, coarse_cells=(32, 64), target_levels=(4096, 16384)):
+    """Held-out instances: wall-clock seconds and iterations to ||g||_1 < tol
+    from (a) zero with the eps schedule, (b) zero at the final eps alone,
+    (c) the learned start (rsot_solve_learned), (d) the combined multilevel
+    start (Sec. 5.3) with the eps schedule spread over the levels."""
+    import torch
+    out = []
+    hier = None
+    if multilevel:
+        p0 = W.config4_instance(ids[0], n_cells=n_cells, n_targets=n_targets)
+        th = time.perf_counter()
+        hier = rsot.target_hierarchy(torch.as_tensor(p0.y, device="cuda"),
+                                     torch.as_tensor(p0.nu, device="cuda"),
+                                     list(target_levels) + [n_targets], lloyd_iters=20, seed=6)
+        torch.cuda.synchronize()
+        hier_s = time.perf_counter() - th
+        _log(f"[warmstart] target hierarchy {[int(h[1].numel()) for h in hier]} in {hier_s:.2f}s "
+             "(shared by every instance: one fixed target cloud)")
+    for k, i in enumerate(ids):
+        p = W.config4_instance(i, n_cells=n_cells, n_targets=n_targets)
+        cond = cond_of(p)
+        sched = eps_schedule(p.eps)
+        rec = {"id": i, "eps": p.eps}
+        pr = make_problem(p, truncation)
+        ts = time.perf_counter()
+        psi_a, ia = pr.solve(sched, tol=tol)
+        rec["zero_sched"] = {"seconds": time.perf_counter() - ts, "iterations": ia["iterations"],
+                             "status": ia["status"]}
+        pr.close()
+        pr = make_problem(p, truncation)
+        ts = time.perf_counter()
+        _, ib = pr.solve([p.eps], tol=tol)
+        rec["zero_direct"] = {"seconds": time.perf_counter() - ts,
+                              "iterations": ib["iterations"], "status": ib["status"]}
+        pr.close()
+        pr = make_problem(p, truncation)
+        ts = time.perf_counter()
+        psi_c, ic, lc = pr.solve_learned(m, cond, sched, tol=tol)
+        rec["learned"] = {"seconds": time.perf_counter() - ts, "iterations": ic["iterations"],
+                          "status": ic["status"], "used_learned": lc["used_learned"],
+                          "predict_ms": lc["predict_ms"], "J_pred": lc["J_pred"],
+                          "J_zero": lc["J_zero"]}
+        pr.close()
+        scale = float(np.max(np.abs(psi_a)))
+        rec["learned"]["max_dpsi_vs_zero_sched"] = float(np.max(np.abs(psi_c - psi_a))) / scale
+        if multilevel:
+            srcs = []
+            for nc in coarse_cells:
+                q = W.gaussian_blob_square(nc, p.meta["c"], p.meta["s"], p.y, p.eps)
+                srcs.append((q.x, q.mu))
+            srcs.append((p.x, p.mu))
+            ml = rsot.Multilevel(srcs, hier, precision="mixed", truncation=truncation, tau=1e-12)
+            E, lev = _ml_stages(p.eps)
+            ts = time.perf_counter()
+            _, idd = ml.solve(E, lev, tol=tol, level_tol=10 * tol)
+            rec["multilevel"] = {"seconds": time.perf_counter() - ts,
+                                 "iterations": int(sum(idd["iterations"])),
+                                 "finest_iterations": int(idd["iterations"][-1]),
+                                 "status": idd["status"]}
+            ml.close()
+        out.append(rec)
+        _log(f"[warmstart] test {k + 1}/{len(ids)} eps {p.eps:.2e}: "
+             + ", ".join(f"{key} {rec[key]['seconds']:.3f}s/{rec[key]['iterations']}it"
+                         for key in ("zero_sched", "zero_direct", "learned", "multilevel")
+                         if key in rec)
+             + f" (learned used: {rec['learned']['used_learned']})")
+    return out
+
+
+def summarize(recs):
+    keys = [k for k in ("zero_sched", "zero_direct", "learned", "multilevel") if k in recs[0]]
+    s = {}
+    for k in keys:
+        secs = np.array([r[k]["seconds"] for r in recs])
+        its = np.array([r[k]["iterations"] for r in recs])
+        ok = np.array([r[k]["status"] == rsot.OK for r in recs])
+        s[k] = {"total_seconds": float(secs.sum()), "median_seconds": float(np.median(secs)),
+                "mean_iterations": float(its.mean()), "converged": int(ok.sum())}
+    s["learned_used"] = int(sum(r["learned"]["used_learned"] for r in recs))
+    s["instances"] = len(recs)
+    base = s["zero_sched"]["total_seconds"]
+    for k in keys:
+        s[k]["speedup_vs_zero_sched"] = base / max(s[k]["total_seconds"], 1e-12)
+    return s
