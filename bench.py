@@ -15,9 +15,11 @@ stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -39,6 +41,25 @@ PEAK_EXP = 256 * 2.4e9 * 32                # 1.966e13 exp/s
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dense_eval_cube64_n65536_hbm_traffic.md")
+EVAL_SOURCE = os.path.join(ROOT, "paper_2507_23602_amd", "csrc", "rsot_eval.hip")
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary (scaled by the plain-copy calibration it records), or
+    None when that summary was taken on another version of the kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    txt = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"kernel source sha256: ([0-9a-f]{64})", txt)
+    sha = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
+    if not m or m.group(1) != sha:
+        return None
+    m = re.search(re.escape(kernel) + r" HBM bytes per launch: ([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
 
 
 def pair_roofline(d: int, n_exp: int, n_ops: int) -> float:
@@ -125,13 +146,13 @@ def main():
     roof_p2 = pair_roofline(d, 1, 2 * d + 3)
     roof_all = pair_roofline(d, 2, 4 * d + 7)
     if p1 >= p2:
-        name, ms, peak = "objective pass (k_pass1, dense)", p1, roof_p1
+        name, key, ms, peak = "objective pass (k_pass1, dense)", "k_pass1", p1, roof_p1
     else:
-        name, ms, peak = "gradient pass (k_pass2, dense)", p2, roof_p2
+        name, key, ms, peak = "gradient pass (k_pass2, dense)", "k_pass2", p2, roof_p2
     achieved = pairs / (ms * 1e-3)
     roofline = {"bound": "alu", "kernel": name, "achieved": achieved / 1e9,
                 "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
-                "traffic": None,
+                "traffic": counter_traffic(key),
                 "eval_frac": value / roof_all, "eval_peak_Gpair_s": roof_all / 1e9}
 
     out = {"metric": "quad-target pairs/s for dual obj+grad (dense, truncated); "

@@ -78,7 +78,9 @@ typedef struct {
     double delta_thr;         /* pointwise threshold (PW); default 1e-12           */
     int inputs_on_device;     /* 1: x, mu, y, nu passed to create are device ptrs  */
     int seg_tiles;            /* gradient pass: point tiles per work item; 0=auto  */
-    int seg_blocks;           /* objective pass: target blocks per work item; 0=256 */
+    int seg_blocks;           /* objective pass: target blocks per work item; 0 = default
+                                 (dense: whole rows unless the tiles are too few to fill
+                                 the device; truncated rules: 256)                     */
     int64_t mem_limit_bytes;  /* cap on library device memory; 0 = none            */
 } rsot_options;
 

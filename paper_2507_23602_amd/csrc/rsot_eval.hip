@@ -653,11 +653,16 @@ __global__ __launch_bounds__(256) void k_pass2(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t b, w, e0, e1;
     if (MODE == MODE_DENSE) {
-        // the four wavefronts of a workgroup share the point segment
+        // Workgroup i is dispatched to XCD i % 8. Each XCD sweeps its own
+        // point segments (s = 8k + xcd), all block groups of one segment
+        // before the next, so the segment's point records stay in that XCD's
+        // L2 while every target block reads them. The four wavefronts of a
+        // workgroup share the segment.
         const int64_t nbg = (n_blocks + 3) / 4;
-        const int64_t sgi = blockIdx.x / nbg;
-        b = (blockIdx.x % nbg) * 4 + wave;
-        if (b >= n_blocks) return;
+        const int64_t kk = blockIdx.x >> 3;
+        const int64_t sgi = (kk / nbg) * 8 + (blockIdx.x & 7);
+        b = (kk % nbg) * 4 + wave;
+        if (sgi >= n_seg || b >= n_blocks) return;
         e0 = sgi * seg;
         e1 = std::min<int64_t>(e0 + seg, n_tiles);
         w = b * n_seg + sgi;
@@ -935,7 +940,7 @@ template <int D, bool F64, int MODE>
 static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t seg) {
     unsigned grid;
     if (MODE == MODE_DENSE)
-        grid = (unsigned)(((p->n_blocks + 3) / 4) * n_seg);
+        grid = (unsigned)(((p->n_blocks + 3) / 4) * ((n_seg + 7) / 8) * 8);
     else
         grid = (unsigned)((n_wi + 3) / 4);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
@@ -1032,10 +1037,20 @@ static rsot_status plan_begin(EvalPlan &e) {
     e.seg1_cfg = p->opt.seg_blocks > 0 ? p->opt.seg_blocks : RSOT_SEG1_DEFAULT;
     if (e.rule == RSOT_TRUNC_DENSE) {
         e.mode = MODE_DENSE;
+        // Dense rows all have n_blocks entries: by default one work item per
+        // tile, split only when the tiles alone cannot fill the device.
+        if (p->opt.seg_blocks <= 0) {
+            const int64_t want_items = 8192;
+            const int64_t nseg = std::max<int64_t>(1, (want_items + p->n_tiles - 1) / p->n_tiles);
+            e.seg1_cfg = (p->n_blocks + nseg - 1) / nseg;
+        }
         e.pw.seg1 = std::min<int64_t>(e.seg1_cfg, p->n_blocks);
         e.pw.n_seg1 = (p->n_blocks + e.pw.seg1 - 1) / e.pw.seg1;
         e.pw.n_items = p->n_tiles * e.pw.n_seg1;
-        int64_t n_seg = std::max<int64_t>(1, (32768 + p->n_blocks - 1) / p->n_blocks);
+        // default: segments of at most 512 tiles (1 MB of point records, kept
+        // in one XCD's L2), and at least 32,768 work items in all
+        int64_t n_seg = std::max<int64_t>((p->n_tiles + 511) / 512,
+                                          (32768 + p->n_blocks - 1) / p->n_blocks);
         if (seg_cfg > 0) n_seg = (p->n_tiles + seg_cfg - 1) / seg_cfg;
         n_seg = std::min<int64_t>(n_seg, p->n_tiles);
         e.seg = (p->n_tiles + n_seg - 1) / n_seg;
