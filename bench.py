@@ -407,7 +407,12 @@ def multilevel_leg():
     t_h = time.perf_counter() - t0
     ml = rsot.Multilevel(c3["sources"], levels, precision="mixed", truncation="tile", tau=1e-12)
     t0 = time.perf_counter()
-    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5)
+    def progress(it):
+        if it.iteration % 25 == 0:
+            log(f"[bench] multilevel: stage eps {it.eps:.2e}, iteration {it.iteration}, "
+                f"|g|_1 {it.grad_l1:.2e}, kept {it.kept_pairs:.3e}")
+        return 0
+    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5, callback=progress)
     t_s = time.perf_counter() - t0
     log(f"[bench] multilevel: hierarchy {t_h:.2f}s, solve {t_s:.2f}s, status {info['status']}, "
         f"|g|_1 {info['grad_l1']:.2e}, iterations {info['iterations']}, "

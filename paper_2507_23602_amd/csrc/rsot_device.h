@@ -24,6 +24,19 @@ __device__ inline int wave_sum_int(int v) {
     return v;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i to XCD
+// i % 8). xcd_group maps workgroup i to a group index so that each XCD runs
+// one contiguous range of groups: neighbouring work items, which read the
+// same point or target records, then share that XCD's L2. Launch
+// xcd_grid(n_groups) workgroups; a result >= n_groups means no work.
+__device__ __forceinline__ int64_t xcd_group(int64_t n_groups) {
+    const int64_t per = (n_groups + 7) / 8;
+    return (int64_t)(blockIdx.x & 7) * per + (int64_t)(blockIdx.x >> 3);
+}
+static inline unsigned xcd_grid(int64_t n_groups) {
+    return (unsigned)(((n_groups + 7) / 8) * 8);
+}
+
 // Lane 0's value of a 64-bit quantity, in scalar registers. The builtin
 // returns a signed int, so each half is widened through uint32_t: a plain
 // (uint64_t) cast would sign-extend the low half into the high one.

@@ -667,7 +667,10 @@ __global__ __launch_bounds__(256) void k_pass2(
         e1 = std::min<int64_t>(e0 + seg, n_tiles);
         w = b * n_seg + sgi;
     } else {
-        w = (int64_t)blockIdx.x * 4 + wave;
+        // items are block-major and blocks Morton-ordered: give each XCD a
+        // contiguous range of items
+        const int64_t g = xcd_group((n_wi + 3) / 4);
+        w = g * 4 + wave;
         if (w >= n_wi) return;
         b = wi_block[w];
         e0 = wi_range[2 * w];
@@ -942,7 +945,7 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
     if (MODE == MODE_DENSE)
         grid = (unsigned)(((p->n_blocks + 3) / 4) * ((n_seg + 7) / 8) * 8);
     else
-        grid = (unsigned)((n_wi + 3) / 4);
+        grid = xcd_grid((n_wi + 3) / 4);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
                        p->trec, p->tG, p->wi_block, p->wi_range, p->col_idx, p->n_tiles,
                        p->n_blocks, n_wi, n_seg, seg, p->gpart);
@@ -1632,7 +1635,8 @@ __global__ __launch_bounds__(256) void k_pass2_lse(
     const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
     const uint32_t *__restrict__ col_idx, int64_t n_wi, double *__restrict__ out) {
     const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w =
+        xcd_group((n_wi + 3) / 4) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= n_wi) return;
     const int64_t F = wi_block[w];
     const double4 rec = frec[F * 64 + lane];
@@ -1736,7 +1740,7 @@ rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coar
     hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((nfb + 255) / 256)), dim3(256), 0, p->stream,
                        cptr, wptr, nfb, seg, wblk, wrng);
     // 4. log-sum-exp gradient-pass loop and merge
-    const dim3 gw((unsigned)((n_wi + 3) / 4));
+    const dim3 gw(xcd_grid((n_wi + 3) / 4));
     const bool f64 = p->opt.precision == RSOT_PREC_FP64;
     if (p->dim == 2) {
         if (f64) hipLaunchKernelGGL((k_pass2_lse<2, true>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);

@@ -1,17 +1,24 @@
 // Learned warm start: the 6-256x4-1 GELU network, its training kernels and
 // the solve from its prediction.
 //
-// Layout (rows padded to RP, a multiple of 1024; padded rows carry zero
+// Layouts (rows padded to RP, a multiple of 1024; padded rows carry zero
 // features and zero loss gradient, so they change no parameter gradient):
-//   H_l   bf16 [RP][256]  activation of hidden layer l (row-major)
-//   HT_l  bf16 [256][RP]  the same, transposed (l = 0..2): operand of dW_{l+1}
-//   Z_l   fp32 [RP][256]  pre-activation (training only)
-//   dZ    bf16 [RP][256]  pre-activation gradient, ping-pong; dZT its transpose
-// The 256x256 layers are one MFMA kernel (v_mfma_f32_32x32x16_bf16) with the
-// whole bf16 weight matrix in LDS; a workgroup tile is 128 rows x 256
-// columns, four waves of 64 x 128. Weight gradients split the rows into
-// chunks of 1024, each writing its own partial; every other sum over rows
-// uses slots of 256 rows. One kernel then adds the partials in a fixed order.
+//   k-blocked bf16   X[c/16][r][c%16]       operand of the layer products
+//                                          (each MFMA operand load is 1 KB
+//                                          contiguous)
+//   row-blocked bf16 X[r/16][c][r%16]       operand of the weight gradients
+//   fragment FP32    per 32x32 block (r/32, c/32) in row-major block order,
+//                    inside it the MFMA accumulator order [g][lane][q]
+//                    (r%32 = 8g + 4(lane/32) + q, c%32 = lane%32): the
+//                    pre-activations, written and read as float4 by the
+//                    layer epilogues
+// The 256x256 layers run on v_mfma_f32_32x32x16_bf16 with the whole bf16
+// weight matrix in LDS; a workgroup of 8 waves owns 128 rows x 256 columns,
+// a wave 32 x 128. The output layer and the loss are fused into the last
+// layer's epilogue, the bias gradients into the epilogues that produce the
+// pre-activation gradients. Sums over rows go to per-workgroup (or per
+// 256-row slot) partials that one kernel adds in a fixed order, so repeated
+// calls give the same bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,16 +37,21 @@ constexpr int NIN = RSOT_MLP_IN;
 constexpr int KPAD = WID + 8;       // LDS row stride (bf16): 528 B, rows 4 banks apart
 constexpr int64_t ROW_ALIGN = 1024; // RP multiple; = CHUNK_DW
 constexpr int CHUNK_DW = 1024;      // rows per weight-gradient partial
-constexpr int SLOT = 256;           // rows per small-parameter partial
+constexpr int SLOT = 256;           // rows per input-layer partial
+constexpr int GW = 8;               // waves per layer workgroup (two per SIMD)
+constexpr int GROWS = GW / 2 * 32;  // rows per layer workgroup tile (128)
+constexpr int MAX_GRID = 256;       // layer workgroups (one per CU)
 
 // flat parameter offsets
-constexpr int64_t OFF_W0 = 0, OFF_B0 = 1536;
+constexpr int64_t OFF_B0 = 1536;
 constexpr int64_t OFF_W[4] = {0, 1792, 67584, 133376};
 constexpr int64_t OFF_B[4] = {1536, 67328, 133120, 198912};
 constexpr int64_t OFF_W4 = 199168, OFF_B4 = 199424;
 constexpr int64_t NPAR = RSOT_MLP_NPARAMS;
 static_assert(OFF_B4 + 1 == NPAR, "parameter layout");
-// small-parameter partial layout: W0 (1536) b0 (256) b1 b2 b3 (256 each) W4 (256) b4 (1)
+// partial layout per slot: W0 (1536) b0 (256) b1 b2 b3 (256 each) W4 (256) b4 (1).
+// W0, b0 come from the input-layer kernel (one slot per 256 rows); the rest
+// from the layer epilogues (one slot per workgroup).
 constexpr int S_W0 = 0, S_B0 = 1536, S_B1 = 1792, S_W4 = 2560, S_B4 = 2816, S_N = 2817;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -61,8 +73,27 @@ __device__ __forceinline__ float gelu_prime(float z) {
            z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
+// GELU and its derivative from one erf and one exp (same roundings as above)
+__device__ __forceinline__ void gelu_and_prime(float z, float &g, float &gp) {
+    const float phi = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    g = z * phi;
+    gp = phi + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
 __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
     return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
+}
+
+__host__ __device__ __forceinline__ int64_t kb_idx(int64_t r, int c, int64_t RP) {
+    return ((int64_t)(c >> 4) * RP + r) * 16 + (c & 15);
+}
+__host__ __device__ __forceinline__ int64_t rb_idx(int64_t r, int c) {
+    return ((r >> 4) * WID + c) * 16 + (r & 15);
+}
+// first element (q = 0) of the float4 holding rows r..r+3 (r % 4 = 0) of column c
+__host__ __device__ __forceinline__ int64_t fr_idx(int64_t r, int c) {
+    const int i = (int)(r & 31);
+    return (((r >> 5) * 8 + (c >> 5)) * 4 + (i >> 3)) * 256 + (((i >> 2) & 1) * 32 + (c & 31)) * 4;
 }
 
 __device__ __forceinline__ float wsum(float v) {
@@ -71,149 +102,337 @@ __device__ __forceinline__ float wsum(float v) {
     return v;
 }
 
+__device__ __forceinline__ uint2 pack4(const uint16_t h[4]) {
+    uint2 v;
+    v.x = h[0] | ((uint32_t)h[1] << 16);
+    v.y = h[2] | ((uint32_t)h[3] << 16);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // input layer: standardise, 6 -> 256 affine (FP32), GELU
 // ---------------------------------------------------------------------------
-// One workgroup = 16 rows, thread = output column. Training also keeps the
-// standardised features (for dW0), Z0 and the transposed activation.
+// One workgroup = 32 rows; thread (column block cbk, lane) owns column
+// cbk*32 + lane%32 and the 16 rows 8g + 4(lane/32) + q of the accumulator
+// layout, so every store matches the layer kernels' layouts. Training also
+// keeps the standardised features (for dW0), Z0 and the row-blocked copy.
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_mlp_in(const float *__restrict__ feats,
+__global__ __launch_bounds__(512) void k_mlp_in(const float *__restrict__ feats,
                                                 const int64_t *__restrict__ idx, int64_t R,
                                                 int64_t RP, const float *__restrict__ norm,
                                                 const uint16_t *__restrict__ W0b,
                                                 const float *__restrict__ b0,
                                                 float *__restrict__ Fout, float *__restrict__ Z0,
-                                                uint16_t *__restrict__ H0,
-                                                uint16_t *__restrict__ HT0) {
-    const int n = threadIdx.x;
+                                                uint16_t *__restrict__ Hkb,
+                                                uint16_t *__restrict__ Hrb) {
+    const int lane = threadIdx.x & 63, cbk = threadIdx.x >> 6;
+    const int li = lane & 31, lh = lane >> 5;
+    const int col = cbk * 32 + li;
     float w[NIN];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) w[f] = bf2f(W0b[f * WID + n]);
-    const float bb = b0[n];
-    const int64_t r0 = (int64_t)blockIdx.x * 16;
-    uint16_t hv[16];
+    for (int f = 0; f < NIN; ++f) w[f] = bf2f(W0b[f * WID + col]);
+    const float bb = b0[col];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-        const int64_t r = r0 + rr;
-        float F[NIN];
-        if (r < R) {
-            const int64_t src = idx ? idx[r] : r;
+    for (int g = 0; g < 4; ++g) {
+        const int64_t rb = r0 + 8 * g + 4 * lh;
+        float z4[4];
+        uint16_t h4[4];
 #pragma unroll
-            for (int f = 0; f < NIN; ++f) F[f] = (feats[src * NIN + f] - norm[f]) / norm[NIN + f];
-        } else {
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = rb + q;
+            float F[NIN];
+            if (r < R) {
+                const int64_t src = idx ? idx[r] : r;
 #pragma unroll
-            for (int f = 0; f < NIN; ++f) F[f] = 0.0f;
+                for (int f = 0; f < NIN; ++f)
+                    F[f] = (feats[src * NIN + f] - norm[f]) / norm[NIN + f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < NIN; ++f) F[f] = 0.0f;
+            }
+            float z = bb;
+#pragma unroll
+            for (int f = 0; f < NIN; ++f) z = fmaf(F[f], w[f], z);
+            z4[q] = z;
+            h4[q] = f2bf(gelu(z));
+            Hkb[kb_idx(r, col, RP)] = h4[q];
+            if (TRAIN && cbk == 0 && li < 8) {
+                float fv = 0.0f;
+#pragma unroll
+                for (int f = 0; f < NIN; ++f) fv = li == f ? F[f] : fv;
+                Fout[r * 8 + li] = fv;
+            }
         }
-        float z = bb;
-#pragma unroll
-        for (int f = 0; f < NIN; ++f) z = fmaf(F[f], w[f], z);
-        const uint16_t h = f2bf(gelu(z));
-        H0[r * WID + n] = h;
-        hv[rr] = h;
         if (TRAIN) {
-            Z0[r * WID + n] = z;
-            if (n < 8) Fout[r * 8 + n] = n < NIN ? F[n] : 0.0f;
+            *(float4 *)(Z0 + fr_idx(rb, col)) = make_float4(z4[0], z4[1], z4[2], z4[3]);
+            *(uint2 *)(Hrb + rb_idx(rb, col)) = pack4(h4);
         }
-    }
-    if (TRAIN) {
-        uint4 a, b;
-        a.x = hv[0] | ((uint32_t)hv[1] << 16);
-        a.y = hv[2] | ((uint32_t)hv[3] << 16);
-        a.z = hv[4] | ((uint32_t)hv[5] << 16);
-        a.w = hv[6] | ((uint32_t)hv[7] << 16);
-        b.x = hv[8] | ((uint32_t)hv[9] << 16);
-        b.y = hv[10] | ((uint32_t)hv[11] << 16);
-        b.z = hv[12] | ((uint32_t)hv[13] << 16);
-        b.w = hv[14] | ((uint32_t)hv[15] << 16);
-        uint4 *dst = (uint4 *)(HT0 + (int64_t)n * RP + r0);
-        dst[0] = a;
-        dst[1] = b;
     }
 }
 
 // ---------------------------------------------------------------------------
 // 256x256 layer on MFMA: C[RP][256] = A[RP][256] . B, B given as Bt[n][k]
 // ---------------------------------------------------------------------------
-// EPI_FWD:   z = C + bias; H = bf16(GELU(z)); training also stores Z and,
-//            if HT is given, the transposed H.
-// EPI_BWD:   C is dH of the layer below; dZ = bf16(C * GELU'(Zin)), stored
-//            row-major and, if DT is given, transposed.
-enum { EPI_FWD = 0, EPI_BWD = 1 };
+// EPI_FWD  hidden layer: z = C + bias, H = bf16(GELU(z)) k-blocked; training
+//          also stores z (fragment order) and H row-blocked.
+// EPI_OUT  last hidden layer fused with the output layer: o_r = H_r . W4 + b4
+//          (rows reduced across lanes and the two column waves through LDS);
+//          prediction writes o * std + mean; training forms the loss
+//          gradient d_r, dZ3 = bf16(d_r W4 GELU'(z)) in both bf16 layouts and
+//          the slot partials of b3 (column sums of dZ3), W4, b4 and the loss.
+// EPI_BWD  C is dH of the layer below: dZ = bf16(C GELU'(Zin)) k-blocked, and
+//          row-blocked if asked; with `colsum` the slot partial of its bias.
+enum { EPI_FWD = 0, EPI_OUT = 1, EPI_BWD = 2 };
+enum { OUT_PREDICT = 0, OUT_MSE = 1, OUT_GIVEN = 2 };
+
+struct LayerArgs {
+    const uint16_t *A;    // k-blocked operand [RP][256]
+    const uint16_t *Bt;   // [256 n][256 k] bf16
+    const float *bias;    // FWD / OUT
+    const float *Zin;     // BWD: pre-activation of the output layer, fragment order
+    float *Zout;          // FWD, training
+    uint16_t *Hkb, *Hrb;  // outputs (Hrb may be null)
+    float *partS;         // slot partials [slot][S_N]
+    int soff;             // column-sum offset in a slot (-1: none)
+    // output layer
+    const uint16_t *w4b;
+    const float *b4, *norm, *target, *dgiven;
+    const int64_t *idx;
+    float *out;
+    double *lossp;
+    int out_mode;
+    int64_t R, RP;
+};
 
 template <int EPI, bool TRAIN>
-__global__ __launch_bounds__(256) void k_mlp_gemm(const uint16_t *__restrict__ A,
-                                                  const uint16_t *__restrict__ Bt,
-                                                  const float *__restrict__ bias,
-                                                  const float *__restrict__ Zin, int64_t RP,
-                                                  float *__restrict__ Zout,
-                                                  uint16_t *__restrict__ Hout,
-                                                  uint16_t *__restrict__ HTout) {
+__global__ __launch_bounds__(GW * 64) void k_mlp_layer(LayerArgs a) {
     __shared__ uint16_t sB[WID * KPAD];
-    for (int i = threadIdx.x; i < WID * (WID / 8); i += 256) {
+    __shared__ float sPart[2][GROWS];   // EPI_OUT: row dots of each column wave
+    __shared__ float sD[GROWS];         // EPI_OUT: loss gradient d_r of each row
+    __shared__ float sRed[GW / 2][WID];
+    __shared__ double sLoss[GW];
+    for (int i = threadIdx.x; i < WID * (WID / 8); i += GW * 64) {
         const int n = i >> 5, c = i & 31;
-        *(uint4 *)&sB[n * KPAD + c * 8] = ((const uint4 *)Bt)[i];
+        *(uint4 *)&sB[n * KPAD + c * 8] = ((const uint4 *)a.Bt)[i];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int li = lane & 31, lh = lane >> 5;
-    const int64_t n_tiles = RP / 128;
+    const int64_t RP = a.RP;
+    const int64_t n_tiles = RP / GROWS;
+    constexpr bool OUT_TRAIN = EPI == EPI_OUT && TRAIN;
+    float csum[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // column sums of the bf16 output
+    float gw4[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // sum_r d_r h[r][col]
+    float gb4 = 0.0f;
+    double lacc = 0.0;
+    float w4c[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (EPI == EPI_OUT) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) w4c[cb] = bf2f(a.w4b[wc * 128 + cb * 32 + li]);
+    }
+    const float om = EPI == EPI_OUT ? a.norm[2 * NIN] : 0.0f;
+    const float osd = EPI == EPI_OUT ? a.norm[2 * NIN + 1] : 1.0f;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t row0 = tile * 128 + wr * 64;
-        f32x16 acc[2][4];
+        const int64_t row0 = tile * GROWS + wr * 32;
+        f32x16 acc[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-        const uint16_t *a0 = A + (row0 + li) * WID + lh * 8;
-        const uint16_t *a1 = a0 + 32 * WID;
+            for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
+        const uint16_t *ap = a.A + (row0 + li) * 16 + lh * 8;
         const uint16_t *bl = sB + (wc * 128 + li) * KPAD + lh * 8;
-#pragma unroll 4
+#pragma unroll 2
         for (int k0 = 0; k0 < WID; k0 += 16) {
-            const bf16x8 fa0 = ld8(a0 + k0), fa1 = ld8(a1 + k0);
+            const bf16x8 fa = ld8(ap + (int64_t)(k0 >> 4) * RP * 16);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 const bf16x8 fb = ld8(bl + cb * 32 * KPAD + k0);
-                acc[0][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb, acc[0][cb], 0, 0, 0);
-                acc[1][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb, acc[1][cb], 0, 0, 0);
+                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[cb], 0, 0, 0);
             }
         }
-        // C[i][j] of a 32x32 block: j = lane % 32, i = 8 (r / 4) + 4 (lane / 32) + r % 4
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
+        // accumulator element (cb, 4g+q): row row0 + 8g + 4lh + q, column
+        // wc*128 + cb*32 + li
+        if (EPI == EPI_FWD) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 const int col = wc * 128 + cb * 32 + li;
-                const float bc = EPI == EPI_FWD ? bias[col] : 0.0f;
+                const float bc = a.bias[col];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const int64_t rbase = row0 + rb * 32 + 8 * g + 4 * lh;
-                    uint16_t hq[4];
+                    const int64_t rb = row0 + 8 * g + 4 * lh;
+                    float z4[4];
+                    uint16_t h4[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int64_t row = rbase + q;
-                        const float c = acc[rb][cb][4 * g + q];
-                        uint16_t h;
-                        if (EPI == EPI_FWD) {
-                            const float z = c + bc;
-                            h = f2bf(gelu(z));
-                            if (TRAIN) Zout[row * WID + col] = z;
-                        } else {
-                            h = f2bf(c * gelu_prime(Zin[row * WID + col]));
-                        }
-                        Hout[row * WID + col] = h;
-                        hq[q] = h;
+                        z4[q] = acc[cb][4 * g + q] + bc;
+                        h4[q] = f2bf(gelu(z4[q]));
+                        a.Hkb[kb_idx(rb + q, col, RP)] = h4[q];
                     }
-                    if (TRAIN && HTout) {
-                        uint2 v;
-                        v.x = hq[0] | ((uint32_t)hq[1] << 16);
-                        v.y = hq[2] | ((uint32_t)hq[3] << 16);
-                        *(uint2 *)(HTout + (int64_t)col * RP + rbase) = v;
+                    if (TRAIN) {
+                        *(float4 *)(a.Zout + fr_idx(rb, col)) =
+                            make_float4(z4[0], z4[1], z4[2], z4[3]);
+                        if (a.Hrb) *(uint2 *)(a.Hrb + rb_idx(rb, col)) = pack4(h4);
                     }
                 }
             }
+        } else if (EPI == EPI_BWD) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int col = wc * 128 + cb * 32 + li;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int64_t rb = row0 + 8 * g + 4 * lh;
+                    const float4 z = *(const float4 *)(a.Zin + fr_idx(rb, col));
+                    const float zq[4] = {z.x, z.y, z.z, z.w};
+                    uint16_t h4[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        h4[q] = f2bf(acc[cb][4 * g + q] * gelu_prime(zq[q]));
+                        a.Hkb[kb_idx(rb + q, col, RP)] = h4[q];
+                        csum[cb] += bf2f(h4[q]);
+                    }
+                    if (a.Hrb) *(uint2 *)(a.Hrb + rb_idx(rb, col)) = pack4(h4);
+                }
+            }
+        } else {
+            // this lane's partial dots for its 16 rows; training keeps the
+            // bf16 activations packed and overwrites acc with GELU'(z)
+            float pd[16];
+            uint32_t hb[4][8];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) pd[r] = 0.0f;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const float bc = a.bias[wc * 128 + cb * 32 + li];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float z = acc[cb][r] + bc;
+                    uint16_t h;
+                    if (OUT_TRAIN) {
+                        float g, gp;
+                        gelu_and_prime(z, g, gp);
+                        h = f2bf(g);
+                        acc[cb][r] = gp;
+                        if (r & 1) hb[cb][r >> 1] |= (uint32_t)h << 16;
+                        else hb[cb][r >> 1] = h;
+                    } else {
+                        h = f2bf(gelu(z));
+                    }
+                    pd[r] = fmaf(bf2f(h), w4c[cb], pd[r]);
+                    // four rows at a time: bounds the live temporaries
+                    if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // sum over the 32 columns of each half-wave; lanes li == 0 publish
+            // their 16 rows, then one thread per row adds the two column
+            // waves and forms the prediction or the loss gradient
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) pd[r] += __shfl_xor(pd[r], o, 64);
+            }
+            if (li == 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    sPart[wc][wr * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = pd[r];
+            }
+            __syncthreads();
+            if (threadIdx.x < GROWS) {
+                const int rl = threadIdx.x;
+                const int64_t row = tile * GROWS + rl;
+                const float o = sPart[0][rl] + sPart[1][rl] + a.b4[0];
+                float d = 0.0f;
+                if (row < a.R) {
+                    if (a.out_mode == OUT_PREDICT) {
+                        a.out[row] = fmaf(o, osd, om);
+                    } else if (a.out_mode == OUT_MSE) {
+                        const int64_t src = a.idx ? a.idx[row] : row;
+                        const float t = (a.target[src] - om) / osd;
+                        const float diff = o - t;
+                        d = 2.0f * diff / (float)a.R;
+                        lacc += (double)diff * (double)diff;
+                    } else {
+                        d = a.dgiven[row] * osd;
+                    }
+                }
+                sD[rl] = d;
+                gb4 += d;
+            }
+            // second barrier: the next tile's writes of sPart must not
+            // overtake these reads, and training reads sD below
+            __syncthreads();
+            if (OUT_TRAIN) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const int col = wc * 128 + cb * 32 + li;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int64_t rb = row0 + 8 * g + 4 * lh;
+                        uint16_t h4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float d = sD[wr * 32 + 8 * g + 4 * lh + q];
+                            const int r = 4 * g + q;
+                            const uint16_t h = (uint16_t)(hb[cb][r >> 1] >> (16 * (r & 1)));
+                            gw4[cb] = fmaf(d, bf2f(h), gw4[cb]);
+                            h4[q] = f2bf(d * w4c[cb] * acc[cb][r]);
+                            a.Hkb[kb_idx(rb + q, col, RP)] = h4[q];
+                            csum[cb] += bf2f(h4[q]);
+                        }
+                        *(uint2 *)(a.Hrb + rb_idx(rb, col)) = pack4(h4);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    }
+    // slot partials of this workgroup: per column, fixed order (lane halves,
+    // then the eight row waves)
+    const bool want_cols = (EPI == EPI_BWD && a.soff >= 0) || OUT_TRAIN;
+    if (!want_cols) return;
+    float *ps = a.partS + (int64_t)blockIdx.x * S_N;
+    for (int pass = 0; pass < (OUT_TRAIN ? 2 : 1); ++pass) {
+        float v[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            v[cb] = pass == 0 ? csum[cb] : gw4[cb];
+            v[cb] += __shfl_xor(v[cb], 32, 64);
+        }
+        __syncthreads();
+        if (lh == 0) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) sRed[wr][wc * 128 + cb * 32 + li] = v[cb];
+        }
+        __syncthreads();
+        if (threadIdx.x < WID) {
+            float s = 0.0f;
+            for (int w = 0; w < GW / 2; ++w) s += sRed[w][threadIdx.x];
+            ps[(pass == 0 ? (EPI == EPI_OUT ? S_B1 + 2 * WID : a.soff) : S_W4) + threadIdx.x] = s;
+        }
+    }
+    if (OUT_TRAIN) {
+        // b4 and loss: threads 0..GROWS-1 hold them (one row each per tile)
+        const float b = wsum(gb4);
+        double l = lacc;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+        __syncthreads();
+        if (lane == 0) {
+            sPart[0][wave] = b;
+            sLoss[wave] = l;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float sb = 0.0f;
+            double sl = 0.0;
+            for (int w = 0; w < GW; ++w) {
+                sb += sPart[0][w];
+                sl += sLoss[w];
+            }
+            ps[S_B4] = sb;
+            a.lossp[blockIdx.x] = sl;
         }
     }
 }
@@ -222,11 +441,11 @@ __global__ __launch_bounds__(256) void k_mlp_gemm(const uint16_t *__restrict__ A
 // weight gradient of a 256x256 layer: dW[k][n] = sum_r H[r][k] dZ[r][n]
 // ---------------------------------------------------------------------------
 // Grid = chunks x 4 quadrants of 128x128; wave = 64x64 of its quadrant over
-// the chunk's 1024 rows. Operands come from the transposed copies, whose rows
-// are contiguous in r. Chunk c of layer l is written at
+// the chunk's 1024 rows. Both operands are row-blocked, so each fragment
+// load is 1 KB contiguous. Chunk c of layer l is written at
 // part_base + c * 3 * 65536, part_base = partW + (l - 1) * 65536.
-__global__ __launch_bounds__(256) void k_mlp_gemm_dw(const uint16_t *__restrict__ HT,
-                                                     const uint16_t *__restrict__ DT, int64_t RP,
+__global__ __launch_bounds__(256) void k_mlp_gemm_dw(const uint16_t *__restrict__ Hrb,
+                                                     const uint16_t *__restrict__ Drb,
                                                      float *__restrict__ part) {
     const int64_t chunk = blockIdx.x >> 2;
     const int quad = blockIdx.x & 3;
@@ -236,20 +455,19 @@ __global__ __launch_bounds__(256) void k_mlp_gemm_dw(const uint16_t *__restrict_
     const int n0c = (quad & 1) * 128 + (wave & 1) * 64;
     f32x16 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    const int64_t rs = chunk * CHUNK_DW + lh * 8;
-    const uint16_t *pa0 = HT + (int64_t)(k0r + li) * RP + rs;
-    const uint16_t *pa1 = pa0 + 32 * RP;
-    const uint16_t *pb0 = DT + (int64_t)(n0c + li) * RP + rs;
-    const uint16_t *pb1 = pb0 + 32 * RP;
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.0f;
+    // rows r0..r0+15 of row block r0/16 start at (r0/16) * 256 * 16
+    const uint16_t *pa = Hrb + (chunk * (CHUNK_DW / 16) * WID + k0r + li) * 16 + lh * 8;
+    const uint16_t *pb = Drb + (chunk * (CHUNK_DW / 16) * WID + n0c + li) * 16 + lh * 8;
 #pragma unroll 4
-    for (int r = 0; r < CHUNK_DW; r += 16) {
-        const bf16x8 a0 = ld8(pa0 + r), a1 = ld8(pa1 + r);
-        const bf16x8 b0 = ld8(pb0 + r), b1 = ld8(pb1 + r);
+    for (int rbk = 0; rbk < CHUNK_DW / 16; ++rbk) {
+        const int64_t o = (int64_t)rbk * WID * 16;
+        const bf16x8 a0 = ld8(pa + o), a1 = ld8(pa + o + 32 * 16);
+        const bf16x8 b0 = ld8(pb + o), b1 = ld8(pb + o + 32 * 16);
         acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
@@ -257,120 +475,27 @@ __global__ __launch_bounds__(256) void k_mlp_gemm_dw(const uint16_t *__restrict_
     }
     float *dst = part + chunk * (int64_t)(3 * WID * WID);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int k = k0r + a * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-                const int n = n0c + b * 32 + li;
-                dst[k * WID + n] = acc[a][b][r];
+                const int k = k0r + x * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+                const int n = n0c + y * 32 + li;
+                dst[k * WID + n] = acc[x][y][r];
             }
 }
 
-// ---------------------------------------------------------------------------
-// output layer and loss gradient
-// ---------------------------------------------------------------------------
-// MODE 0: prediction only (out = o * std + mean for rows < R).
-// MODE 1: MSE against target: d_r = 2 (o_r - t_r) / R in standardised units.
-// MODE 2: given dL/dout: d_r = dout_r * std.
-// Training modes also write dZ3 = bf16(d_r W4 GELU'(Z3)) (row-major and
-// transposed) and the slot's partials of W4, b4 and the loss.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_mlp_out(
-    const uint16_t *__restrict__ H3, const float *__restrict__ Z3, const uint16_t *__restrict__ w4b,
-    const float *__restrict__ b4, const float *__restrict__ norm, const float *__restrict__ target,
-    const float *__restrict__ dgiven, const int64_t *__restrict__ idx, int64_t R, int64_t RP,
-    float *__restrict__ out, uint16_t *__restrict__ dZ, uint16_t *__restrict__ dZT,
-    float *__restrict__ partS, double *__restrict__ lossp) {
-    __shared__ float sd[SLOT];
-    __shared__ double sl[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * SLOT;
-    const float om = norm[2 * NIN], osd = norm[2 * NIN + 1];
-    float wl[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) wl[q] = bf2f(w4b[lane * 4 + q]);
-    double lacc = 0.0;
-    for (int rr = wave; rr < SLOT; rr += 4) {
-        const int64_t r = base + rr;
-        const uint2 hv = *(const uint2 *)(H3 + r * WID + lane * 4);
-        float p = bf2f((uint16_t)(hv.x & 0xFFFF)) * wl[0];
-        p = fmaf(bf2f((uint16_t)(hv.x >> 16)), wl[1], p);
-        p = fmaf(bf2f((uint16_t)(hv.y & 0xFFFF)), wl[2], p);
-        p = fmaf(bf2f((uint16_t)(hv.y >> 16)), wl[3], p);
-        const float o = wsum(p) + b4[0];
-        if (MODE == 0) {
-            if (lane == 0 && r < R) out[r] = fmaf(o, osd, om);
-            continue;
-        }
-        float d = 0.0f;
-        if (r < R) {
-            if (MODE == 1) {
-                const int64_t src = idx ? idx[r] : r;
-                const float t = (target[src] - om) / osd;
-                const float diff = o - t;
-                d = 2.0f * diff / (float)R;
-                lacc += (double)diff * (double)diff;
-            } else {
-                d = dgiven[r] * osd;
-            }
-        }
-        if (lane == 0) sd[rr] = d;
-    }
-    if (MODE == 0) return;
-    if (lane == 0) sl[wave] = lacc;
-    __syncthreads();
-    const int k = threadIdx.x;
-    const float wk = bf2f(w4b[k]);
-    float gw = 0.0f;
-    for (int r8 = 0; r8 < SLOT; r8 += 8) {
-        uint16_t dq[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t r = base + r8 + q;
-            const float d = sd[r8 + q];
-            gw = fmaf(d, bf2f(H3[r * WID + k]), gw);
-            const uint16_t dz = f2bf(d * wk * gelu_prime(Z3[r * WID + k]));
-            dZ[r * WID + k] = dz;
-            dq[q] = dz;
-        }
-        uint4 v;
-        v.x = dq[0] | ((uint32_t)dq[1] << 16);
-        v.y = dq[2] | ((uint32_t)dq[3] << 16);
-        v.z = dq[4] | ((uint32_t)dq[5] << 16);
-        v.w = dq[6] | ((uint32_t)dq[7] << 16);
-        *(uint4 *)(dZT + (int64_t)k * RP + base + r8) = v;
-    }
-    float *ps = partS + (int64_t)blockIdx.x * S_N;
-    ps[S_W4 + k] = gw;
-    if (k == 0) {
-        float sb = 0.0f;
-        for (int r = 0; r < SLOT; ++r) sb += sd[r];
-        ps[S_B4] = sb;
-        lossp[blockIdx.x] = sl[0] + sl[1] + sl[2] + sl[3];
-    }
-}
-
-// bias gradient of hidden layer l: slot partial of sum_r dZ[r][n]
-__global__ __launch_bounds__(256) void k_mlp_colsum(const uint16_t *__restrict__ dZ,
-                                                    float *__restrict__ partS, int soff) {
-    const int n = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * SLOT;
-    float s = 0.0f;
-    for (int r = 0; r < SLOT; ++r) s += bf2f(dZ[(base + r) * WID + n]);
-    partS[(int64_t)blockIdx.x * S_N + soff + n] = s;
-}
-
-// input layer gradients: slot partials of dW0[f][n] = sum_r F[r][f] dZ0[r][n], db0
+// input layer gradients: slot partials of dW0[f][n] = sum_r F[r][f] dZ0[r][n]
+// and db0, dZ0 k-blocked
 __global__ __launch_bounds__(256) void k_mlp_dw0(const float *__restrict__ F,
-                                                 const uint16_t *__restrict__ dZ0,
+                                                 const uint16_t *__restrict__ dZ0, int64_t RP,
                                                  float *__restrict__ partS) {
     const int n = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * SLOT;
     float g[NIN] = {0, 0, 0, 0, 0, 0}, gb = 0.0f;
     for (int r = 0; r < SLOT; ++r) {
-        const float dz = bf2f(dZ0[(base + r) * WID + n]);
+        const float dz = bf2f(dZ0[kb_idx(base + r, n, RP)]);
         const float *fr = F + (base + r) * 8;
 #pragma unroll
         for (int f = 0; f < NIN; ++f) g[f] = fmaf(fr[f], dz, g[f]);
@@ -382,29 +507,32 @@ __global__ __launch_bounds__(256) void k_mlp_dw0(const float *__restrict__ F,
     ps[S_B0 + n] = gb;
 }
 
-// fixed-order sum of the partials into the flat gradient; thread 0 of block 0
-// also sums the loss partials
+// fixed-order sum of the partials into the flat gradient: hidden weights
+// over the row chunks, W0 and b0 over the 256-row slots, the other entries
+// over the layer workgroups; thread 0 of block 0 also sums the loss partials
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ partW,
                                                     int64_t n_chunks,
                                                     const float *__restrict__ partS,
-                                                    int64_t n_slots,
+                                                    int64_t n_slots, int64_t n_groups,
                                                     const double *__restrict__ lossp, int64_t R,
                                                     float *__restrict__ grad,
                                                     double *__restrict__ loss) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i == 0 && loss) {
         double s = 0.0;
-        for (int64_t c = 0; c < n_slots; ++c) s += lossp[c];
+        for (int64_t c = 0; c < n_groups; ++c) s += lossp[c];
         *loss = s / (double)R;
     }
     if (i >= NPAR) return;
     int layer = 0;
     for (int l = 1; l < 4; ++l)
         if (i >= OFF_W[l] && i < OFF_W[l] + WID * WID) layer = l;
-    double s = 0.0;
+    const float *src;
+    int64_t stride, count;
     if (layer > 0) {
-        const int64_t off = (int64_t)(layer - 1) * WID * WID + (i - OFF_W[layer]);
-        for (int64_t c = 0; c < n_chunks; ++c) s += partW[c * 3 * WID * WID + off];
+        src = partW + (int64_t)(layer - 1) * WID * WID + (i - OFF_W[layer]);
+        stride = 3 * WID * WID;
+        count = n_chunks;
     } else {
         int j;
         if (i < OFF_B0 + WID) j = (int)i;                                   // W0, b0
@@ -414,9 +542,19 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ pa
             while (!(i >= OFF_B[l] && i < OFF_B[l] + WID)) ++l;
             j = S_B1 + (l - 1) * WID + (int)(i - OFF_B[l]);
         }
-        for (int64_t c = 0; c < n_slots; ++c) s += partS[c * S_N + j];
+        src = partS + j;
+        stride = S_N;
+        count = j < S_B1 ? n_slots : n_groups;
     }
-    grad[i] = (float)s;
+    // eight independent sums (c = 8m + u), added in a fixed order
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t c = 0;
+    for (; c + 8 <= count; c += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += src[(c + u) * stride];
+    }
+    for (int u = 0; c < count; ++c, ++u) s8[u] += src[c * stride];
+    grad[i] = (float)(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
 }
 
 // Adam step (FP32) with bias corrections c1 = 1/(1-b1^t), c2 = 1/(1-b2^t);
@@ -610,11 +748,11 @@ struct rsot_mlp {
     int64_t step = 0;
     // training workspace, sized for cap_tr rows
     int64_t cap_tr = 0;
-    float *Z[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint16_t *H[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint16_t *HT[3] = {nullptr, nullptr, nullptr};
-    uint16_t *dZ[2] = {nullptr, nullptr};
-    uint16_t *dZT = nullptr;
+    float *Zf[3] = {nullptr, nullptr, nullptr};         // Z0..Z2, fragment order
+    uint16_t *Hkb[3] = {nullptr, nullptr, nullptr};     // H0..H2, k-blocked
+    uint16_t *Hrb[3] = {nullptr, nullptr, nullptr};     // H0..H2, row-blocked
+    uint16_t *dZkb[2] = {nullptr, nullptr};             // ping-pong, k-blocked
+    uint16_t *dZrb = nullptr;                           // row-blocked
     float *F = nullptr, *partW = nullptr, *partS = nullptr;
     double *lossp = nullptr;
     std::vector<void *> ws_tr;
@@ -644,6 +782,7 @@ struct rsot_mlp {
 };
 
 static int64_t padded_rows(int64_t R) { return (R + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
+static unsigned layer_grid(int64_t RP) { return (unsigned)std::min<int64_t>(RP / GROWS, MAX_GRID); }
 
 template <typename T>
 static rsot_status ws_alloc(std::vector<void *> &list, T **p, size_t count) {
@@ -667,15 +806,15 @@ static rsot_status ensure_train_ws(rsot_mlp *m, int64_t RP) {
     m->cap_tr = 0;
     auto &L = m->ws_tr;
     const size_t rw = (size_t)RP * WID;
-    for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(L, &m->Z[l], rw));
-    for (int l = 0; l < 4; ++l) RSOT_TRY(ws_alloc(L, &m->H[l], rw));
-    for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(L, &m->HT[l], rw));
-    for (int l = 0; l < 2; ++l) RSOT_TRY(ws_alloc(L, &m->dZ[l], rw));
-    RSOT_TRY(ws_alloc(L, &m->dZT, rw));
+    for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(L, &m->Zf[l], rw));
+    for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(L, &m->Hkb[l], rw));
+    for (int l = 0; l < 3; ++l) RSOT_TRY(ws_alloc(L, &m->Hrb[l], rw));
+    for (int l = 0; l < 2; ++l) RSOT_TRY(ws_alloc(L, &m->dZkb[l], rw));
+    RSOT_TRY(ws_alloc(L, &m->dZrb, rw));
     RSOT_TRY(ws_alloc(L, &m->F, (size_t)RP * 8));
     RSOT_TRY(ws_alloc(L, &m->partW, (size_t)(RP / CHUNK_DW) * 3 * WID * WID));
-    RSOT_TRY(ws_alloc(L, &m->partS, (size_t)(RP / SLOT) * S_N));
-    RSOT_TRY(ws_alloc(L, &m->lossp, (size_t)(RP / SLOT)));
+    RSOT_TRY(ws_alloc(L, &m->partS, (size_t)std::max<int64_t>(RP / SLOT, MAX_GRID) * S_N));
+    RSOT_TRY(ws_alloc(L, &m->lossp, (size_t)MAX_GRID));
     m->cap_tr = RP;
     return RSOT_OK;
 }
@@ -694,57 +833,103 @@ static rsot_status ensure_inf_ws(rsot_mlp *m, int64_t RP) {
     return RSOT_OK;
 }
 
-static unsigned gemm_grid(int64_t RP) { return (unsigned)std::min<int64_t>(RP / 128, 256); }
+static LayerArgs layer_args(rsot_mlp *m, int64_t R, int64_t RP) {
+    LayerArgs a{};
+    a.R = R;
+    a.RP = RP;
+    a.soff = -1;
+    a.partS = m->partS;
+    a.w4b = m->w4b;
+    a.b4 = m->P + OFF_B4;
+    a.norm = m->norm;
+    a.lossp = m->lossp;
+    return a;
+}
 
-// forward pass; training keeps Z, H, HT and the standardised inputs
+// Forward pass. Prediction writes o * std + mean into `out`; training keeps
+// what the backward pass needs and ends with dZ3 in dZkb[0] / dZrb and the
+// output-layer partials (out_mode OUT_MSE with target/idx, or OUT_GIVEN with
+// dout).
 static rsot_status run_forward(rsot_mlp *m, const float *feats, const int64_t *idx, int64_t R,
-                               int64_t RP, bool train) {
+                               int64_t RP, bool train, int out_mode, const float *target,
+                               const float *dout, float *out) {
     const hipStream_t st = m->stream;
-    const float *bias[4] = {m->P + OFF_B[0], m->P + OFF_B[1], m->P + OFF_B[2], m->P + OFF_B[3]};
+    const unsigned gl = layer_grid(RP);
     if (train) {
-        hipLaunchKernelGGL(k_mlp_in<true>, dim3((unsigned)(RP / 16)), dim3(256), 0, st, feats, idx,
-                           R, RP, m->norm, m->W0b, bias[0], m->F, m->Z[0], m->H[0], m->HT[0]);
-        for (int l = 1; l < 4; ++l)
-            hipLaunchKernelGGL((k_mlp_gemm<EPI_FWD, true>), dim3(gemm_grid(RP)), dim3(256), 0, st,
-                               m->H[l - 1], m->WTb + (size_t)(l - 1) * WID * WID, bias[l],
-                               (const float *)nullptr, RP, m->Z[l], m->H[l],
-                               l < 3 ? m->HT[l] : (uint16_t *)nullptr);
+        hipLaunchKernelGGL(k_mlp_in<true>, dim3((unsigned)(RP / 32)), dim3(512), 0, st, feats,
+                           idx, R, RP, m->norm, m->W0b, m->P + OFF_B[0], m->F, m->Zf[0],
+                           m->Hkb[0], m->Hrb[0]);
+        for (int l = 1; l < 3; ++l) {
+            LayerArgs a = layer_args(m, R, RP);
+            a.A = m->Hkb[l - 1];
+            a.Bt = m->WTb + (size_t)(l - 1) * WID * WID;
+            a.bias = m->P + OFF_B[l];
+            a.Zout = m->Zf[l];
+            a.Hkb = m->Hkb[l];
+            a.Hrb = m->Hrb[l];
+            hipLaunchKernelGGL((k_mlp_layer<EPI_FWD, true>), dim3(gl), dim3(GW * 64), 0, st, a);
+        }
+        LayerArgs a = layer_args(m, R, RP);
+        a.A = m->Hkb[2];
+        a.Bt = m->WTb + (size_t)2 * WID * WID;
+        a.bias = m->P + OFF_B[3];
+        a.Hkb = m->dZkb[0];
+        a.Hrb = m->dZrb;
+        a.target = target;
+        a.dgiven = dout;
+        a.idx = idx;
+        a.out_mode = out_mode;
+        hipLaunchKernelGGL((k_mlp_layer<EPI_OUT, true>), dim3(gl), dim3(GW * 64), 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_mlp_in<false>, dim3((unsigned)(RP / 16)), dim3(256), 0, st, feats, idx,
-                           R, RP, m->norm, m->W0b, bias[0], (float *)nullptr, (float *)nullptr,
-                           m->Hi[0], (uint16_t *)nullptr);
-        for (int l = 1; l < 4; ++l)
-            hipLaunchKernelGGL((k_mlp_gemm<EPI_FWD, false>), dim3(gemm_grid(RP)), dim3(256), 0,
-                               st, m->Hi[(l - 1) & 1], m->WTb + (size_t)(l - 1) * WID * WID,
-                               bias[l], (const float *)nullptr, RP, (float *)nullptr, m->Hi[l & 1],
-                               (uint16_t *)nullptr);
+        hipLaunchKernelGGL(k_mlp_in<false>, dim3((unsigned)(RP / 32)), dim3(512), 0, st, feats,
+                           idx, R, RP, m->norm, m->W0b, m->P + OFF_B[0], (float *)nullptr,
+                           (float *)nullptr, m->Hi[0], (uint16_t *)nullptr);
+        for (int l = 1; l < 3; ++l) {
+            LayerArgs a = layer_args(m, R, RP);
+            a.A = m->Hi[(l - 1) & 1];
+            a.Bt = m->WTb + (size_t)(l - 1) * WID * WID;
+            a.bias = m->P + OFF_B[l];
+            a.Hkb = m->Hi[l & 1];
+            hipLaunchKernelGGL((k_mlp_layer<EPI_FWD, false>), dim3(gl), dim3(GW * 64), 0, st, a);
+        }
+        LayerArgs a = layer_args(m, R, RP);
+        a.A = m->Hi[0];
+        a.Bt = m->WTb + (size_t)2 * WID * WID;
+        a.bias = m->P + OFF_B[3];
+        a.out_mode = OUT_PREDICT;
+        a.out = out;
+        hipLaunchKernelGGL((k_mlp_layer<EPI_OUT, false>), dim3(gl), dim3(GW * 64), 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? RSOT_OK : RSOT_ERR_DEVICE;
 }
 
-// backward from dZ3 (in dZ[0], dZT) to the flat gradient `grad` (device)
+// backward from dZ3 (dZkb[0], dZrb) to the flat gradient `grad` (device)
 static rsot_status run_backward(rsot_mlp *m, int64_t R, int64_t RP, float *grad,
                                 double *loss_dev) {
     const hipStream_t st = m->stream;
     const int64_t n_chunks = RP / CHUNK_DW, n_slots = RP / SLOT;
+    const unsigned gl = layer_grid(RP);
     int cur = 0;
     for (int l = 3; l >= 1; --l) {
-        // dW_l from H_{l-1} and dZ_l (transposed copies)
+        // dW_l from H_{l-1} and dZ_l (row-blocked)
         hipLaunchKernelGGL(k_mlp_gemm_dw, dim3((unsigned)(n_chunks * 4)), dim3(256), 0, st,
-                           m->HT[l - 1], m->dZT, RP, m->partW + (size_t)(l - 1) * WID * WID);
-        hipLaunchKernelGGL(k_mlp_colsum, dim3((unsigned)n_slots), dim3(256), 0, st, m->dZ[cur],
-                           m->partS, S_B1 + (l - 1) * WID);
-        // dZ_{l-1} = bf16((dZ_l W_l^T) * GELU'(Z_{l-1})); W_l as [k][n] is Bt of this product
-        hipLaunchKernelGGL((k_mlp_gemm<EPI_BWD, true>), dim3(gemm_grid(RP)), dim3(256), 0, st,
-                           m->dZ[cur], m->Wb + (size_t)(l - 1) * WID * WID, (const float *)nullptr,
-                           m->Z[l - 1], RP, (float *)nullptr, m->dZ[cur ^ 1],
-                           l - 1 >= 1 ? m->dZT : (uint16_t *)nullptr);
+                           m->Hrb[l - 1], m->dZrb, m->partW + (size_t)(l - 1) * WID * WID);
+        // dZ_{l-1} = bf16((dZ_l W_l^T) * GELU'(Z_{l-1})); W_l as [k][n] is Bt here
+        LayerArgs a = layer_args(m, R, RP);
+        a.A = m->dZkb[cur];
+        a.Bt = m->Wb + (size_t)(l - 1) * WID * WID;
+        a.Zin = m->Zf[l - 1];
+        a.Hkb = m->dZkb[cur ^ 1];
+        a.Hrb = l - 1 >= 1 ? m->dZrb : nullptr;
+        a.soff = l - 1 >= 1 ? S_B1 + (l - 2) * WID : -1;
+        hipLaunchKernelGGL((k_mlp_layer<EPI_BWD, true>), dim3(gl), dim3(GW * 64), 0, st, a);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_mlp_dw0, dim3((unsigned)n_slots), dim3(256), 0, st, m->F, m->dZ[cur],
-                       m->partS);
+    hipLaunchKernelGGL(k_mlp_dw0, dim3((unsigned)n_slots), dim3(256), 0, st, m->F, m->dZkb[cur],
+                       RP, m->partS);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((NPAR + 255) / 256)), dim3(256), 0, st,
-                       m->partW, n_chunks, m->partS, n_slots, m->lossp, R, grad, loss_dev);
+                       m->partW, n_chunks, m->partS, n_slots, (int64_t)gl, m->lossp, R, grad,
+                       loss_dev);
     return hipGetLastError() == hipSuccess ? RSOT_OK : RSOT_ERR_DEVICE;
 }
 
@@ -911,13 +1096,7 @@ extern "C" rsot_status rsot_mlp_forward(rsot_mlp *m, const float *feats, int64_t
     if (rows == 0) return RSOT_OK;
     const int64_t RP = padded_rows(rows);
     RSOT_TRY(ensure_inf_ws(m, RP));
-    RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, false));
-    hipLaunchKernelGGL(k_mlp_out<0>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->Hi[1], (const float *)nullptr, m->w4b,
-                       m->P + OFF_B4, m->norm, (const float *)nullptr, (const float *)nullptr,
-                       (const int64_t *)nullptr, rows, RP, out, (uint16_t *)nullptr,
-                       (uint16_t *)nullptr, (float *)nullptr, (double *)nullptr);
-    RSOT_HIP(hipGetLastError());
+    RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, false, OUT_PREDICT, nullptr, nullptr, out));
     RSOT_HIP(hipStreamSynchronize(m->stream));
     return RSOT_OK;
 }
@@ -926,14 +1105,8 @@ extern "C" rsot_status rsot_mlp_forward(rsot_mlp *m, const float *feats, int64_t
 static rsot_status predict_rows(rsot_mlp *m, const float *feats, int64_t rows) {
     const int64_t RP = padded_rows(rows);
     RSOT_TRY(ensure_inf_ws(m, RP));
-    RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, false));
-    hipLaunchKernelGGL(k_mlp_out<0>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->Hi[1], (const float *)nullptr, m->w4b, m->P + OFF_B4, m->norm,
-                       (const float *)nullptr, (const float *)nullptr, (const int64_t *)nullptr,
-                       rows, RP, m->outb, (uint16_t *)nullptr, (uint16_t *)nullptr,
-                       (float *)nullptr, (double *)nullptr);
-    RSOT_HIP(hipGetLastError());
-    return RSOT_OK;
+    return run_forward(m, feats, nullptr, rows, RP, false, OUT_PREDICT, nullptr, nullptr,
+                       m->outb);
 }
 
 static rsot_status ensure_featb(rsot_mlp *m, int64_t rows) {
@@ -955,12 +1128,7 @@ extern "C" rsot_status rsot_mlp_backward(rsot_mlp *m, const float *feats, int64_
     if (!m || rows < 1 || !feats || !dout || !grad) return RSOT_ERR_INVALID_ARG;
     const int64_t RP = padded_rows(rows);
     RSOT_TRY(ensure_train_ws(m, RP));
-    RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, true));
-    hipLaunchKernelGGL(k_mlp_out<2>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->H[3], m->Z[3], m->w4b, m->P + OFF_B4, m->norm, (const float *)nullptr,
-                       dout, (const int64_t *)nullptr, rows, RP, (float *)nullptr, m->dZ[0], m->dZT,
-                       m->partS, m->lossp);
-    RSOT_HIP(hipGetLastError());
+    RSOT_TRY(run_forward(m, feats, nullptr, rows, RP, true, OUT_GIVEN, nullptr, dout, nullptr));
     RSOT_TRY(run_backward(m, rows, RP, grad, nullptr));
     RSOT_HIP(hipStreamSynchronize(m->stream));
     return RSOT_OK;
@@ -998,12 +1166,7 @@ extern "C" rsot_status rsot_mlp_train_step(rsot_mlp *m, const float *feats, cons
         return RSOT_ERR_INVALID_ARG;
     const int64_t RP = padded_rows(rows);
     RSOT_TRY(ensure_train_ws(m, RP));
-    RSOT_TRY(run_forward(m, feats, idx, rows, RP, true));
-    hipLaunchKernelGGL(k_mlp_out<1>, dim3((unsigned)(RP / SLOT)), dim3(256), 0, m->stream,
-                       m->H[3], m->Z[3], m->w4b, m->P + OFF_B4, m->norm, target,
-                       (const float *)nullptr, idx, rows, RP, (float *)nullptr, m->dZ[0], m->dZT, m->partS,
-                       m->lossp);
-    RSOT_HIP(hipGetLastError());
+    RSOT_TRY(run_forward(m, feats, idx, rows, RP, true, OUT_MSE, target, nullptr, nullptr));
     RSOT_TRY(run_backward(m, rows, RP, m->grad, m->dloss));
     RSOT_TRY(launch_adam(m, m->grad, lr, b1, b2, eps));
     if (loss) {

@@ -514,7 +514,9 @@ class Multilevel:
         except Exception:
             pass
 
-    def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000):
+    def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000, callback=None):
+        """rsot_solve_multilevel. ``callback(iter_info)`` is called after every
+        accepted iteration of every level; a true return value cancels."""
         lib = load_library()
         e = np.ascontiguousarray(eps, dtype=np.float64)
         lv = np.ascontiguousarray(level, dtype=np.int32)
@@ -522,6 +524,12 @@ class Multilevel:
         lib.rsot_solve_params_default(ctypes.byref(mp.base))
         mp.base.tol = tol
         mp.base.max_iter = max_iter
+        cb = None
+        if callback is not None:
+            def _cb(ptr, _user):
+                return int(bool(callback(ptr.contents)))
+            cb = CALLBACK(_cb)
+            mp.base.callback = cb
         mp.eps = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         mp.level = lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         mp.n_stages = len(e)

@@ -331,17 +331,28 @@ def config4_instance(i: int, n_cells: int = 128, n_targets: int = 65536) -> Prob
     return p
 
 
-def config5_instance(i: int, scale: float = 1.0) -> Problem:
-    """Instance i of the batched family (seed 2000+i): N_q ~ logU[1e5, 4e6]
-    realised as a cube of n^3 x 24 points, N ~ logU[4096, 262144], mixture
-    source and targets (sigma 0.1), eps ~ logU[1e-4, 1e-2]. ``scale`` shrinks
-    both sizes for tests."""
+def _config5_draw(i: int, scale: float):
     rng = np.random.default_rng(2000 + i)
     nq_t = float(np.exp(rng.uniform(np.log(1e5), np.log(4e6)))) * scale
     n_t = float(np.exp(rng.uniform(np.log(4096), np.log(262144)))) * scale
     eps = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
     n_cells = max(2, int(round((nq_t / 24.0) ** (1.0 / 3.0))))
     n_targets = max(8, int(round(n_t)))
+    return rng, n_cells, n_targets, eps
+
+
+def config5_sizes(i: int, scale: float = 1.0):
+    """(quadrature points, targets) of batched instance i without building it."""
+    _, n_cells, n_targets, _ = _config5_draw(i, scale)
+    return 24 * n_cells ** 3, n_targets
+
+
+def config5_instance(i: int, scale: float = 1.0) -> Problem:
+    """Instance i of the batched family (seed 2000+i): N_q ~ logU[1e5, 4e6]
+    realised as a cube of n^3 x 24 points, N ~ logU[4096, 262144], mixture
+    source and targets (sigma 0.1), eps ~ logU[1e-4, 1e-2]. ``scale`` shrinks
+    both sizes for tests."""
+    rng, n_cells, n_targets, eps = _config5_draw(i, scale)
     src_seed, tm_seed, ts_seed = rng.integers(0, 2**31, size=3)
     p = cube_mixture(n_cells, n_targets, eps, int(src_seed), int(tm_seed), int(ts_seed))
     p.name = f"batch{i}"

@@ -91,3 +91,28 @@ def test_autotune_choice_is_valid_and_equivalent():
     assert abs(r2.J - r1.J) <= 1e-9 * abs(r1.J)
     g1, g2 = r1.grad.cpu().numpy(), r2.grad.cpu().numpy()
     assert np.max(np.abs(g1 - g2) / (p.nu + g1 + p.nu)) < 1e-6
+
+
+def test_batched_full_size_smallest_instances_against_oracle():
+    """The eight smallest instances of the 64-instance batched workload at
+    full size (1.4e9 to 4.2e9 pairs each), dense rule, mixed precision, in
+    one batched call, each against the FP64 oracle."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    sizes = sorted((W.config5_sizes(i)[0] * W.config5_sizes(i)[1], i) for i in range(64))
+    ids = [i for _, i in sizes[:8]]
+    insts = [W.config5_instance(i) for i in ids]
+    _say(f"full-size batch: instances {ids}")
+    probs = [rsot.Problem(p.x, p.mu, p.y, p.nu) for p in insts]
+    psis = [torch.as_tensor(W.random_psi(300 + i, p.n, p.eps), device="cuda")
+            for i, p in zip(ids, insts)]
+    J, grads, infos, ms = rsot.dual_eval_batched(probs, [p.eps for p in insts], psis)
+    _say(f"  batch {ms:.1f} ms for {sum(p.nq * p.n for p in insts):.3e} pairs")
+    for k, p in enumerate(insts):
+        ref = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psis[k].cpu().numpy(), p.eps)
+        g = grads[k].cpu().numpy()
+        eg = np.max(np.abs(g - ref.grad) / (p.nu + ref.grad + p.nu))
+        ej = abs(J[k] - ref.J) / abs(ref.J)
+        _say(f"  instance {ids[k]}: nq={p.nq} n={p.n} eps={p.eps:.2e} ej={ej:.2e} eg={eg:.2e}")
+        assert ej <= 1e-9 and eg <= 1e-6
+        assert infos[k]["kept_pairs"] == p.nq * p.n
