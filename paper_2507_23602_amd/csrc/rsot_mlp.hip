@@ -125,14 +125,28 @@ __global__ __launch_bounds__(512) void k_mlp_in(const float *__restrict__ feats,
                                                 float *__restrict__ Fout, float *__restrict__ Z0,
                                                 uint16_t *__restrict__ Hkb,
                                                 uint16_t *__restrict__ Hrb) {
+    __shared__ float sF[32][8];
     const int lane = threadIdx.x & 63, cbk = threadIdx.x >> 6;
     const int li = lane & 31, lh = lane >> 5;
     const int col = cbk * 32 + li;
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    // standardised features of the workgroup's 32 rows, once per row
+    if (threadIdx.x < 32 * 8) {
+        const int rr = threadIdx.x >> 3, f = threadIdx.x & 7;
+        const int64_t r = r0 + rr;
+        float v = 0.0f;
+        if (r < R && f < NIN) {
+            const int64_t src = idx ? idx[r] : r;
+            v = (feats[src * NIN + f] - norm[f]) / norm[NIN + f];
+        }
+        sF[rr][f] = v;
+        if (TRAIN) Fout[r * 8 + f] = v;
+    }
+    __syncthreads();
     float w[NIN];
 #pragma unroll
     for (int f = 0; f < NIN; ++f) w[f] = bf2f(W0b[f * WID + col]);
     const float bb = b0[col];
-    const int64_t r0 = (int64_t)blockIdx.x * 32;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int64_t rb = r0 + 8 * g + 4 * lh;
@@ -140,29 +154,13 @@ __global__ __launch_bounds__(512) void k_mlp_in(const float *__restrict__ feats,
         uint16_t h4[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t r = rb + q;
-            float F[NIN];
-            if (r < R) {
-                const int64_t src = idx ? idx[r] : r;
-#pragma unroll
-                for (int f = 0; f < NIN; ++f)
-                    F[f] = (feats[src * NIN + f] - norm[f]) / norm[NIN + f];
-            } else {
-#pragma unroll
-                for (int f = 0; f < NIN; ++f) F[f] = 0.0f;
-            }
+            const int rl = 8 * g + 4 * lh + q;
             float z = bb;
 #pragma unroll
-            for (int f = 0; f < NIN; ++f) z = fmaf(F[f], w[f], z);
+            for (int f = 0; f < NIN; ++f) z = fmaf(sF[rl][f], w[f], z);
             z4[q] = z;
             h4[q] = f2bf(gelu(z));
-            Hkb[kb_idx(r, col, RP)] = h4[q];
-            if (TRAIN && cbk == 0 && li < 8) {
-                float fv = 0.0f;
-#pragma unroll
-                for (int f = 0; f < NIN; ++f) fv = li == f ? F[f] : fv;
-                Fout[r * 8 + li] = fv;
-            }
+            Hkb[kb_idx(rb + q, col, RP)] = h4[q];
         }
         if (TRAIN) {
             *(float4 *)(Z0 + fr_idx(rb, col)) = make_float4(z4[0], z4[1], z4[2], z4[3]);
