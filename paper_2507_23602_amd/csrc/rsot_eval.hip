@@ -22,6 +22,8 @@
 // S_q = log2 mu_q - Lt(x_q) stored by the objective pass; point records are
 // wave-uniform. Each work item sums a segment of point tiles; segments are
 // merged per target in a fixed order, so results are bitwise reproducible.
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -370,6 +372,15 @@ __global__ void k_fill_work(const int64_t *__restrict__ col_ptr, const int64_t *
     }
 }
 
+// sort keys of work items: the item's first list entry (a block or tile index)
+__global__ void k_item_keys(const int64_t *__restrict__ wi_range, const uint32_t *__restrict__ idx,
+                            int64_t n, int32_t *__restrict__ key, int32_t *__restrict__ val) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n) return;
+    key[w] = (int32_t)(idx[wi_range[2 * w]] & ~RSOT_PARTIAL_BIT);
+    val[w] = (int32_t)w;
+}
+
 // ---------------------------------------------------------------------------
 // objective pass
 // ---------------------------------------------------------------------------
@@ -514,17 +525,24 @@ __global__ __launch_bounds__(256) void k_pass1(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
     const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
     const uint32_t *__restrict__ row_idx, const int32_t *__restrict__ wi_tile,
-    const int64_t *__restrict__ wi_range, int64_t n_items, int64_t n_blocks, int64_t seg1,
-    int64_t n_seg1, double kcs, double *__restrict__ part, double *__restrict__ partk) {
+    const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm, int64_t n_items,
+    int64_t n_blocks, int64_t seg1, int64_t n_seg1, double kcs, double *__restrict__ part,
+    double *__restrict__ partk) {
     const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= n_items) return;
-    int64_t t, e0, e1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t w, t, e0, e1;
     if (MODE == MODE_DENSE) {
+        w = (int64_t)blockIdx.x * 4 + wave;
+        if (w >= n_items) return;
         t = w / n_seg1;
         e0 = (w % n_seg1) * seg1;
         e1 = std::min<int64_t>(e0 + seg1, n_blocks);
     } else {
+        // items in the order of their first target block, each XCD taking a
+        // contiguous part of that order
+        const int64_t k = xcd_group((n_items + 3) / 4) * 4 + wave;
+        if (k >= n_items) return;
+        w = perm[k];
         t = wi_tile[w];
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
@@ -647,8 +665,8 @@ __global__ __launch_bounds__(256) void k_pass2(
     const double4 *__restrict__ qp, const double *__restrict__ qH,
     const double4 *__restrict__ trec, const double *__restrict__ tG,
     const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
-    const uint32_t *__restrict__ col_idx, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
-    int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
+    const int32_t *__restrict__ perm, const uint32_t *__restrict__ col_idx, int64_t n_tiles,
+    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t b, w, e0, e1;
@@ -667,11 +685,12 @@ __global__ __launch_bounds__(256) void k_pass2(
         e1 = std::min<int64_t>(e0 + seg, n_tiles);
         w = b * n_seg + sgi;
     } else {
-        // items are block-major and blocks Morton-ordered: give each XCD a
-        // contiguous range of items
-        const int64_t g = xcd_group((n_wi + 3) / 4);
-        w = g * 4 + wave;
-        if (w >= n_wi) return;
+        // items in the order of their first point tile, each XCD taking a
+        // contiguous part of that order: items that read the same point
+        // records share that XCD's L2
+        const int64_t k = xcd_group((n_wi + 3) / 4) * 4 + wave;
+        if (k >= n_wi) return;
+        w = perm[k];
         b = wi_block[w];
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
@@ -694,12 +713,14 @@ struct BatchDesc {
     const uint32_t *row_idx;
     const int32_t *wi1_tile;
     const int64_t *wi1_range;
+    const int32_t *wi1_perm;
     int64_t n_items1, seg1, n_seg1;
     double kcs;
     double *part1, *part1k;
     const uint32_t *col_idx;
     const int32_t *wi_block;
     const int64_t *wi_range;
+    const int32_t *wi_perm;
     int64_t n_wi, n_seg, seg;
     double *gpart;
 };
@@ -757,7 +778,7 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
             e1 = std::min<int64_t>(e0 + d.seg1, d.n_blocks);
             w = t * d.n_seg1 + s1;
         } else {
-            w = v;
+            w = uniform_const(d.wi1_perm)[v];
             t = uniform_const(d.wi1_tile)[w];
             e0 = uniform_const(d.wi1_range)[2 * w];
             e1 = uniform_const(d.wi1_range)[2 * w + 1];
@@ -790,7 +811,7 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
             e1 = std::min<int64_t>(e0 + d.seg, d.n_tiles);
             w = b * d.n_seg + sgi;
         } else {
-            w = v;
+            w = uniform_const(d.wi_perm)[v];
             b = uniform_const(d.wi_block)[w];
             e0 = uniform_const(d.wi_range)[2 * w];
             e1 = uniform_const(d.wi_range)[2 * w + 1];
@@ -929,9 +950,11 @@ struct Pass1Work {
 
 template <int D, bool F64, int MODE>
 static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
-    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3((unsigned)((pw.n_items + 3) / 4)), dim3(256),
-                       0, p->stream, p->qp, p->trec, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile,
-                       p->wi1_range, pw.n_items, p->n_blocks, pw.seg1, pw.n_seg1, kcs, p->part1,
+    const unsigned grid = MODE == MODE_DENSE ? (unsigned)((pw.n_items + 3) / 4)
+                                             : xcd_grid((pw.n_items + 3) / 4);
+    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp,
+                       p->trec, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile, p->wi1_range,
+                       p->wi1_perm, pw.n_items, p->n_blocks, pw.seg1, pw.n_seg1, kcs, p->part1,
                        p->part1k);
     hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
                        p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
@@ -947,8 +970,8 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
     else
         grid = xcd_grid((n_wi + 3) / 4);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
-                       p->trec, p->tG, p->wi_block, p->wi_range, p->col_idx, p->n_tiles,
-                       p->n_blocks, n_wi, n_seg, seg, p->gpart);
+                       p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
+                       p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
 }
 
 template <int D, bool F64>
@@ -1111,6 +1134,32 @@ static rsot_status plan_begin(EvalPlan &e) {
     return RSOT_OK;
 }
 
+// processing order of n work items: item numbers sorted (stable radix sort)
+// by the first entry of their list range
+static rsot_status order_items(rsot_problem *p, hipStream_t st, const int64_t *range,
+                               const uint32_t *idx, int64_t n, int64_t n_keys, int32_t **perm,
+                               size_t *perm_cap) {
+    if (n <= 0) return RSOT_OK;
+    if (n > INT32_MAX) return RSOT_ERR_INVALID_ARG;
+    RSOT_TRY(grow(p, perm, perm_cap, (size_t)n));
+    size_t cap = p->sort_cap, cap2 = p->sort_cap, cap3 = p->sort_cap;
+    RSOT_TRY(grow(p, &p->sort_key, &cap, (size_t)n));
+    RSOT_TRY(grow(p, &p->sort_key2, &cap2, (size_t)n));
+    RSOT_TRY(grow(p, &p->sort_val, &cap3, (size_t)n));
+    p->sort_cap = std::min(cap, std::min(cap2, cap3));
+    hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, range,
+                       idx, n, p->sort_key, p->sort_val);
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < n_keys) ++bits;
+    size_t tmp_bytes = 0;
+    RSOT_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, p->sort_key, p->sort_key2,
+                                                p->sort_val, *perm, (int)n, 0, bits, st));
+    RSOT_TRY(grow(p, (char **)&p->sort_tmp, &p->sort_tmp_cap, tmp_bytes));
+    RSOT_HIP(hipcub::DeviceRadixSort::SortPairs(p->sort_tmp, tmp_bytes, p->sort_key, p->sort_key2,
+                                                p->sort_val, *perm, (int)n, 0, bits, st));
+    return RSOT_OK;
+}
+
 // after plan_begin's stream work completed (only needed when culled)
 static rsot_status plan_lists(EvalPlan &e) {
     rsot_problem *p = e.p;
@@ -1147,6 +1196,12 @@ static rsot_status plan_lists(EvalPlan &e) {
         hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((p->n_tiles + 255) / 256)), dim3(256), 0,
                            st, p->row_ptr, p->wi1_ptr, p->n_tiles, (int)e.seg1_cfg, p->wi1_tile,
                            p->wi1_range);
+        RSOT_HIP(hipGetLastError());
+        RSOT_TRY(order_items(p, st, p->wi1_range, p->row_idx, e.pw.n_items, p->n_blocks,
+                             &p->wi1_perm, &p->perm1_cap));
+        if (grad)
+            RSOT_TRY(order_items(p, st, p->wi_range, p->col_idx, e.n_wi, p->n_tiles, &p->wi_perm,
+                                 &p->perm_cap));
     }
     size_t c1 = p->part1_cap, c2 = p->part1_cap;
     RSOT_TRY(grow(p, &p->part1, &c1, (size_t)std::max<int64_t>(e.pw.n_items, 1) * 64));
@@ -1317,6 +1372,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.row_idx = p->row_idx;
         d.wi1_tile = p->wi1_tile;
         d.wi1_range = p->wi1_range;
+        d.wi1_perm = p->wi1_perm;
         d.n_items1 = e.pw.n_items;
         d.seg1 = e.pw.seg1;
         d.n_seg1 = e.pw.n_seg1;
@@ -1326,6 +1382,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.col_idx = p->col_idx;
         d.wi_block = p->wi_block;
         d.wi_range = p->wi_range;
+        d.wi_perm = p->wi_perm;
         d.n_wi = e.grad ? e.n_wi : 0;
         d.n_seg = e.n_seg;
         d.seg = e.seg;

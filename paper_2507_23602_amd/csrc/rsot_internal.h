@@ -95,6 +95,15 @@ struct rsot_problem {
     int64_t *wi1_range = nullptr;
     int64_t *wi1_ptr = nullptr;  // [n_tiles+1]
     size_t wi1_cap = 0;
+    // processing order of the work items of the truncated rules: item numbers
+    // sorted by their first entry (first target block of an objective-pass
+    // item, first point tile of a gradient-pass item), so items that read the
+    // same records run close together; partials stay at the item's own index
+    int32_t *wi1_perm = nullptr, *wi_perm = nullptr;
+    int32_t *sort_key = nullptr, *sort_key2 = nullptr, *sort_val = nullptr;
+    size_t perm1_cap = 0, perm_cap = 0, sort_cap = 0;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_cap = 0;
     double *part1 = nullptr;     // [items*64] partial log2-sum-exp
     double *part1k = nullptr;    // [items*64] kept pairs
     size_t part1_cap = 0;
