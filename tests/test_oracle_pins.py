@@ -282,6 +282,9 @@ def test_tile_rule_bound_and_degenerate_cases():
     block_of = np.empty(256, np.int32)
     block_of[to] = np.arange(256) // 16
     nt, nb = x.shape[0] // 16, 16
+    # every term nu_j exp((psi_j - c_qj) / eps), to check the bound point by point
+    c = 0.5 * ((x[:, None, :] - y[None, :, :]) ** 2).sum(-1)
+    terms = nu[None, :] * np.exp((psi[None, :] - c) / eps)
     for tau in [1e-3, 1e-8, 1e-12]:
         r = oracle.dual_eval_tile(x, mu, y, nu, psi, eps, tile_of, nt, block_of, nb,
                                   tau, abs(dense.J), want_keep=True)
@@ -289,6 +292,12 @@ def test_tile_rule_bound_and_degenerate_cases():
         assert 0.0 <= E <= tau * abs(dense.J)
         assert r.keep.any(axis=1).all()
         assert abs(r.grad.sum() - (mu.sum() - nu.sum())) < 1e-13
+        # the inequality behind the bound, at every point: neglected <= eta * kept
+        kept_pair = r.keep[tile_of][:, block_of].astype(bool)
+        neglected = np.where(kept_pair, 0.0, terms).sum(1)
+        kept_sum = np.where(kept_pair, terms, 0.0).sum(1)
+        eta = tau * abs(dense.J) / (eps * mu.sum())
+        assert np.all(neglected <= eta * kept_sum * (1 + 1e-12))
         if tau == 1e-3:
             assert r.kept < 0.55 * x.shape[0] * 256
     # tau -> 0 keeps every pair: equals dense
