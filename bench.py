@@ -412,7 +412,8 @@ def multilevel_leg():
             log(f"[bench] multilevel: stage eps {it.eps:.2e}, iteration {it.iteration}, "
                 f"|g|_1 {it.grad_l1:.2e}, kept {it.kept_pairs:.3e}")
         return 0
-    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5, callback=progress)
+    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5, stage_tol=1e-5,
+                         callback=progress)
     t_s = time.perf_counter() - t0
     log(f"[bench] multilevel: hierarchy {t_h:.2f}s, solve {t_s:.2f}s, status {info['status']}, "
         f"|g|_1 {info['grad_l1']:.2e}, iterations {info['iterations']}, "

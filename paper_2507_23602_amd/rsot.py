@@ -514,9 +514,12 @@ class Multilevel:
         except Exception:
             pass
 
-    def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000, callback=None):
+    def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000, callback=None,
+              stage_tol=0.0):
         """rsot_solve_multilevel. ``callback(iter_info)`` is called after every
-        accepted iteration of every level; a true return value cancels."""
+        accepted iteration of every level; a true return value cancels.
+        ``level_tol`` / ``stage_tol``: ||grad||_1 targets of non-final levels
+        and of non-final eps stages within a level (0 = tol)."""
         lib = load_library()
         e = np.ascontiguousarray(eps, dtype=np.float64)
         lv = np.ascontiguousarray(level, dtype=np.int32)
@@ -524,6 +527,7 @@ class Multilevel:
         lib.rsot_solve_params_default(ctypes.byref(mp.base))
         mp.base.tol = tol
         mp.base.max_iter = max_iter
+        mp.base.stage_tol = stage_tol
         cb = None
         if callback is not None:
             def _cb(ptr, _user):

@@ -118,7 +118,8 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
     """Held-out instances: wall-clock seconds and iterations to ||g||_1 < tol
     from (a) zero with the eps schedule, (b) zero at the final eps alone,
     (c) the learned start (rsot_solve_learned), (d) the combined multilevel
-    start (Sec. 5.3) with the eps schedule spread over the levels."""
+    start (Sec. 5.3) with the eps schedule spread over the levels. Stages and
+    levels before the last stop at 10 tol."""
     import torch
     out = []
     hier = None
@@ -139,7 +140,7 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
         rec = {"id": i, "eps": p.eps}
         pr = make_problem(p, truncation)
         ts = time.perf_counter()
-        psi_a, ia = pr.solve(sched, tol=tol)
+        psi_a, ia = pr.solve(sched, tol=tol, stage_tol=10 * tol)
         rec["zero_sched"] = {"seconds": time.perf_counter() - ts, "iterations": ia["iterations"],
                              "status": ia["status"]}
         pr.close()
@@ -168,7 +169,7 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
             ml = rsot.Multilevel(srcs, hier, precision="mixed", truncation=truncation, tau=1e-12)
             E, lev = _ml_stages(p.eps)
             ts = time.perf_counter()
-            _, idd = ml.solve(E, lev, tol=tol, level_tol=10 * tol)
+            _, idd = ml.solve(E, lev, tol=tol, level_tol=10 * tol, stage_tol=10 * tol)
             rec["multilevel"] = {"seconds": time.perf_counter() - ts,
                                  "iterations": int(sum(idd["iterations"])),
                                  "finest_iterations": int(idd["iterations"][-1]),

@@ -274,3 +274,38 @@ def test_full_size_sampled_points():
     g = r.grad.cpu().numpy()
     assert abs(g.sum() - (p.mu.sum() - p.nu.sum())) < 1e-9
     assert r.info["kept_pairs"] == p.nq * p.n
+
+
+@pytest.mark.parametrize("which", ["zero", "random", "lbfgs20"])
+def test_full_size_error_table(which):
+    """Full-size 3D workload at three potentials (zero, N(0, eps^2), the
+    iterate after 20 L-BFGS iterations): sampled L_q against the oracle, and
+    the mixed-precision objective and gradient against the FP64 path (which
+    the oracle pins at smaller sizes) within the stated bounds (objective
+    1e-9 relative, gradient 1e-6 against the local mass scale)."""
+    import torch
+    _say(f"full size error table: psi {which}")
+    p = W.config2()
+    dev = [torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)]
+    prob = _problem(*dev)
+    if which == "zero":
+        psi = np.zeros(p.n)
+    elif which == "random":
+        psi = W.random_psi(11, p.n, p.eps)
+    else:
+        psi, info = prob.solve([p.eps], max_iter=20)
+        _say(f"  20 iterations: |g|_1 {info['grad_l1']:.3e}")
+    pt = torch.as_tensor(psi, device="cuda")
+    r = prob.dual_eval(pt, p.eps)
+    L = prob.lse().cpu().numpy()
+    g = r.grad.cpu().numpy()
+    prob.set_precision("fp64")
+    r64 = prob.dual_eval(pt, p.eps)
+    g64 = r64.grad.cpu().numpy()
+    idx = np.random.default_rng(1).choice(p.nq, 2000, replace=False)
+    ref = oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, want_L=True)
+    el = np.max(np.abs(L[idx] - ref.L) / np.maximum(1.0, np.abs(ref.L)))
+    ej = abs(r.J - r64.J) / abs(r64.J)
+    eg = np.max(np.abs(g - g64) / (p.nu + g64 + p.nu))
+    _say(f"  sampled L err {el:.2e}, J mixed vs fp64 {ej:.2e}, grad {eg:.2e}")
+    assert el <= 1e-6 and ej <= 1e-9 and eg <= 1e-6
