@@ -77,7 +77,9 @@ typedef struct {
     double tau;               /* relative error tolerance (GEOM, INT, TILE); 1e-12 */
     double delta_thr;         /* pointwise threshold (PW); default 1e-12           */
     int inputs_on_device;     /* 1: x, mu, y, nu passed to create are device ptrs  */
-    int seg_tiles;            /* gradient pass: point tiles per work item; 0=auto  */
+    int seg_tiles;            /* gradient pass: point tiles per work item; 0 = default
+                                 (dense: 512-tile segments, at least 32,768 items;
+                                 truncated rules: 64 list entries)                    */
     int seg_blocks;           /* objective pass: target blocks per work item; 0 = default
                                  (dense: whole rows unless the tiles are too few to fill
                                  the device; truncated rules: 256)                     */
