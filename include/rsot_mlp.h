@@ -24,7 +24,7 @@
  * Memory: every pointer marked DEVICE is a device address on the model's
  * stream; HOST pointers are read or written before the call returns. The
  * model owns its parameters and a workspace that grows to the largest row
- * count seen (about 9.5 KB per row for training, 1 KB per row for inference).
+ * count seen (about 7.5 KB per row for training, 1 KB per row for inference).
  * Calls on one model must not overlap.
  */
 #ifndef RSOT_MLP_H

@@ -58,3 +58,32 @@ def test_multilevel_index_rule():
     table = [rsot.multilevel_indices(3, 1, l) for l in range(3)]
     assert table == [(0, 0), (1, 0), (2, 0)]
     assert [rsot.multilevel_indices(4, 4, l) for l in range(4)] == [(l, l) for l in range(4)]
+
+
+def test_autotune_cache_by_shape_class(tmp_path):
+    """rsot.tuned: the first problem of a shape class runs the autotuner and
+    stores its choice in the JSON cache; later problems of that class reuse
+    it without tuning; another class tunes again."""
+    class FakeProblem:
+        def __init__(self, dim, nq, n):
+            self.dim, self.nq, self.n = dim, nq, n
+            self.tuned_with, self.autotuned = None, 0
+
+        def autotune(self, psi, eps, reps=2):
+            self.autotuned += 1
+            return {"seg_blocks": 128, "seg_tiles": 32, "best_ms": 1.0, "default_ms": 2.0}
+
+        def set_tuning(self, sb, st):
+            self.tuned_with = (sb, st)
+
+    cache = str(tmp_path / "tune.json")
+    a = FakeProblem(3, 1_000_000, 65536)
+    r = rsot.tuned(a, None, 1e-3, "tile", cache)
+    assert a.autotuned == 1 and r["cached"] is False
+    b = FakeProblem(3, 1_040_000, 66000)          # same log2 sizes and eps decade
+    r = rsot.tuned(b, None, 2e-3, "tile", cache)
+    assert b.autotuned == 0 and r["cached"] is True and b.tuned_with == (128, 32)
+    c = FakeProblem(3, 1_000_000, 65536)
+    rsot.tuned(c, None, 1e-3, "dense", cache)     # another rule: its own class
+    assert c.autotuned == 1
+    assert rsot.shape_class(3, 1_000_000, 65536, 1e-3, "tile") == "d3_q20_n16_e-3_tile"
