@@ -4,29 +4,125 @@
 // inverse-Hessian scaling s'y / y'y (and eps N / sum nu before the first pair
 // exists, the inverse of J's diagonal scale nu_j / eps), strong-Wolfe line
 // search (c1 = 1e-4, c2 = 0.9) by bracketing and safeguarded cubic
-// interpolation, at most max_ls evaluations per search. Host FP64 vectors;
-// every evaluation is one rsot_dual_eval on the device.
+// interpolation, at most max_ls evaluations per search. Host FP64 vectors,
+// their arithmetic spread over a small pool of threads; every evaluation is
+// one rsot_dual_eval on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "rsot_internal.h"
 
 namespace {
 
-double dot(const std::vector<double> &a, const std::vector<double> &b) {
-    double s = 0.0;
-    const size_t n = a.size();
-    for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
-    return s;
-}
+// Vector arithmetic of the solver over NCH fixed chunks. Chunks are spread
+// over up to 16 threads, and sums add the chunk partials in chunk order, so
+// results do not depend on the machine's thread count. Short vectors run on
+// the calling thread.
+class Par {
+  public:
+    static constexpr int NCH = 16;
+    static constexpr size_t MIN_PAR = 32768;
+
+    explicit Par(size_t n) {
+        if (n < MIN_PAR) return;
+        unsigned hw = std::thread::hardware_concurrency();
+        nt_ = (int)std::max(1u, std::min<unsigned>(hw ? hw : 1, NCH));
+        for (int k = 1; k < nt_; ++k) th_.emplace_back([this, k] { worker(k); });
+    }
+    ~Par() {
+        {
+            std::lock_guard<std::mutex> l(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // f(i0, i1) over the chunks of [0, n)
+    void chunks(size_t n, const std::function<void(size_t, size_t)> &f) {
+        if (nt_ <= 1 || n < MIN_PAR) {
+            f(0, n);
+            return;
+        }
+        run([&](int k) {
+            for (int c = k; c < NCH; c += nt_) f(n * c / NCH, n * (c + 1) / NCH);
+        });
+    }
+    double dot(const double *a, const double *b, size_t n) {
+        double part[NCH] = {0};
+        if (nt_ <= 1 || n < MIN_PAR) {
+            double s = 0.0;
+            for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
+            return s;
+        }
+        run([&](int k) {
+            for (int c = k; c < NCH; c += nt_) {
+                double s = 0.0;
+                for (size_t i = n * c / NCH; i < n * (c + 1) / NCH; ++i) s += a[i] * b[i];
+                part[c] = s;
+            }
+        });
+        double s = 0.0;
+        for (int c = 0; c < NCH; ++c) s += part[c];
+        return s;
+    }
+    double dot(const std::vector<double> &a, const std::vector<double> &b) {
+        return dot(a.data(), b.data(), a.size());
+    }
+
+  private:
+    // f(k) on thread k = 0..nt_-1 (k = 0 is the caller); returns when all end
+    void run(const std::function<void(int)> &f) {
+        {
+            std::lock_guard<std::mutex> l(m_);
+            job_ = &f;
+            pending_ = nt_ - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(0);
+        std::unique_lock<std::mutex> l(m_);
+        done_.wait(l, [this] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+    void worker(int k) {
+        long seen = 0;
+        for (;;) {
+            const std::function<void(int)> *job = nullptr;
+            {
+                std::unique_lock<std::mutex> l(m_);
+                cv_.wait(l, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (stop_) return;
+                job = job_;
+            }
+            (*job)(k);
+            std::lock_guard<std::mutex> l(m_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    int nt_ = 1;
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    int pending_ = 0;
+    long gen_ = 0;
+    bool stop_ = false;
+};
 
 struct Evaluator {
     rsot_problem *p;
+    Par *par;
     double eps;
     int evals = 0;
     double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept = 0.0;
@@ -36,14 +132,18 @@ struct Evaluator {
     rsot_status operator()(const std::vector<double> &psi, double &J, std::vector<double> &g) {
         if (cancel && *cancel) return RSOT_ERR_CANCELLED;
         const size_t n = psi.size();
-        std::memcpy(p->hpsi, psi.data(), n * sizeof(double));
+        par->chunks(n, [&](size_t a, size_t b) {
+            std::memcpy(p->hpsi + a, psi.data() + a, (b - a) * sizeof(double));
+        });
         RSOT_HIP(hipMemcpyAsync(p->dpsi, p->hpsi, n * sizeof(double), hipMemcpyHostToDevice,
                                 p->stream));
         RSOT_TRY(rsot_eval_impl(p, eps, p->dpsi, &J, p->dgrad, &last));
         RSOT_HIP(hipMemcpyAsync(p->hgrad, p->dgrad, n * sizeof(double), hipMemcpyDeviceToHost,
                                 p->stream));
         RSOT_HIP(hipStreamSynchronize(p->stream));
-        std::memcpy(g.data(), p->hgrad, n * sizeof(double));
+        par->chunks(n, [&](size_t a, size_t b) {
+            std::memcpy(g.data() + a, p->hgrad + a, (b - a) * sizeof(double));
+        });
         ++evals;
         eval_ms += last.kernel_ms;
         cull_ms += last.setup_ms;
@@ -76,26 +176,32 @@ double cubic_step(double a, double fa, double da, double b, double fb, double db
 struct Point {
     double alpha, f, d;
     std::vector<double> psi, g;
+    double gl1 = 0.0, glinf = 0.0;   // norms of g, from its evaluation
 };
 
 // Strong-Wolfe line search along p (Nocedal & Wright, Algs. 3.5/3.6).
-// On success cur holds the accepted point.
+// On success out holds the accepted point. Points trade their vectors by
+// swap or move; the start point (alpha 0) carries none, since it is never
+// returned.
 rsot_status line_search(Evaluator &ev, const std::vector<double> &psi0, double f0,
                         const std::vector<double> &g0, const std::vector<double> &dir,
                         double alpha1, double c1, double c2, int max_ls, Point &out) {
-    const double d0 = dot(g0, dir);
+    Par &par = *ev.par;
+    const double d0 = par.dot(g0, dir);
     const size_t n = psi0.size();
-    Point prev{0.0, f0, d0, psi0, g0};
+    Point prev{0.0, f0, d0, {}, {}, 0.0, 0.0};
     Point cur;
-    cur.psi.resize(n);
-    cur.g.resize(n);
     auto eval_at = [&](double a, Point &pt) -> rsot_status {
         pt.alpha = a;
         pt.psi.resize(n);
         pt.g.resize(n);
-        for (size_t i = 0; i < n; ++i) pt.psi[i] = psi0[i] + a * dir[i];
+        par.chunks(n, [&](size_t i0, size_t i1) {
+            for (size_t i = i0; i < i1; ++i) pt.psi[i] = psi0[i] + a * dir[i];
+        });
         RSOT_TRY(ev(pt.psi, pt.f, pt.g));
-        pt.d = dot(pt.g, dir);
+        pt.d = par.dot(pt.g, dir);
+        pt.gl1 = ev.last.grad_l1;
+        pt.glinf = ev.last.grad_linf;
         return RSOT_OK;
     };
     // f noise allowance of the approximate-Wolfe acceptance: the objective of
@@ -118,30 +224,30 @@ rsot_status line_search(Evaluator &ev, const std::vector<double> &psi0, double f
         }
         if (cur.f > f0 + c1 * a * d0 || (i > 0 && cur.f >= prev.f)) {
             if (approx_wolfe(cur)) {
-                out = cur;
+                out = std::move(cur);
                 return RSOT_OK;
             }
-            lo = prev;
-            hi = cur;
+            lo = std::move(prev);
+            std::swap(hi, cur);
             zoom = true;
             break;
         }
         if (std::fabs(cur.d) <= -c2 * d0) {
-            out = cur;
+            out = std::move(cur);
             return RSOT_OK;
         }
         if (cur.d >= 0.0) {
-            lo = cur;
-            hi = prev;
+            std::swap(lo, cur);
+            hi = std::move(prev);
             zoom = true;
             break;
         }
-        prev = cur;
+        std::swap(prev, cur);
         a *= 2.0;
     }
     if (!zoom) {
         if (prev.alpha > 0.0 && prev.f < f0) {  // still descending: accept the last point
-            out = prev;
+            out = std::move(prev);
             return RSOT_OK;
         }
         return RSOT_ERR_LINESEARCH;
@@ -152,21 +258,21 @@ rsot_status line_search(Evaluator &ev, const std::vector<double> &psi0, double f
         ++used;
         if (cur.f > f0 + c1 * at * d0 || cur.f >= lo.f) {
             if (approx_wolfe(cur)) {
-                out = cur;
+                out = std::move(cur);
                 return RSOT_OK;
             }
-            hi = cur;
+            std::swap(hi, cur);
         } else {
             if (std::fabs(cur.d) <= -c2 * d0) {
-                out = cur;
+                out = std::move(cur);
                 return RSOT_OK;
             }
-            if (cur.d * (hi.alpha - lo.alpha) >= 0.0) hi = lo;
-            lo = cur;
+            if (cur.d * (hi.alpha - lo.alpha) >= 0.0) std::swap(hi, lo);
+            std::swap(lo, cur);
         }
     }
     if (lo.alpha > 0.0 && lo.f < f0) {  // best bracket end still decreases J
-        out = lo;
+        out = std::move(lo);
         return RSOT_OK;
     }
     return RSOT_ERR_LINESEARCH;
@@ -201,6 +307,7 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         if (!std::isfinite(psi_inout[i])) return RSOT_ERR_NONFINITE;
 
     const auto t0 = std::chrono::steady_clock::now();
+    Par par(n);
     std::vector<double> psi(psi_inout, psi_inout + n), g(n), dir(n), q(n);
     rsot_solve_info inf{};
     rsot_status status = RSOT_OK;
@@ -229,7 +336,7 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
     };
 
     for (int stage = 0; stage < sp.n_eps; ++stage) {
-        Evaluator ev{p, sp.eps_schedule[stage]};
+        Evaluator ev{p, &par, sp.eps_schedule[stage]};
         ev.cancel = sp.cancel;
         const bool final_stage = stage == sp.n_eps - 1;
         const double tol = (!final_stage && sp.stage_tol > 0.0) ? sp.stage_tol : sp.tol;
@@ -247,7 +354,7 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         }
         double gl1 = ev.last.grad_l1, glinf = ev.last.grad_linf;
         std::vector<std::vector<double>> S, Y;
-        std::vector<double> rho;
+        std::vector<double> rho, sv, yv;
         int it = 0;
         rsot_status st = RSOT_OK;
         while (gl1 > tol) {
@@ -256,30 +363,39 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
                 break;
             }
             // two-loop recursion: dir = -H g
-            q = g;
+            auto axpy = [&](std::vector<double> &yv, double a, const std::vector<double> &xv) {
+                par.chunks(n, [&](size_t i0, size_t i1) {
+                    for (size_t t = i0; t < i1; ++t) yv[t] += a * xv[t];
+                });
+            };
+            auto scaled = [&](std::vector<double> &yv, double a, const std::vector<double> &xv) {
+                par.chunks(n, [&](size_t i0, size_t i1) {
+                    for (size_t t = i0; t < i1; ++t) yv[t] = a * xv[t];
+                });
+            };
+            scaled(q, 1.0, g);
             const int k = (int)S.size();
             std::vector<double> al(k);
             for (int i = k - 1; i >= 0; --i) {
-                al[i] = rho[i] * dot(S[i], q);
-                for (size_t t = 0; t < n; ++t) q[t] -= al[i] * Y[i][t];
+                al[i] = rho[i] * par.dot(S[i], q);
+                axpy(q, -al[i], Y[i]);
             }
             double gamma;
             if (k > 0)
-                gamma = dot(S[k - 1], Y[k - 1]) / dot(Y[k - 1], Y[k - 1]);
+                gamma = par.dot(S[k - 1], Y[k - 1]) / par.dot(Y[k - 1], Y[k - 1]);
             else
                 gamma = ev.eps * (double)n / p->sum_nu;
-            for (size_t t = 0; t < n; ++t) q[t] *= gamma;
+            scaled(q, gamma, q);
             for (int i = 0; i < k; ++i) {
-                const double be = rho[i] * dot(Y[i], q);
-                for (size_t t = 0; t < n; ++t) q[t] += S[i][t] * (al[i] - be);
+                const double be = rho[i] * par.dot(Y[i], q);
+                axpy(q, al[i] - be, S[i]);
             }
-            for (size_t t = 0; t < n; ++t) dir[t] = -q[t];
-            if (!(dot(dir, g) < 0.0)) {  // lost descent: restart from the scaled gradient
+            scaled(dir, -1.0, q);
+            if (!(par.dot(dir, g) < 0.0)) {  // lost descent: restart from the scaled gradient
                 S.clear();
                 Y.clear();
                 rho.clear();
-                const double gm = ev.eps * (double)n / p->sum_nu;
-                for (size_t t = 0; t < n; ++t) dir[t] = -gm * g[t];
+                scaled(dir, -ev.eps * (double)n / p->sum_nu, g);
             }
             Point np;
             p->absJ_ref = std::fabs(J);
@@ -288,40 +404,46 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
                 S.clear();
                 Y.clear();
                 rho.clear();
-                const double gm = ev.eps * (double)n / p->sum_nu;
-                for (size_t t = 0; t < n; ++t) dir[t] = -gm * g[t];
+                scaled(dir, -ev.eps * (double)n / p->sum_nu, g);
                 ls = line_search(ev, psi, J, g, dir, 1.0, sp.c1, sp.c2, sp.max_ls, np);
             }
             if (ls != RSOT_OK) {
                 st = ls;
                 break;
             }
-            std::vector<double> sv(n), yv(n);
-            for (size_t t = 0; t < n; ++t) {
-                sv[t] = np.psi[t] - psi[t];
-                yv[t] = np.g[t] - g[t];
-            }
-            const double sy = dot(sv, yv);
+            // history pair (sv, yv persist across iterations; the pair that
+            // drops out of the memory lends its storage to the next one)
+            sv.resize(n);
+            yv.resize(n);
+            par.chunks(n, [&](size_t i0, size_t i1) {
+                for (size_t t = i0; t < i1; ++t) {
+                    sv[t] = np.psi[t] - psi[t];
+                    yv[t] = np.g[t] - g[t];
+                }
+            });
+            const double sy = par.dot(sv, yv);
             if (sy > 1e-300) {
-                S.push_back(std::move(sv));
-                Y.push_back(std::move(yv));
-                rho.push_back(1.0 / sy);
-                if ((int)S.size() > sp.lbfgs_m) {
+                std::vector<double> os, oy;
+                if ((int)S.size() >= sp.lbfgs_m) {
+                    os = std::move(S.front());
+                    oy = std::move(Y.front());
                     S.erase(S.begin());
                     Y.erase(Y.begin());
                     rho.erase(rho.begin());
                 }
+                S.push_back(std::move(sv));
+                Y.push_back(std::move(yv));
+                rho.push_back(1.0 / sy);
+                sv = std::move(os);
+                yv = std::move(oy);
             }
             const double step = np.alpha;
             psi.swap(np.psi);
             g.swap(np.g);
             J = np.f;
-            gl1 = 0.0;
-            glinf = 0.0;
-            for (size_t t = 0; t < n; ++t) {
-                gl1 += std::fabs(g[t]);
-                glinf = std::max(glinf, std::fabs(g[t]));
-            }
+            // norms of the accepted gradient (its evaluation's own, from the device)
+            gl1 = np.gl1;
+            glinf = np.glinf;
             ++it;
             if (sp.callback) {
                 rsot_iter_info ii{};
