@@ -59,7 +59,10 @@ def build_probes() -> str:
     """Builds the standalone instruction-rate microbenchmark."""
     os.makedirs(BUILD, exist_ok=True)
     exe = os.path.join(BUILD, "probe_rates")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", os.path.join(CSRC, "probe_rates.hip"), "-o", exe]
+    # matrix-core results straight into vector registers, as a kernel that
+    # consumes them in the vector ALU would be compiled
+    cmd = [HIPCC, *FLAGS, "-mllvm", "-amdgpu-mfma-vgpr-form", "-x", "hip",
+           os.path.join(CSRC, "probe_rates.hip"), "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True)
     return exe
 

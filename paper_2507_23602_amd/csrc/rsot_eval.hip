@@ -504,16 +504,22 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         if (D == 3) v = fma(x2, r.z, v);
         m = ceil(v + r.w);
     }
+    // the next list entry is read one block ahead, and the block's pair
+    // count before its pairs, so neither load waits at a block boundary
+    uint32_t ent_next = MODE == MODE_DENSE ? (uint32_t)e0 : (e1 > e0 ? row_idx[e0] : 0u);
     for (int64_t e = e0; e < e1; ++e) {
-        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
+        const uint32_t ent = ent_next;
+        if (MODE == MODE_DENSE) ent_next = (uint32_t)(e + 1);
+        else if (e + 1 < e1) ent_next = row_idx[e + 1];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
         const auto T = trec + b * 64;
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
             lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
         } else {
+            const double cnt = (double)blk_cnt[b];
             if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
             else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
-            kept += (double)blk_cnt[b];
+            kept += cnt;
         }
     }
     part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
@@ -648,8 +654,11 @@ __device__ __forceinline__ void pass2_item(QP qp, HP qH, const double4 *__restri
     const double4 rec = trec[j];
     const double G = MODE == MODE_MASK ? tG[j] : 0.0;
     double acc = 0.0;
+    uint32_t ent_next = MODE == MODE_DENSE ? (uint32_t)e0 : (e1 > e0 ? col_idx[e0] : 0u);
     for (int64_t e = e0; e < e1; ++e) {
-        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
+        const uint32_t ent = ent_next;
+        if (MODE == MODE_DENSE) ent_next = (uint32_t)(e + 1);
+        else if (e + 1 < e1) ent_next = col_idx[e + 1];
         const int64_t t = ent & ~RSOT_PARTIAL_BIT;
         const auto Q = qp + t * 64;
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
