@@ -276,7 +276,8 @@ typedef struct {
 typedef struct {
     int iterations;             /* accepted iterations, all stages                 */
     int evaluations;            /* dual evaluations, all stages                    */
-    int stages;                 /* stages completed                                */
+    int stages;                 /* stages run; after an error the last of them is
+                                   the one that stopped (resume from it with psi) */
     double J, grad_l1, grad_linf;
     double seconds;             /* wall time of the solve                           */
     double eval_ms;             /* device time spent in evaluations                */

@@ -314,12 +314,8 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
     double J = 0.0;
     double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept_sum = 0.0;
     int total_it = 0, total_ev = 0;
-    const double saved_ref = p->absJ_ref;
 
     auto finish = [&](rsot_status st) {
-        // centre: sum_j nu_j psi_j = 0 is the representative of App. A; the
-        // evaluation is invariant under constant shifts when masses balance
-        std::vector<double> nu(n);
         std::memcpy(psi_inout, psi.data(), n * sizeof(double));
         inf.iterations = total_it;
         inf.evaluations = total_ev;
@@ -478,7 +474,6 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
             break;
         }
     }
-    (void)saved_ref;
     // centre the potential: sum_j nu_j psi_j = 0
     {
         std::vector<double> nu(n);

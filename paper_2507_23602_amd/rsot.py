@@ -42,8 +42,14 @@ _PREC_NAMES = {"mixed": PREC_MIXED, "fp64": PREC_FP64}
 
 
 class RsotError(RuntimeError):
-    def __init__(self, code: int, what: str):
+    """A library call returned an error status. Solves attach the best
+    accepted iterate (``psi``) and the solve info (``info``), which the
+    library writes on every outcome: they are the state to resume from."""
+
+    def __init__(self, code: int, what: str, psi=None, info=None):
         self.code = code
+        self.psi = psi
+        self.info = info
         super().__init__(f"{what}: {status_string(code)} ({code})")
 
 
@@ -421,7 +427,7 @@ class Problem:
         rc = load_library().rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data,
                                        ctypes.byref(info))
         if rc not in (OK, ERR_NOT_CONVERGED):
-            raise RsotError(rc, "rsot_solve")
+            raise RsotError(rc, "rsot_solve", psi=psi, info=info.as_dict())
         return psi, info.as_dict()
 
     def solve_learned(self, mlp, cond, eps_schedule, tol=1e-6, max_iter=10000, lbfgs_m=10,

@@ -81,3 +81,35 @@ def test_exp2f_mean_error_on_device():
     mean = rel.mean().item()
     _say(f"  exp2f mean rel error {mean:.3e}, max {rel.abs().max().item():.3e}")
     assert abs(mean - (-3.40e-9)) < 0.5e-9
+
+
+def test_cancel_and_resume_from_the_returned_iterate():
+    """Recovery: a solve stopped by its callback returns its best accepted
+    iterate and the stage it stopped in; the remaining stages, started from
+    that iterate, reach the same minimiser as an uninterrupted solve."""
+    from paper_2507_23602_amd import rsot
+    _say("cancel + resume")
+    p = W.square_uniform(16, 64, seed=3, eps=2.5e-3)
+    prob = rsot.Problem(p.x, p.mu, p.y, p.nu, precision="fp64")
+    sched = [0.04, 0.02, 0.01, 0.005, 0.0025]
+    ref, info_ref = prob.solve(sched, tol=1e-9, stage_tol=1e-6)
+    assert info_ref["status"] == rsot.OK
+
+    def stop(it):
+        return it.stage == 2 and it.iteration == 3
+
+    with pytest.raises(rsot.RsotError) as e:
+        prob.solve(sched, tol=1e-9, stage_tol=1e-6, callback=stop)
+    err = e.value
+    assert err.code == rsot.ERR_CANCELLED
+    assert err.info["stages"] == 3 and err.info["status"] == rsot.ERR_CANCELLED
+    assert np.all(np.isfinite(err.psi))
+    k = err.info["stages"] - 1
+    psi, info = prob.solve(sched[k:], psi0=err.psi, tol=1e-9, stage_tol=1e-6)
+    _say(f"  resumed at stage {k}: {info['iterations']} it, |g|_1 {info['grad_l1']:.2e}")
+    assert info["status"] == rsot.OK
+    r = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    assert np.abs(r.grad).sum() <= 2e-9
+    err_psi = np.max(np.abs(psi - ref))
+    _say(f"  max |psi_resumed - psi_uninterrupted| = {err_psi:.3e}")
+    assert err_psi < 1e-5 * p.eps * p.n ** 0.5

@@ -336,3 +336,32 @@ def test_empty_set_handling_pointwise():
     assert r.nempty == int((sq >= 0.05).sum()) > 0
     assert np.all(np.isneginf(r.L[sq >= 0.05]))
     assert abs((r.grad[0] + 1.0) - mu[sq < 0.05].sum()) < 1e-14
+
+
+# -- stored record ------------------------------------------------------------
+# The paper prints no per-instance values; tests/golden/config1_oracle.json
+# records the oracle on config 1 (written by tests/golden/make_golden.py,
+# which calls only the oracle and the generators). Catches an unintended
+# change of the input generators or of the oracle's arithmetic; agreement to
+# rounding (the oracle's thread count changes the summation order).
+def test_golden_config1_record():
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(here, "config1_oracle.json")) as f:
+        ref = json.load(f)
+    spec = importlib.util.spec_from_file_location("make_golden",
+                                                  os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    now = mg.compute()
+    assert now["n_quad"] == ref["n_quad"] == 6144 and now["n_target"] == ref["n_target"] == 256
+    for key in ("dense_zero", "dense_random", "geom_random"):
+        a, b = now[key], ref[key]
+        assert a["kept"] == b["kept"], key
+        assert abs(a["J"] - b["J"]) <= 1e-13 * abs(b["J"]), key
+        np.testing.assert_allclose(a["grad"], b["grad"], rtol=0, atol=1e-15)
+        if "L" in b:
+            np.testing.assert_allclose(a["L"], b["L"], rtol=1e-13, atol=0)
+    assert now["geom_random"]["C"] == pytest.approx(ref["geom_random"]["C"], rel=1e-14)
