@@ -63,6 +63,25 @@ __device__ __forceinline__ double4 ld4(const RSOT_CAS double4 *p) {
     return r;
 }
 
+// Target record k of a block for the objective pass. 3D: the 32-byte
+// records {Y0, Y1, Y2, B}. 2D: the packed 24-byte copies {Y0, Y1, B}, so the
+// eight records of a chunk are 192 contiguous bytes that load as three
+// 64-byte scalar loads (the 32-byte records with their unused third
+// component would load as sixteen 8- and 16-byte pieces).
+template <int D, typename P>
+__device__ __forceinline__ double4 trec_at(P T, int k) {
+    if constexpr (D == 3) {
+        return ld4(T + k);
+    } else {
+        double4 r;
+        r.x = T[3 * k + 0];
+        r.y = T[3 * k + 1];
+        r.z = 0.0;
+        r.w = T[3 * k + 2];
+        return r;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-target records and block statistics
 // ---------------------------------------------------------------------------
@@ -71,7 +90,8 @@ __global__ __launch_bounds__(256) void k_prep_targets(
     const double *__restrict__ psi, const int32_t *__restrict__ tperm,
     const double *__restrict__ ty, const double *__restrict__ tnu,
     const double *__restrict__ tlog2nu, int64_t n_blocks, double kappa, double cs,
-    double4 *__restrict__ trec, double *__restrict__ tpsi, double *__restrict__ blk_stat) {
+    double4 *__restrict__ trec, double *__restrict__ trec3, double *__restrict__ tpsi,
+    double *__restrict__ blk_stat) {
     const int lane = threadIdx.x & 63;
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= n_blocks) return;
@@ -87,6 +107,11 @@ __global__ __launch_bounds__(256) void k_prep_targets(
     rec.z = 2.0 * kappa * cs * y2;
     rec.w = real ? kappa * (ps - cs * r2) + tlog2nu[j] : -INFINITY;
     trec[j] = rec;
+    if (D == 2) {
+        trec3[j * 3 + 0] = rec.x;
+        trec3[j * 3 + 1] = rec.y;
+        trec3[j * 3 + 2] = rec.w;
+    }
     tpsi[j] = ps;
     const bool fin = isfinite(ps);
     const double vmax = wave_max(real && fin ? ps : -INFINITY);
@@ -395,7 +420,7 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
         double cm = -INFINITY;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = ld4(T + k0 + k);
+            const double4 r = trec_at<D>(T, k0 + k);
             double v = x0 * r.x;
             v = fma(x1, r.y, v);
             if (D == 3) v = fma(x2, r.z, v);
@@ -445,7 +470,7 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
         float cs = 0.0f;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = ld4(T + k0 + k);
+            const double4 r = trec_at<D>(T, k0 + k);
             double v = r.w - m;
             v = fma(x0, r.x, v);
             v = fma(x1, r.y, v);
@@ -467,7 +492,7 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
             cs = 0.0f;
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const double4 r = ld4(T + k0 + k);
+                const double4 r = trec_at<D>(T, k0 + k);
                 double v = r.w - m;
                 v = fma(x0, r.x, v);
                 v = fma(x1, r.y, v);
@@ -484,9 +509,10 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
 // targets, and the number of pairs it summed. Rows of very different length
 // (a tile far from every target keeps many blocks) are split into segments,
 // so no wavefront carries a whole long row.
-template <int D, bool F64, int MODE, typename RP, typename GP, typename CP, typename IP>
-__device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP trec, GP tG,
-                                           CP blk_cnt, IP row_idx, int64_t t, int64_t e0,
+template <int D, bool F64, int MODE, typename RP, typename R3, typename GP, typename CP,
+          typename IP>
+__device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP trec, R3 trec3,
+                                           GP tG, CP blk_cnt, IP row_idx, int64_t t, int64_t e0,
                                            int64_t e1, double kcs, int64_t w, int lane,
                                            double *__restrict__ part, double *__restrict__ partk) {
     const int64_t q = t * 64 + lane;
@@ -498,7 +524,10 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
     if (FAST && e1 > e0) {
         // reference from the first target of the first block (a kept target)
         const uint32_t ent0 = MODE == MODE_DENSE ? (uint32_t)e0 : row_idx[e0];
-        const double4 r = ld4(trec + (int64_t)(ent0 & ~RSOT_PARTIAL_BIT) * 64);
+        const int64_t b0 = (int64_t)(ent0 & ~RSOT_PARTIAL_BIT);
+        double4 r;
+        if constexpr (D == 3) r = trec_at<D>(trec + b0 * 64, 0);
+        else r = trec_at<D>(trec3 + b0 * 192, 0);
         double v = x0 * r.x;
         v = fma(x1, r.y, v);
         if (D == 3) v = fma(x2, r.z, v);
@@ -512,15 +541,18 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         if (MODE == MODE_DENSE) ent_next = (uint32_t)(e + 1);
         else if (e + 1 < e1) ent_next = row_idx[e + 1];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
-        const auto T = trec + b * 64;
-        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
-            lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
-        } else {
-            const double cnt = (double)blk_cnt[b];
-            if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
-            else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
-            kept += cnt;
-        }
+        auto block = [&](auto T) {
+            if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
+                lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
+            } else {
+                const double cnt = (double)blk_cnt[b];
+                if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
+                else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
+                kept += cnt;
+            }
+        };
+        if constexpr (D == 3) block(trec + b * 64);
+        else block(trec3 + b * 192);
     }
     part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
     partk[w * 64 + lane] = kept;
@@ -529,8 +561,9 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
 template <int D, bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_pass1(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
-    const double *__restrict__ tG, const int32_t *__restrict__ blk_cnt,
-    const uint32_t *__restrict__ row_idx, const int32_t *__restrict__ wi_tile,
+    const double *__restrict__ trec3, const double *__restrict__ tG,
+    const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
+    const int32_t *__restrict__ wi_tile,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm, int64_t n_items,
     int64_t n_blocks, int64_t seg1, int64_t n_seg1, double kcs, double *__restrict__ part,
     double *__restrict__ partk) {
@@ -553,7 +586,8 @@ __global__ __launch_bounds__(256) void k_pass1(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    pass1_item<D, F64, MODE>(qp, trec, tG, blk_cnt, row_idx, t, e0, e1, kcs, w, lane, part, partk);
+    pass1_item<D, F64, MODE>(qp, trec, trec3, tG, blk_cnt, row_idx, t, e0, e1, kcs, w, lane, part,
+                             partk);
 }
 
 // One wavefront per tile: merge the tile's partial log-sum-exps (FP64) into
@@ -717,6 +751,7 @@ struct BatchDesc {
     const double4 *qp;
     const double *qH;
     const double4 *trec;
+    const double *trec3;
     const double *tG;
     const int32_t *blk_cnt;
     const uint32_t *row_idx;
@@ -792,7 +827,8 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
             e0 = uniform_const(d.wi1_range)[2 * w];
             e1 = uniform_const(d.wi1_range)[2 * w + 1];
         }
-        pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.tG),
+        pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.trec3),
+                                   uniform_const(d.tG),
                                    uniform_const(d.blk_cnt), uniform_const(d.row_idx), t, e0, e1,
                                    d.kcs, w, lane, d.part1, d.part1k);
     }
@@ -962,7 +998,8 @@ static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
     const unsigned grid = MODE == MODE_DENSE ? (unsigned)((pw.n_items + 3) / 4)
                                              : xcd_grid((pw.n_items + 3) / 4);
     hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp,
-                       p->trec, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile, p->wi1_range,
+                       p->trec, p->trec3, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile,
+                       p->wi1_range,
                        p->wi1_perm, pw.n_items, p->n_blocks, pw.seg1, pw.n_seg1, kcs, p->part1,
                        p->part1k);
     hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
@@ -1059,12 +1096,12 @@ static rsot_status plan_begin(EvalPlan &e) {
     const dim3 gtile((unsigned)((p->n_tiles + 3) / 4));
     if (D == 2)
         hipLaunchKernelGGL(k_prep_targets<2>, gblk, dim3(256), 0, st, e.psi, p->tperm, p->ty,
-                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->tpsi,
-                           p->blk_stat);
+                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->trec3,
+                           p->tpsi, p->blk_stat);
     else
         hipLaunchKernelGGL(k_prep_targets<3>, gblk, dim3(256), 0, st, e.psi, p->tperm, p->ty,
-                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->tpsi,
-                           p->blk_stat);
+                           p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->trec3,
+                           p->tpsi, p->blk_stat);
     hipLaunchKernelGGL(k_pre_scalars, dim3(1), dim3(256), 0, st, p->blk_stat, p->n_blocks, e.rule,
                        eps, p->C0 < 0 ? 0.0 : p->C0, p->nu_min, p->nu_max, p->opt.tau,
                        p->absJ_ref, p->log_D_prev, p->opt.delta_thr, p->dscal);
@@ -1376,6 +1413,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.qp = p->qp;
         d.qH = p->qH;
         d.trec = p->trec;
+        d.trec3 = p->trec3;
         d.tG = p->tG;
         d.blk_cnt = p->blk_cnt;
         d.row_idx = p->row_idx;

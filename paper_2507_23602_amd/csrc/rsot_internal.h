@@ -63,6 +63,7 @@ struct rsot_problem {
     double *tlog2nu = nullptr;   // [n_pad]
     int32_t *tperm = nullptr;    // [n_pad]
     double4 *trec = nullptr;     // [n_pad] per evaluation {Y0,Y1,Y2,B}
+    double *trec3 = nullptr;     // [3 n_pad] d = 2: the same records packed {Y0,Y1,B}
     double *tG = nullptr;        // [n_pad] per evaluation cutoff constant
     double *tpsi = nullptr;      // [n_pad] sorted psi (per evaluation)
     double *blk_lo = nullptr;    // [n_blocks*3]

@@ -457,6 +457,7 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_TRY(dalloc(p, &p->tlog2nu, p->n_pad));
     RSOT_TRY(dalloc(p, &p->tperm, p->n_pad));
     RSOT_TRY(dalloc(p, &p->trec, p->n_pad));
+    if (p->dim == 2) RSOT_TRY(dalloc(p, &p->trec3, p->n_pad * 3));
     RSOT_TRY(dalloc(p, &p->tG, p->n_pad));
     RSOT_TRY(dalloc(p, &p->tpsi, p->n_pad));
     RSOT_TRY(dalloc(p, &p->blk_lo, p->n_blocks * 3));
