@@ -126,6 +126,7 @@ __global__ __launch_bounds__(512) void k_mlp_in(const float *__restrict__ feats,
                                                 uint16_t *__restrict__ Hkb,
                                                 uint16_t *__restrict__ Hrb) {
     __shared__ float sF[32][8];
+    __shared__ uint16_t sH[32][WID + 8];   // the tile's bf16 activations (528-byte rows)
     const int lane = threadIdx.x & 63, cbk = threadIdx.x >> 6;
     const int li = lane & 31, lh = lane >> 5;
     const int col = cbk * 32 + li;
@@ -160,12 +161,20 @@ __global__ __launch_bounds__(512) void k_mlp_in(const float *__restrict__ feats,
             for (int f = 0; f < NIN; ++f) z = fmaf(sF[rl][f], w[f], z);
             z4[q] = z;
             h4[q] = f2bf(gelu(z));
-            Hkb[kb_idx(rb + q, col, RP)] = h4[q];
+            sH[rl][col] = h4[q];
         }
         if (TRAIN) {
             *(float4 *)(Z0 + fr_idx(rb, col)) = make_float4(z4[0], z4[1], z4[2], z4[3]);
             *(uint2 *)(Hrb + rb_idx(rb, col)) = pack4(h4);
         }
+    }
+    __syncthreads();
+    // k-blocked copy from LDS in 16-byte pieces (8 columns of one row): each
+    // 64 consecutive pieces are 1 KB of contiguous output
+    for (int i = threadIdx.x; i < 32 * (WID / 8); i += 512) {
+        const int c16 = i >> 6, rl = (i >> 1) & 31, hf = i & 1;
+        const int c = c16 * 16 + hf * 8;
+        *(uint4 *)(Hkb + kb_idx(r0 + rl, c, RP)) = *(const uint4 *)&sH[rl][c];
     }
 }
 
@@ -241,13 +250,22 @@ __global__ __launch_bounds__(GW * 64) void k_mlp_layer(LayerArgs a) {
             for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
         const uint16_t *ap = a.A + (row0 + li) * 16 + lh * 8;
         const uint16_t *bl = sB + (wc * 128 + li) * KPAD + lh * 8;
-#pragma unroll 2
-        for (int k0 = 0; k0 < WID; k0 += 16) {
-            const bf16x8 fa = ld8(ap + (int64_t)(k0 >> 4) * RP * 16);
+        // operand fragments are requested eight k steps at a time, so the
+        // wave waits for memory twice per tile instead of once per k step
+#pragma unroll 1
+        for (int k0 = 0; k0 < WID / 16; k0 += 8) {
+            bf16x8 fa[8];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const bf16x8 fb = ld8(bl + cb * 32 * KPAD + k0);
-                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[cb], 0, 0, 0);
+            for (int k = 0; k < 8; ++k) fa[k] = ld8(ap + (int64_t)(k0 + k) * RP * 16);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const bf16x8 fb = ld8(bl + cb * 32 * KPAD + (k0 + k) * 16);
+                    acc[cb] =
+                        __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[k], fb, acc[cb], 0, 0, 0);
+                }
             }
         }
         // accumulator element (cb, 4g+q): row row0 + 8g + 4lh + q, column
@@ -275,6 +293,7 @@ __global__ __launch_bounds__(GW * 64) void k_mlp_layer(LayerArgs a) {
                     }
                 }
             }
+        }
         } else if (EPI == EPI_BWD) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
@@ -461,15 +480,30 @@ __global__ __launch_bounds__(256) void k_mlp_gemm_dw(const uint16_t *__restrict_
     // rows r0..r0+15 of row block r0/16 start at (r0/16) * 256 * 16
     const uint16_t *pa = Hrb + (chunk * (CHUNK_DW / 16) * WID + k0r + li) * 16 + lh * 8;
     const uint16_t *pb = Drb + (chunk * (CHUNK_DW / 16) * WID + n0c + li) * 16 + lh * 8;
-#pragma unroll 4
-    for (int rbk = 0; rbk < CHUNK_DW / 16; ++rbk) {
-        const int64_t o = (int64_t)rbk * WID * 16;
-        const bf16x8 a0 = ld8(pa + o), a1 = ld8(pa + o + 32 * 16);
-        const bf16x8 b0 = ld8(pb + o), b1 = ld8(pb + o + 32 * 16);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    // one wave per SIMD: the fragments of eight row blocks are requested
+    // together, so the wave waits for memory eight times per chunk, not 64
+#pragma unroll 1
+    for (int rb0 = 0; rb0 < CHUNK_DW / 16; rb0 += 8) {
+        bf16x8 fa[8][2], fb[8][2];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t o = (int64_t)(rb0 + u) * WID * 16;
+            fa[u][0] = ld8(pa + o);
+            fa[u][1] = ld8(pa + o + 32 * 16);
+            fb[u][0] = ld8(pb + o);
+            fb[u][1] = ld8(pb + o + 32 * 16);
+        }
+        // keep the scheduler from interleaving the loads with the products
+        // (it would trade the batching back for fewer live registers)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[u][x], fb[u][y],
+                                                                        acc[x][y], 0, 0, 0);
     }
     float *dst = part + chunk * (int64_t)(3 * WID * WID);
 #pragma unroll
@@ -547,6 +581,16 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ pa
     // eight independent sums (c = 8m + u), added in a fixed order
     double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t c = 0;
+    for (; c + 16 <= count; c += 16) {
+        // sixteen partials requested together; partial c still goes to
+        // sum c % 8, in increasing c
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = src[(c + u) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s8[u & 7] += v[u];
+    }
     for (; c + 8 <= count; c += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) s8[u] += src[(c + u) * stride];
