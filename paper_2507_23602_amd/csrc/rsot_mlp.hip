@@ -293,7 +293,6 @@ __global__ __launch_bounds__(GW * 64) void k_mlp_layer(LayerArgs a) {
                     }
                 }
             }
-        }
         } else if (EPI == EPI_BWD) {
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
