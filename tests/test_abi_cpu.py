@@ -87,3 +87,54 @@ def test_autotune_cache_by_shape_class(tmp_path):
     rsot.tuned(c, None, 1e-3, "dense", cache)     # another rule: its own class
     assert c.autotuned == 1
     assert rsot.shape_class(3, 1_000_000, 65536, 1e-3, "tile") == "d3_q20_n16_e-3_tile"
+
+
+def test_arguments_are_checked_before_any_device_work():
+    """Every entry point validates its arguments before touching the device,
+    so these calls return their documented status on a machine without a
+    GPU; destroy calls accept NULL."""
+    import ctypes
+
+    import numpy as np
+    lib = rsot.load_library()
+    x = np.random.default_rng(0).uniform(0, 1, (10, 2))
+    mu = np.full(10, 0.1)
+    y = np.random.default_rng(1).uniform(0, 1, (3, 2))
+    nu = np.full(3, 1 / 3)
+    P = lambda a: a.ctypes.data  # noqa: E731
+    out = ctypes.c_void_p(123)
+
+    def create(dim=2, nq=10, n=3, xp=P(x), opt=None, outp=None):
+        o = rsot.Options()
+        lib.rsot_options_default(ctypes.byref(o))
+        for k, v in (opt or {}).items():
+            setattr(o, k, v)
+        return lib.rsot_problem_create(dim, nq, xp, P(mu), n, P(y), P(nu), ctypes.byref(o), None,
+                                       ctypes.byref(out) if outp is None else outp)
+
+    for kw in ({"dim": 4}, {"dim": 1}, {"nq": 0}, {"n": 0}, {"nq": -5}, {"xp": None},
+               {"opt": {"cost_scale": 0.0}}, {"opt": {"tau": 0.0}}, {"opt": {"truncation": 9}},
+               {"opt": {"precision": 7}}, {"opt": {"mem_limit_bytes": -1}}):
+        out.value = 123
+        assert create(**kw) == rsot.ERR_INVALID_ARG, kw
+        assert out.value is None            # *out cleared on failure
+    J = ctypes.c_double(0.0)
+    psi = np.zeros(3)
+    assert lib.rsot_dual_eval(None, 0.01, P(psi), ctypes.byref(J), None, None) == \
+        rsot.ERR_INVALID_ARG
+    sp = rsot.SolveParams()
+    lib.rsot_solve_params_default(ctypes.byref(sp))
+    assert lib.rsot_solve(None, ctypes.byref(sp), P(psi), None) == rsot.ERR_INVALID_ARG
+    assert lib.rsot_dual_eval_batched(None, 0, None, None, None, None, None, None) == \
+        rsot.ERR_INVALID_ARG
+    m = ctypes.c_void_p(123)
+    assert lib.rsot_mlp_create(None, None, ctypes.byref(m)) == rsot.ERR_INVALID_ARG
+    params = np.zeros(rsot.MLP_NPARAMS, dtype=np.float32)
+    params[17] = np.nan
+    assert lib.rsot_mlp_create(P(params), None, ctypes.byref(m)) == rsot.ERR_NONFINITE
+    assert m.value is None
+    lib.rsot_problem_destroy(None)
+    lib.rsot_mlp_destroy(None)
+    lib.rsot_multilevel_destroy(None)
+    texts = {lib.rsot_status_string(c).decode() for c in range(9)}
+    assert len(texts) == 9 and all(texts)
