@@ -10,7 +10,8 @@
 // The expansion is formed in FP64 (full rate on CDNA), so the argument of every
 // exponential carries ~1e-16 relative error before it is rounded to FP32; the
 // rounded argument is then O(10) for every term that matters, which keeps the
-// relative error of each weight near FP32 round-off.
+// relative error of each weight near FP32 round-off (about |u| 2^-24 for an
+// argument u, and the rounding errors of different pairs are independent).
 //
 // Objective pass (one wavefront = one 64-point tile, lane = point): the
 // per-point log-sum-exp Lt(x) = log2 sum_j 2^(B_j + x.Y_j) is accumulated
