@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
+    ap.add_argument("--ml-spread", action="store_true",
+                    help="multilevel leg with the eps stages spread over all four levels")
     ap.add_argument("--multilevel", action="store_true",
                     help="also time the combined multilevel solve of the 2D disk workload")
     ap.add_argument("--batched", type=int, default=0,
@@ -228,7 +230,7 @@ def main():
         out["extras"] = extras
 
     if args.multilevel:
-        out.setdefault("extras", {})["multilevel"] = multilevel_leg()
+        out.setdefault("extras", {})["multilevel"] = multilevel_leg(spread=args.ml_spread)
     if args.batched:
         out.setdefault("extras", {})["batched"] = batched_leg(args.batched)
     if args.mlp:
@@ -392,9 +394,11 @@ def batched_leg(k):
     return res
 
 
-def multilevel_leg():
+def multilevel_leg(spread=False):
     """Time to ||grad||_1 < 1e-6 of the combined multilevel solve (Sec. 5.3)
-    with the eps schedule, on the 2D disk workload; per-level breakdown."""
+    with the eps schedule, on the 2D disk workload; per-level breakdown.
+    Default: the schedule on the two coarsest levels and the final eps on the
+    finer ones; spread=True: the final eps first on the finest level."""
     import torch
     from paper_2507_23602_amd import rsot, workloads as W
     c3 = W.config3()
@@ -412,15 +416,17 @@ def multilevel_leg():
             log(f"[bench] multilevel: stage eps {it.eps:.2e}, iteration {it.iteration}, "
                 f"|g|_1 {it.grad_l1:.2e}, kept {it.kept_pairs:.3e}")
         return 0
-    psi, info = ml.solve(c3["eps"], c3["level"], tol=1e-6, level_tol=1e-5, stage_tol=1e-5,
-                         callback=progress)
+    key = "_spread" if spread else ""
+    psi, info = ml.solve(c3["eps" + key], c3["level" + key], tol=1e-6, level_tol=1e-5,
+                         stage_tol=1e-5, callback=progress)
     t_s = time.perf_counter() - t0
     log(f"[bench] multilevel: hierarchy {t_h:.2f}s, solve {t_s:.2f}s, status {info['status']}, "
         f"|g|_1 {info['grad_l1']:.2e}, iterations {info['iterations']}, "
         f"seconds {[round(v, 3) for v in info['seconds']]}, "
         f"refine {[round(v, 3) for v in info['refine_seconds']]}")
     ml.close()
-    return {"workload": c3["name"], "hierarchy_seconds": t_h, "solve_seconds": t_s,
+    return {"workload": c3["name"], "schedule": "spread" if spread else "coarse",
+            "hierarchy_seconds": t_h, "solve_seconds": t_s,
             "target_sizes": [int(l[1].numel()) for l in levels], **info}
 
 

@@ -106,11 +106,10 @@ def train(feats, target, epochs=20, batch=32768, lr=1e-3, lr_end=1e-5, seed=0, i
 
 
 def _ml_stages(eps):
+    """The eps schedule of Sec. 4.2 on the coarsest level, then the final
+    eps alone on the two finer levels (each from the refined potential)."""
     E = eps_schedule(eps)
-    while len(E) < 3:
-        E = [E[0]] + E
-    level = [0] * (len(E) - 2) + [1, 2]
-    return E, level
+    return E + [E[-1], E[-1]], [0] * len(E) + [1, 2]
 
 
 def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
@@ -118,8 +117,8 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
     """Held-out instances: wall-clock seconds and iterations to ||g||_1 < tol
     from (a) zero with the eps schedule, (b) zero at the final eps alone,
     (c) the learned start (rsot_solve_learned), (d) the combined multilevel
-    start (Sec. 5.3) with the eps schedule spread over the levels. Stages and
-    levels before the last stop at 10 tol."""
+    start (Sec. 5.3): the eps schedule on the coarsest level, the final eps on
+    the finer ones. Stages and levels before the last stop at 10 tol."""
     import torch
     out = []
     hier = None
