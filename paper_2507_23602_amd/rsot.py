@@ -521,7 +521,7 @@ class Multilevel:
             pass
 
     def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000, callback=None,
-              stage_tol=0.0):
+              stage_tol=0.0, lbfgs_m=10):
         """rsot_solve_multilevel. ``callback(iter_info)`` is called after every
         accepted iteration of every level; a true return value cancels.
         ``level_tol`` / ``stage_tol``: ||grad||_1 targets of non-final levels
@@ -534,6 +534,7 @@ class Multilevel:
         mp.base.tol = tol
         mp.base.max_iter = max_iter
         mp.base.stage_tol = stage_tol
+        mp.base.lbfgs_m = lbfgs_m
         cb = None
         if callback is not None:
             def _cb(ptr, _user):

@@ -118,7 +118,9 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
     from (a) zero with the eps schedule, (b) zero at the final eps alone,
     (c) the learned start (rsot_solve_learned), (d) the combined multilevel
     start (Sec. 5.3): the eps schedule on the coarsest level, the final eps on
-    the finer ones. Stages and levels before the last stop at 10 tol."""
+    the finer ones. Levels and eps stages before the last stop at 10 tol
+    (the three levels cost about the same, and solving the coarser two to
+    tol measured slower: 6.60 s against 5.92 s over the 64 test instances)."""
     import torch
     out = []
     hier = None
