@@ -392,9 +392,8 @@ def config3(rings: int = 60, levels: int = 4, n_targets: int = 1 << 20,
 
     eps is halved from 1e-1 (k = 0..9) then set to 1e-4. Two mappings of these
     stages to the four combined levels:
-    * "eps"/"level" (default): the schedule runs on the two coarsest levels
-      (k = 0..6 on level 0; k = 7..9 and 1e-4 on level 1), and levels 2 and 3
-      solve at 1e-4 only, from the refined potential;
+    * "eps"/"level" (default): the whole schedule runs on the coarsest level,
+      and levels 1, 2 and 3 solve at 1e-4 only, from the refined potential;
     * "eps_spread"/"level_spread": stages {0-3}, {4-6}, {7-8}, {9, final},
       so the final eps is first reached on the finest level."""
     meshes = disk_hierarchy(rings, levels)
@@ -402,8 +401,8 @@ def config3(rings: int = 60, levels: int = 4, n_targets: int = 1 << 20,
     y = blob_targets_disk(n_targets, seed=5)
     nu = np.full(n_targets, 1.0 / n_targets)
     sched = [0.1 * 2.0 ** (-k) for k in range(10)] + [1e-4]
-    eps = sched + [1e-4, 1e-4]
-    level = [0] * 7 + [1] * 4 + [2, 3]
+    eps = sched + [1e-4] * 3
+    level = [0] * len(sched) + [1, 2, 3]
     level_spread = [0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 3]
     return {"sources": sources, "y": y, "nu": nu, "target_levels": list(target_levels),
             "eps": eps, "level": level, "eps_spread": sched, "level_spread": level_spread,
