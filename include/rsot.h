@@ -271,6 +271,12 @@ typedef struct {
     rsot_callback callback;     /* called after every accepted iteration, or NULL  */
     void *user;
     volatile int *cancel;       /* polled between evaluations, or NULL             */
+    double absJ_start;          /* |J| reference of the truncation rules for the
+                                   first evaluation (Sec. 4.1 uses |J| of the
+                                   current iterate; later ones use the last
+                                   accepted iterate, and each eps stage starts
+                                   from the previous stage's); 0 = evaluate the
+                                   warm start densely to obtain it; >= 0      */
 } rsot_solve_params;
 
 typedef struct {

@@ -1284,6 +1284,7 @@ extern "C" rsot_status rsot_solve_learned(rsot_problem *p, rsot_mlp *m, const do
         rsot_solve_params one = *sp;
         one.eps_schedule = &eps_f;
         one.n_eps = 1;
+        one.absJ_start = std::fabs(li.J_pred);   // J at the start was just evaluated
         s = rsot_solve(p, &one, psi.data(), info);
     } else {
         li.used_learned = 0;

@@ -142,6 +142,7 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
 
     int it_prev = -1, is_prev = -1;
     double eps_prev = mp->eps[0];
+    double absJ_prev = 0.0;
     std::vector<double> psi;
     double *d_a = nullptr, *d_b = nullptr;
     rsot_status status = RSOT_OK;
@@ -191,6 +192,10 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
             rsot_solve_params sp = mp->base;
             sp.eps_schedule = eps_l.data();
             sp.n_eps = (int)eps_l.size();
+            // the previous level's final |J| serves as the reference of the
+            // truncation rules for this level's warm start (the refined
+            // potential), so its first evaluation need not run dense
+            if (l > 0 && absJ_prev > 0.0) sp.absJ_start = absJ_prev;
             const bool last = (l == Lmax);
             if (!last && mp->level_tol > 0.0) sp.tol = mp->level_tol;
             rsot_solve_info si{};
@@ -200,6 +205,7 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
             inf.eval_ms[l] = si.eval_ms;
             inf.kept_frac[l] = si.kept_frac;
             inf.grad_l1 = si.grad_l1;
+            absJ_prev = std::fabs(si.J);
             if (s != RSOT_OK && !(s == RSOT_ERR_NOT_CONVERGED && !last)) status = s;
             eps_prev = eps_l.back();
         }

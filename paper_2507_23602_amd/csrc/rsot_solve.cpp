@@ -296,7 +296,8 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
     if (!p || !sp_in || !psi_inout) return RSOT_ERR_INVALID_ARG;
     rsot_solve_params sp = *sp_in;
     if (!sp.eps_schedule || sp.n_eps < 1 || !(sp.tol > 0.0) || sp.max_iter < 1 ||
-        sp.lbfgs_m < 1 || !(sp.c1 > 0.0 && sp.c1 < sp.c2 && sp.c2 < 1.0) || sp.max_ls < 2)
+        sp.lbfgs_m < 1 || !(sp.c1 > 0.0 && sp.c1 < sp.c2 && sp.c2 < 1.0) || sp.max_ls < 2 ||
+        !(sp.absJ_start >= 0.0) || !std::isfinite(sp.absJ_start))
         return RSOT_ERR_INVALID_ARG;
     for (int k = 0; k < sp.n_eps; ++k)
         if (!(sp.eps_schedule[k] > 0.0) || !std::isfinite(sp.eps_schedule[k]))
@@ -336,7 +337,12 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         ev.cancel = sp.cancel;
         const bool final_stage = stage == sp.n_eps - 1;
         const double tol = (!final_stage && sp.stage_tol > 0.0) ? sp.stage_tol : sp.tol;
-        p->absJ_ref = 0.0;  // first evaluation of a stage runs dense
+        // |J| reference of the truncation rules: for the first stage the
+        // caller's (0: the warm start is evaluated densely to obtain it), for
+        // later ones the last accepted iterate's, which the previous stage
+        // left (the new stage's warm start is that iterate). D of the INT
+        // rule depends on eps and is taken afresh.
+        if (stage == 0) p->absJ_ref = sp.absJ_start;
         p->have_D = 0;
         rsot_status s = ev(psi, J, g);
         if (s != RSOT_OK) {

@@ -91,7 +91,7 @@ class SolveParams(ctypes.Structure):
                 ("lbfgs_m", ctypes.c_int), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("max_ls", ctypes.c_int), ("stage_tol", ctypes.c_double),
                 ("callback", CALLBACK), ("user", ctypes.c_void_p),
-                ("cancel", ctypes.POINTER(ctypes.c_int))]
+                ("cancel", ctypes.POINTER(ctypes.c_int)), ("absJ_start", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
