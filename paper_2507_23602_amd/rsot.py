@@ -397,7 +397,8 @@ class Problem:
         return t, b, nt.value, nb.value
 
     @staticmethod
-    def _solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback, max_ls):
+    def _solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback, max_ls,
+                      absJ_start=0.0):
         sp = SolveParams()
         load_library().rsot_solve_params_default(ctypes.byref(sp))
         sp.eps_schedule = eps_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -407,6 +408,7 @@ class Problem:
         sp.lbfgs_m = lbfgs_m
         sp.stage_tol = stage_tol
         sp.max_ls = max_ls
+        sp.absJ_start = absJ_start
         cb = None
         if callback is not None:
             def _cb(ptr, _user):
@@ -416,13 +418,15 @@ class Problem:
         return sp, cb
 
     def solve(self, eps_schedule, psi0=None, tol=1e-6, max_iter=10000, lbfgs_m=10,
-              stage_tol=0.0, callback=None, max_ls=20):
+              stage_tol=0.0, callback=None, max_ls=20, absJ_start=0.0):
         """rsot_solve: returns (psi numpy array, info dict). Raises on error
-        codes other than NOT_CONVERGED (reported in info['status'])."""
+        codes other than NOT_CONVERGED (reported in info['status']).
+        ``absJ_start``: |J| reference of the truncation rules for the first
+        evaluation (0: that evaluation runs dense to obtain it)."""
         eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
         psi = np.zeros(self.n) if psi0 is None else np.array(psi0, dtype=np.float64)
         sp, _keep = self._solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback,
-                                       max_ls)
+                                       max_ls, absJ_start)
         info = SolveInfo()
         rc = load_library().rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data,
                                        ctypes.byref(info))

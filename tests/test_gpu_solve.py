@@ -87,6 +87,32 @@ def test_eps_schedule_and_failure_codes():
     assert e.value.code == rsot.ERR_UNBALANCED
 
 
+def test_truncation_reference_across_stages():
+    """Tile rule with an eps schedule: the |J| reference of the truncation
+    thresholds carries from stage to stage, and absJ_start supplies it for
+    the first evaluation. Both solves meet the tolerance at the oracle and
+    agree; an invalid start reference is refused."""
+    from paper_2507_23602_amd import rsot
+    _say("tile rule: |J| reference across stages, absJ_start")
+    p = W.square_uniform(16, 64, seed=3, eps=2.5e-3)
+    prob = rsot.Problem(p.x, p.mu, p.y, p.nu, precision="mixed", truncation="tile", tau=1e-12)
+    sched = [0.04, 0.02, 0.01, 0.005, 0.0025]
+    psi_a, ia = prob.solve(sched, tol=1e-6, stage_tol=1e-5)
+    J0 = oracle.dual_eval(p.x, p.mu, p.y, p.nu, np.zeros(p.n), sched[0]).J
+    psi_b, ib = prob.solve(sched, tol=1e-6, stage_tol=1e-5, absJ_start=abs(J0))
+    _say(f"  dense start: {ia['evaluations']} evals, kept {ia['kept_frac']:.3f}; "
+         f"absJ_start {abs(J0):.3e}: {ib['evaluations']} evals, kept {ib['kept_frac']:.3f}")
+    for psi, info in ((psi_a, ia), (psi_b, ib)):
+        assert info["status"] == rsot.OK and info["stages"] == len(sched)
+        r = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+        assert np.abs(r.grad).sum() <= 1.5e-6
+    assert np.max(np.abs(psi_a - psi_b)) < 2e-5 * p.eps * p.n ** 0.5
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(rsot.RsotError) as e:
+            prob.solve(sched, absJ_start=bad)
+        assert e.value.code == rsot.ERR_INVALID_ARG
+
+
 def test_exp2f_mean_error_on_device():
     """The mixed path removes a measured mean relative error of -3.40e-9 of
     the FP32 exp2 instruction; re-measure it on this device."""
