@@ -287,8 +287,9 @@ def test_full_size_disk_sampled_points():
     workload's 1e-9: the FP32 exponential's mean error (-3.4e-9) is removed
     by a fixed factor calibrated over uniformly spread fractional parts, but
     at eps = 1e-4 most of a point's mass sits in one gradient-pass term whose
-    argument is close to 0, where the instruction is nearly exact, so the
-    factor itself leaves up to 3.4e-9 sum mu in the gradient's sum."""
+    argument is close to log2 mu_q, and on this uniform mesh those share one
+    fractional part, where the error differs from its mean (2.5e-9 of sum mu
+    measured; the per-term bound 8.4e-8 caps it)."""
     import torch
     _say("full size disk, dense and tile rule")
     c3 = W.config3()
