@@ -37,6 +37,27 @@ static inline unsigned xcd_grid(int64_t n_groups) {
     return (unsigned)(((n_groups + 7) / 8) * 8);
 }
 
+// Work items taken in a sorted order (neighbours read the same records) are
+// dealt to the XCDs in runs of RSOT_XCD_RUN consecutive items, run r to XCD
+// r % 8, and each XCD takes its runs in order. A run keeps sorted neighbours
+// on one XCD's L2, and the runs spread the heavy and light parts of the order
+// evenly over the XCDs, which one contiguous range per XCD does not when item
+// costs drift along the order. xcd_run_item gives the sorted position of
+// this wave's item (wave = wave index in a 4-wave workgroup); launch
+// xcd_run_grid(n) workgroups; a result >= n means no work. Every position
+// below n is produced exactly once.
+#define RSOT_XCD_RUN 64
+__device__ __forceinline__ int64_t xcd_run_item(int wave) {
+    const int64_t s = (int64_t)(blockIdx.x >> 3) * 4 + wave;   // slot within this XCD
+    const int64_t run = (s / RSOT_XCD_RUN) * 8 + (int64_t)(blockIdx.x & 7);
+    return run * RSOT_XCD_RUN + s % RSOT_XCD_RUN;
+}
+static inline unsigned xcd_run_grid(int64_t n) {
+    const int64_t runs = (n + RSOT_XCD_RUN - 1) / RSOT_XCD_RUN;
+    const int64_t runs_per_xcd = (runs + 7) / 8;
+    return (unsigned)(runs_per_xcd * (RSOT_XCD_RUN / 4) * 8);
+}
+
 // Lane 0's value of a 64-bit quantity, in scalar registers. The builtin
 // returns a signed int, so each half is widened through uint32_t: a plain
 // (uint64_t) cast would sign-extend the low half into the high one.

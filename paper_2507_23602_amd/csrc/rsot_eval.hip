@@ -578,9 +578,9 @@ __global__ __launch_bounds__(256) void k_pass1(
         e0 = (w % n_seg1) * seg1;
         e1 = std::min<int64_t>(e0 + seg1, n_blocks);
     } else {
-        // items in the order of their first target block, each XCD taking a
-        // contiguous part of that order
-        const int64_t k = xcd_group((n_items + 3) / 4) * 4 + wave;
+        // items in the order of their first target block, dealt to the XCDs
+        // in runs of that order
+        const int64_t k = xcd_run_item(wave);
         if (k >= n_items) return;
         w = perm[k];
         t = wi_tile[w];
@@ -729,10 +729,10 @@ __global__ __launch_bounds__(256) void k_pass2(
         e1 = std::min<int64_t>(e0 + seg, n_tiles);
         w = b * n_seg + sgi;
     } else {
-        // items in the order of their first point tile, each XCD taking a
-        // contiguous part of that order: items that read the same point
-        // records share that XCD's L2
-        const int64_t k = xcd_group((n_wi + 3) / 4) * 4 + wave;
+        // items in the order of their first point tile, dealt to the XCDs in
+        // runs of that order: items that read the same point records share
+        // that XCD's L2
+        const int64_t k = xcd_run_item(wave);
         if (k >= n_wi) return;
         w = perm[k];
         b = wi_block[w];
@@ -997,7 +997,7 @@ struct Pass1Work {
 template <int D, bool F64, int MODE>
 static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
     const unsigned grid = MODE == MODE_DENSE ? (unsigned)((pw.n_items + 3) / 4)
-                                             : xcd_grid((pw.n_items + 3) / 4);
+                                             : xcd_run_grid(pw.n_items);
     hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp,
                        p->trec, p->trec3, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile,
                        p->wi1_range,
@@ -1015,7 +1015,7 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
     if (MODE == MODE_DENSE)
         grid = (unsigned)(((p->n_blocks + 3) / 4) * ((n_seg + 7) / 8) * 8);
     else
-        grid = xcd_grid((n_wi + 3) / 4);
+        grid = xcd_run_grid(n_wi);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
                        p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
                        p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
