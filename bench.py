@@ -374,7 +374,7 @@ def learned_leg(n_train, n_test, epochs):
 def batched_leg(k):
     """k uneven 3D instances (points logU[1e5,4e6], targets logU[4096,262144],
     eps logU[1e-4,1e-2], mixture sources/targets), tile rule tau = 1e-12,
-    mixed precision: one persistent batched call against k single calls, with
+    mixed precision: one batched call against k single calls, with
     the library defaults and with autotuned work granularity."""
     import torch
     from paper_2507_23602_amd import rsot, workloads as W

@@ -169,8 +169,8 @@ rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi, doubl
 /*
  * Evaluates n problems in one call (same quantities as rsot_dual_eval for
  * each): every problem's preparation and culling, one host synchronisation,
- * then one persistent launch per pass in which wavefronts pull (problem, work
- * item) pairs from a shared queue, problems in decreasing order of work.
+ * then one launch per pass over the (problem, work item) pairs of all
+ * problems, numbered with the problems in decreasing order of work.
  * Problems with the FP64 arithmetic or a cutoff rule (GEOM/INT/PW) run their
  * own passes inside the same call. All work is issued on ps[0]'s stream.
  *   ps        n problem handles (distinct)

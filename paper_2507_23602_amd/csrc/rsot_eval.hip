@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void k_pass2(
 }
 
 // ---------------------------------------------------------------------------
-// batched evaluation: one persistent launch per pass over many problems
+// batched evaluation: one launch per pass over many problems
 // ---------------------------------------------------------------------------
 // Work descriptor of one problem in a batch (device memory).
 struct BatchDesc {
@@ -770,17 +770,7 @@ struct BatchDesc {
     double *gpart;
 };
 
-__global__ void k_zero_counter(unsigned long long *c) { *c = 0ull; }
-
-// next work item of the shared queue, same value in every lane
-__device__ inline uint64_t next_item(unsigned long long *counter, int lane) {
-    unsigned long long g = 0;
-    if (lane == 0) g = atomicAdd(counter, 1ull);
-    g = __shfl(g, 0, 64);
-    return uniform_u64((uint64_t)g);
-}
-
-// position k of the problem owning queue item g: begin[k] <= g < begin[k+1]
+// position k of the problem owning group item g: begin[k] <= g < begin[k+1]
 __device__ inline int owner(const int64_t *__restrict__ begin, int n, uint64_t g) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -799,72 +789,66 @@ __device__ __forceinline__ const RSOT_CAS T *uniform_const(const T *p) {
 }
 
 // Objective pass of every problem of one (dimension, rule) group of the
-// batch: waves pull items from one queue (problems in decreasing cost
-// order) until it is empty.
+// batch, one launch: the group's items (problems in decreasing cost order,
+// each problem's items in its own sorted order) are numbered consecutively
+// and dealt to the XCDs in runs as in the single-problem passes; each wave
+// finds its item's problem by binary search and runs the same item body.
 template <int D, int MODE>
 __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restrict__ descs,
                                                        const int32_t *__restrict__ order,
-                                                       const int64_t *__restrict__ begin, int n,
-                                                       unsigned long long *counter) {
+                                                       const int64_t *__restrict__ begin, int n) {
     const int lane = threadIdx.x & 63;
-    const uint64_t total = (uint64_t)begin[n];
-    for (;;) {
-        const uint64_t g = next_item(counter, lane);
-        if (g >= total) break;
-        const int k = owner(begin, n, g);
-        const BatchDesc &d = descs[order[k]];
-        const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
-        int64_t t, e0, e1, w;
-        if (MODE == MODE_DENSE) {
-            // consecutive items share the block segment (target records)
-            const int64_t s1 = v / d.n_tiles;
-            t = v % d.n_tiles;
-            e0 = s1 * d.seg1;
-            e1 = std::min<int64_t>(e0 + d.seg1, d.n_blocks);
-            w = t * d.n_seg1 + s1;
-        } else {
-            w = uniform_const(d.wi1_perm)[v];
-            t = uniform_const(d.wi1_tile)[w];
-            e0 = uniform_const(d.wi1_range)[2 * w];
-            e1 = uniform_const(d.wi1_range)[2 * w + 1];
-        }
-        pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.trec3),
-                                   uniform_const(d.tG),
-                                   uniform_const(d.blk_cnt), uniform_const(d.row_idx), t, e0, e1,
-                                   d.kcs, w, lane, d.part1, d.part1k);
+    const uint64_t g = (uint64_t)xcd_run_item(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    if (g >= (uint64_t)begin[n]) return;
+    const int k = owner(begin, n, g);
+    const BatchDesc &d = descs[order[k]];
+    const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
+    int64_t t, e0, e1, w;
+    if (MODE == MODE_DENSE) {
+        // consecutive items share the block segment (target records)
+        const int64_t s1 = v / d.n_tiles;
+        t = v % d.n_tiles;
+        e0 = s1 * d.seg1;
+        e1 = std::min<int64_t>(e0 + d.seg1, d.n_blocks);
+        w = t * d.n_seg1 + s1;
+    } else {
+        w = uniform_const(d.wi1_perm)[v];
+        t = uniform_const(d.wi1_tile)[w];
+        e0 = uniform_const(d.wi1_range)[2 * w];
+        e1 = uniform_const(d.wi1_range)[2 * w + 1];
     }
+    pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.trec3),
+                               uniform_const(d.tG),
+                               uniform_const(d.blk_cnt), uniform_const(d.row_idx), t, e0, e1,
+                               d.kcs, w, lane, d.part1, d.part1k);
 }
 
 template <int D, int MODE>
 __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restrict__ descs,
                                                        const int32_t *__restrict__ order,
-                                                       const int64_t *__restrict__ begin, int n,
-                                                       unsigned long long *counter) {
+                                                       const int64_t *__restrict__ begin, int n) {
     const int lane = threadIdx.x & 63;
-    const uint64_t total = (uint64_t)begin[n];
-    for (;;) {
-        const uint64_t g = next_item(counter, lane);
-        if (g >= total) break;
-        const int k = owner(begin, n, g);
-        const BatchDesc &d = descs[order[k]];
-        const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
-        int64_t b, e0, e1, w;
-        if (MODE == MODE_DENSE) {
-            // consecutive items share the point segment (point records)
-            const int64_t sgi = v / d.n_blocks;
-            b = v % d.n_blocks;
-            e0 = sgi * d.seg;
-            e1 = std::min<int64_t>(e0 + d.seg, d.n_tiles);
-            w = b * d.n_seg + sgi;
-        } else {
-            w = uniform_const(d.wi_perm)[v];
-            b = uniform_const(d.wi_block)[w];
-            e0 = uniform_const(d.wi_range)[2 * w];
-            e1 = uniform_const(d.wi_range)[2 * w + 1];
-        }
-        pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH), d.trec, d.tG,
-                                   uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
+    const uint64_t g = (uint64_t)xcd_run_item(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    if (g >= (uint64_t)begin[n]) return;
+    const int k = owner(begin, n, g);
+    const BatchDesc &d = descs[order[k]];
+    const int64_t v = (int64_t)(g - (uint64_t)begin[k]);
+    int64_t b, e0, e1, w;
+    if (MODE == MODE_DENSE) {
+        // consecutive items share the point segment (point records)
+        const int64_t sgi = v / d.n_blocks;
+        b = v % d.n_blocks;
+        e0 = sgi * d.seg;
+        e1 = std::min<int64_t>(e0 + d.seg, d.n_tiles);
+        w = b * d.n_seg + sgi;
+    } else {
+        w = uniform_const(d.wi_perm)[v];
+        b = uniform_const(d.wi_block)[w];
+        e0 = uniform_const(d.wi_range)[2 * w];
+        e1 = uniform_const(d.wi_range)[2 * w + 1];
     }
+    pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH), d.trec, d.tG,
+                               uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
 }
 
 // per target: merge the work-item partials in order, un-permute, norms
@@ -1049,7 +1033,7 @@ static rsot_status ensure_cull_buffers(rsot_problem *p) {
 }
 
 // One evaluation in stages, so that a batch of problems can share host
-// synchronisations and persistent launches:
+// synchronisations and batched launches:
 //   plan_begin  target records, psi statistics, cutoff, culling and counts
 //   plan_lists  (after a sync when culling ran) list and work-item fills
 //   plan_passes objective + gradient passes of this problem alone
@@ -1364,7 +1348,7 @@ extern "C" rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double 
 }
 
 // Batched evaluation: every problem's preparation and culling, one host
-// synchronisation, one persistent launch per pass for the problems that run
+// synchronisation, one launch per pass for the problems that run
 // mixed precision with the dense or tile rule (others run their own passes in
 // the same stream), one final synchronisation. Work goes on ps[0]'s stream.
 extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, const double *eps,
@@ -1393,7 +1377,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
     if (any_cull) RSOT_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < n; ++i) RSOT_TRY(plan_lists(plans[(size_t)i]));
 
-    // problems for the persistent kernels, in decreasing order of work
+    // problems for the batched kernels, in decreasing order of work
     std::vector<BatchDesc> descs;
     std::vector<int> members;
     std::vector<double> cost;
@@ -1441,7 +1425,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
     }
     const int nb = (int)descs.size();
     if (nb > 0) {
-        // group members by (dimension, rule): one persistent launch per group
+        // group members by (dimension, rule): one launch per pass and group
         // and pass; within a group, problems in decreasing order of work
         std::vector<int32_t> order((size_t)nb);
         for (int k = 0; k < nb; ++k) order[(size_t)k] = k;
@@ -1475,8 +1459,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         const size_t s_desc = (sizeof(BatchDesc) * nb + 255) & ~size_t(255);
         const size_t s_ord = (sizeof(int32_t) * nb + 255) & ~size_t(255);
         const size_t s_beg = (sizeof(int64_t) * nbeg + 255) & ~size_t(255);
-        const size_t s_cnt = sizeof(unsigned long long) * 2 * ng;
-        const size_t bytes = s_desc + s_ord + 2 * s_beg + s_cnt + 256;
+        const size_t bytes = s_desc + s_ord + 2 * s_beg + 256;
         size_t cap = p0->batch_cap;
         RSOT_TRY(grow(p0, &p0->batch_buf, &cap, bytes));
         p0->batch_cap = cap;
@@ -1485,7 +1468,6 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         int32_t *d_order = (int32_t *)(base + s_desc);
         int64_t *d_b1 = (int64_t *)(base + s_desc + s_ord);
         int64_t *d_b2 = (int64_t *)(base + s_desc + s_ord + s_beg);
-        unsigned long long *d_cnt = (unsigned long long *)(base + s_desc + s_ord + 2 * s_beg);
         const size_t stage_bytes = s_desc + s_ord + 2 * s_beg;
         std::vector<char> stage(stage_bytes);
         std::memcpy(stage.data(), descs.data(), sizeof(BatchDesc) * nb);
@@ -1494,22 +1476,21 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         std::memcpy(stage.data() + s_desc + s_ord + s_beg, begin2.data(), sizeof(int64_t) * nbeg);
         RSOT_HIP(hipMemcpyAsync(base, stage.data(), stage_bytes, hipMemcpyHostToDevice, st));
         for (int k = 0; k < nb; ++k) (void)hipEventRecord(ps[members[(size_t)k]]->ev_p1, st);
-        const unsigned grid = 256u * 8u;
         for (int gi = 0; gi < ng; ++gi) {
             const int k0 = gstart[(size_t)gi], cnt = gstart[(size_t)gi + 1] - k0;
             const BatchDesc &d0 = descs[(size_t)order[(size_t)k0]];
             const int32_t *o = d_order + k0;
             const int64_t *b1 = d_b1 + goff[(size_t)gi];
-            unsigned long long *c = d_cnt + 2 * gi;
-            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, c);
+            const unsigned grid = xcd_run_grid(begin1[goff[(size_t)gi] + (size_t)cnt]);
+            if (grid == 0) continue;
             if (d0.dim == 3 && d0.mode == MODE_DENSE)
-                hipLaunchKernelGGL((k_pass1_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+                hipLaunchKernelGGL((k_pass1_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt);
             else if (d0.dim == 3)
-                hipLaunchKernelGGL((k_pass1_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+                hipLaunchKernelGGL((k_pass1_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt);
             else if (d0.mode == MODE_DENSE)
-                hipLaunchKernelGGL((k_pass1_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+                hipLaunchKernelGGL((k_pass1_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt);
             else
-                hipLaunchKernelGGL((k_pass1_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt, c);
+                hipLaunchKernelGGL((k_pass1_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b1, cnt);
         }
         for (int k = 0; k < nb; ++k) {
             EvalPlan &e = plans[(size_t)members[(size_t)k]];
@@ -1525,16 +1506,15 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
             const BatchDesc &d0 = descs[(size_t)order[(size_t)k0]];
             const int32_t *o = d_order + k0;
             const int64_t *b2 = d_b2 + goff[(size_t)gi];
-            unsigned long long *c = d_cnt + 2 * gi + 1;
-            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, st, c);
+            const unsigned grid = xcd_run_grid(begin2[goff[(size_t)gi] + (size_t)cnt]);
             if (d0.dim == 3 && d0.mode == MODE_DENSE)
-                hipLaunchKernelGGL((k_pass2_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+                hipLaunchKernelGGL((k_pass2_batched<3, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt);
             else if (d0.dim == 3)
-                hipLaunchKernelGGL((k_pass2_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+                hipLaunchKernelGGL((k_pass2_batched<3, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt);
             else if (d0.mode == MODE_DENSE)
-                hipLaunchKernelGGL((k_pass2_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+                hipLaunchKernelGGL((k_pass2_batched<2, MODE_DENSE>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt);
             else
-                hipLaunchKernelGGL((k_pass2_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt, c);
+                hipLaunchKernelGGL((k_pass2_batched<2, MODE_LIST>), dim3(grid), dim3(256), 0, st, d_desc, o, b2, cnt);
         }
         RSOT_HIP(hipGetLastError());
         // the host staging buffer must outlive the asynchronous copy

@@ -1,4 +1,4 @@
-"""GPU tests of the batched evaluation (one persistent launch per pass)."""
+"""GPU tests of the batched evaluation (one launch per pass)."""
 import sys
 
 import numpy as np
