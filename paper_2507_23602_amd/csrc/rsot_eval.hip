@@ -1439,7 +1439,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
             if (k == 0 || gkey(order[(size_t)k]) != gkey(order[(size_t)k - 1])) gstart.push_back(k);
         gstart.push_back(nb);
         const int ng = (int)gstart.size() - 1;
-        // per group: queue offsets of its problems (count + 1 entries each)
+        // per group: item offsets of its problems (count + 1 entries each)
         std::vector<int64_t> begin1, begin2;
         std::vector<size_t> goff;
         for (int gi = 0; gi < ng; ++gi) {

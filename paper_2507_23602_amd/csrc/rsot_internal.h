@@ -130,7 +130,7 @@ struct rsot_problem {
     int64_t last_refine_pairs = 0;   // (tile, fine block) pairs x 64 x 64 of the last refinement
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // batched call
-    char *batch_buf = nullptr;                      // batched call: descriptors, queues
+    char *batch_buf = nullptr;                      // batched call: descriptors, order, item offsets
     size_t batch_cap = 0;
 };
 
