@@ -205,7 +205,7 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
             inf.eval_ms[l] = si.eval_ms;
             inf.kept_frac[l] = si.kept_frac;
             inf.grad_l1 = si.grad_l1;
-            absJ_prev = std::fabs(si.J);
+            absJ_prev = std::isfinite(si.J) ? std::fabs(si.J) : 0.0;   // 0: next level starts dense
             if (s != RSOT_OK && !(s == RSOT_ERR_NOT_CONVERGED && !last)) status = s;
             eps_prev = eps_l.back();
         }
