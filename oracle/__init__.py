@@ -25,7 +25,8 @@ Functions and the passage each follows:
                        half-plane clipping (no quadrature)
   two_target_mass   -- closed form of int_0^1 sigma((a - b x)/eps) dx
 
-Parity pins for every function are in tests/test_oracle_pins.py.
+Parity pins for every function are in tests/test_oracle_pins.py and
+tests/test_oracle_pins_cutoffs.py (two-sided cutoff windows, D).
 """
 from __future__ import annotations
 
