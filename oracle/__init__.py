@@ -12,6 +12,7 @@ Functions and the passage each follows:
   dual_eval_tile    -- same over tile/block pairs kept by the tile-local bound
                        derived from App. B (rule stated in rsot_oracle.c)
   covering_cost     -- C_0 = max_x min_j c(x, y_j) (Sec. 4.1, App. B)
+  kept_counts       -- |I_q| = #{j : c_qj < C} per point (Sec. 4.1), brute force
   cutoff_geom/int/pw-- Eqs. truncation_cutoff_geom, truncation_cutoff_int,
                        cost_cutoff_delta
   softmax_refine    -- Eq. softmax_refinement_formula (log domain)
@@ -66,6 +67,8 @@ def _load():
         lib.oracle_dual_eval.restype = _I
         lib.oracle_dual_eval.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D, _D, _I,
                                          _P, _P, _P, _P, _P]
+        lib.oracle_kept_counts.restype = _I
+        lib.oracle_kept_counts.argtypes = [_I, _I64, _P, _I64, _P, _D, _D, _D, _I, _P, _P]
         lib.oracle_covering_cost.restype = _D
         lib.oracle_covering_cost.argtypes = [_I, _I64, _P, _I64, _P, _D, _I]
         lib.oracle_cutoff_geom.restype = _D
@@ -152,6 +155,21 @@ def dual_eval_tile(x, mu, y, nu, psi, eps, tile_of, n_tiles, block_of, n_blocks,
     r = EvalResult(J.value, grad, L, kept.value, 0)
     r.keep = keep
     return r
+
+
+def kept_counts(x, y, cutoff, cost_scale=0.5, rel_band=0.0, threads=0):
+    """Per point |I_q| = #{j : c(x_q, y_j) < cutoff} (Sec. 4.1), and the
+    number of targets whose cost is within rel_band * cutoff of the cutoff."""
+    lib = _load()
+    x, y = _c(x), _c(y)
+    kept = np.empty(x.shape[0], dtype=np.int32)
+    near = np.empty(x.shape[0], dtype=np.int32)
+    rc = lib.oracle_kept_counts(x.shape[1], x.shape[0], _ptr(x), y.shape[0], _ptr(y),
+                                float(cost_scale), float(cutoff), float(rel_band), int(threads),
+                                _ptr(kept), _ptr(near))
+    if rc != 0:
+        raise ValueError("oracle_kept_counts: invalid arguments")
+    return kept, near
 
 
 def covering_cost(x, y, cost_scale=0.5, threads=0) -> float:

@@ -183,6 +183,33 @@ double oracle_covering_cost(int d, int64_t nq, const double *x, int64_t n,
     return best;
 }
 
+/*
+ * Kept-set sizes of a cost cutoff (Sec. 4.1): kept_out[q] = |I_q| =
+ * #{ j : c(x_q, y_j) < cutoff }, brute force. near_out (may be NULL) counts
+ * the targets with |c(x_q, y_j) - cutoff| <= rel_band * cutoff: the pairs whose
+ * membership another, equally exact evaluation order of the cost may decide
+ * the other way.
+ */
+int oracle_kept_counts(int d, int64_t nq, const double *x, int64_t n, const double *y,
+                       double cost_scale, double cutoff, double rel_band, int nthreads,
+                       int32_t *kept_out, int32_t *near_out)
+{
+    if (d < 1 || nq < 0 || n < 1 || !kept_out || !(rel_band >= 0.0)) return -1;
+    const int T = oracle_threads(nthreads);
+#pragma omp parallel for num_threads(T) schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        int32_t k = 0, m = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            double c = cost(d, x + q * d, y + j * d, cost_scale);
+            if (c < cutoff) ++k;
+            if (fabs(c - cutoff) <= rel_band * fabs(cutoff)) ++m;
+        }
+        kept_out[q] = k;
+        if (near_out) near_out[q] = m;
+    }
+    return 0;
+}
+
 /* Geometric cutoff (Eq. truncation_cutoff_geom, App. B):
  * C = C_0 + (M - m) + eps ln(eps / (nu_min tau |J|)), and C >= C_0. */
 double oracle_cutoff_geom(double C0, double M, double m, double nu_min,

@@ -55,20 +55,6 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def build_probes() -> str:
-    """Builds the standalone instruction-rate microbenchmark."""
-    os.makedirs(BUILD, exist_ok=True)
-    exe = os.path.join(BUILD, "probe_rates")
-    # matrix-core results straight into vector registers, as a kernel that
-    # consumes them in the vector ALU would be compiled
-    cmd = [HIPCC, *FLAGS, "-mllvm", "-amdgpu-mfma-vgpr-form", "-x", "hip",
-           os.path.join(CSRC, "probe_rates.hip"), "-o", exe]
-    subprocess.run(cmd, check=True, capture_output=True)
-    return exe
-
-
 if __name__ == "__main__":
     build(verbose=True)
-    if "--probes" in sys.argv:
-        print(f"built {build_probes()}")
     sys.exit(0)

@@ -58,13 +58,18 @@ static inline unsigned xcd_run_grid(int64_t n) {
     return (unsigned)(runs_per_xcd * (RSOT_XCD_RUN / 4) * 8);
 }
 
-// Lane 0's value of a 64-bit quantity, in scalar registers. The builtin
-// returns a signed int, so each half is widened through uint32_t: a plain
-// (uint64_t) cast would sign-extend the low half into the high one.
+// A 64-bit value from its two 32-bit halves in the signed-int form a 32-bit
+// register move returns them: each half is widened through uint32_t, because
+// a plain (uint64_t) cast of a low half with bit 31 set would sign-extend
+// into the high one. Host-callable so the widening is tested on the CPU.
+__host__ __device__ constexpr uint64_t join_halves(int lo, int hi) {
+    return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// Lane 0's value of a 64-bit quantity, in scalar registers.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | (uint64_t)lo;
+    return join_halves(__builtin_amdgcn_readfirstlane((int)(uint32_t)v),
+                       __builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)));
 }
 
 // least distance between the intervals [a0,a1] and [b0,b1] along one axis

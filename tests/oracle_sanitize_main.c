@@ -13,6 +13,9 @@ int oracle_dual_eval(int d, int64_t nq, const double *x, const double *mu, int64
                      double *grad_out, double *L_out, int64_t *kept_out, int64_t *nempty_out);
 double oracle_covering_cost(int d, int64_t nq, const double *x, int64_t n, const double *y,
                             double cost_scale, int nthreads);
+int oracle_kept_counts(int d, int64_t nq, const double *x, int64_t n, const double *y,
+                       double cost_scale, double cutoff, double rel_band, int nthreads,
+                       int32_t *kept_out, int32_t *near_out);
 double oracle_cutoff_geom(double C0, double M, double m, double nu_min, double tau,
                           double absJ, double eps);
 double oracle_cutoff_int(double C0, double M, double D, double tau, double absJ, double eps);
@@ -89,6 +92,14 @@ static void run(int d, int64_t nq, int64_t n, double eps) {
     rc = oracle_dual_eval_tile(d, nq, x, mu, n, y, nu, psi, eps, 0.5, tof, nt, bof, nb, 1e-10,
                                fabs(J), 2, &Jtile, g, L, &kept, keep);
     printf("tile rc=%d J=%.15e kept=%ld\n", rc, Jtile, (long)kept);
+    /* kept-set sizes at a cutoff */
+    int32_t *kq = (int32_t *)malloc(sizeof(int32_t) * (size_t)nq);
+    int32_t *nr = (int32_t *)malloc(sizeof(int32_t) * (size_t)nq);
+    rc = oracle_kept_counts(d, nq, x, n, y, 0.5, 0.05, 1e-12, 2, kq, nr);
+    long ks = 0;
+    for (int64_t q = 0; q < nq; ++q) ks += kq[q] + nr[q];
+    printf("counts rc=%d sum=%ld\n", rc, ks);
+    free(kq); free(nr);
     /* softmax refinement onto 7 fine targets */
     double *yf = alloc_fill(7 * d, 0.0, 1.0), *pf = alloc_fill(7, 0, 0);
     oracle_dual_eval(d, nq, x, mu, n, y, nu, psi, eps, 0.5, INFINITY, 1, &J, NULL, L, &kept,

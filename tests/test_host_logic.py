@@ -2,11 +2,14 @@
 schedule of Sec. 4.2 and the stage-to-level lists of the multilevel starts
 (Sec. 5.3, with the reading that runs the schedule on the coarsest level)."""
 import math
+import os
 
 import pytest
 
 from paper_2507_23602_amd import warmstart
 from paper_2507_23602_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.mark.parametrize("eps", [1e-3, 2.5e-3, 1e-2, 0.07, 0.1, 0.3])
@@ -50,3 +53,36 @@ def test_disk_workload_stage_lists():
     assert lv == sorted(lv) and set(lv) == {0, 1, 2, 3}
     assert lv[-1] == 3 and lv[-2] == 3          # final eps first reached on the finest level
     assert all(math.isclose(a, 2 * b) for a, b in zip(sched[:9], sched[1:10]))
+
+
+def test_join_halves_widening(tmp_path):
+    """The 64-bit join used to make descriptor pointers wave-uniform widens
+    each signed 32-bit half through uint32_t: values whose low word has bit 31
+    set (where a sign-extending cast corrupts the high word) come back intact.
+    Compiled host-only with hipcc from the library's own device header."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    src = tmp_path / "join.cpp"
+    src.write_text(r'''
+#include "rsot_device.h"
+#include <cstdio>
+int main() {
+    const uint64_t vals[] = {0x0ull, 0x80000000ull, 0x00007f12c0000010ull,
+                             0xffffffff00000000ull, 0x00000000ffffffffull,
+                             0x7fffffff80000001ull, 0xdeadbeefcafef00dull};
+    int bad = 0;
+    for (uint64_t v : vals) {
+        const uint64_t r = join_halves((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
+        if (r != v) { std::printf("%llx -> %llx\n", (unsigned long long)v,
+                                  (unsigned long long)r); ++bad; }
+    }
+    return bad;
+}
+''')
+    exe = tmp_path / "join"
+    csrc = os.path.join(ROOT, "paper_2507_23602_amd", "csrc")
+    subprocess.run([hipcc, "--offload-host-only", "-x", "hip", "-I", csrc, str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout

@@ -162,3 +162,38 @@ def test_integral_D_drops_empty_points():
     c = 0.5 * ((x - y[0]) ** 2).sum(1)
     ref = np.sum(mu[keep] * np.exp(c[keep] / 0.05))
     assert abs(oracle.integral_D(mu, r.L) - ref) <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_kept_counts_bruteforce_and_totals(d):
+    """|I_q| = #{j : c_qj < C} per point (Sec. 4.1): equal to a brute-force
+    count from scipy's pairwise squared distances, summing to the kept-pair
+    total and the empty-point count of the truncated evaluation, n at C = inf
+    and 0 at C = 0."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(40 + d)
+    x = rng.uniform(0, 1, (53, d))
+    y = rng.uniform(-0.1, 1.1, (29, d))
+    mu = np.full(53, 1 / 53)
+    nu = np.full(29, 1 / 29)
+    psi = 0.01 * rng.standard_normal(29)
+    c = 0.5 * cdist(x, y, "sqeuclidean")
+    for C in [0.004, 0.03, 0.2]:
+        kept, near = oracle.kept_counts(x, y, C)
+        assert np.array_equal(kept, (c < C).sum(1))
+        ev = oracle.dual_eval(x, mu, y, nu, psi, 0.02, cutoff=C)
+        assert int(kept.sum()) == ev.kept
+        assert int((kept == 0).sum()) == ev.nempty
+    assert np.all(oracle.kept_counts(x, y, math.inf)[0] == 29)
+    assert np.all(oracle.kept_counts(x, y, 0.0)[0] == 0)
+
+
+def test_kept_counts_near_band():
+    """A target placed at cost exactly C from the point is outside I_q (the
+    cut is strict) and inside the near-tie band; one slightly inside is kept."""
+    C = 0.125
+    x = np.zeros((1, 2))
+    r = math.sqrt(2 * C)
+    y = np.array([[r, 0.0], [0.0, r * (1 - 1e-9)], [0.9, 0.9]])
+    kept, near = oracle.kept_counts(x, y, C, rel_band=1e-12)
+    assert kept[0] == 1 and near[0] == 1
