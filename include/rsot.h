@@ -50,7 +50,11 @@ typedef enum {
 
 /* Arithmetic of the pair loop.
  * MIXED: exponent arguments formed in FP64, exponentials and per-chunk sums
- *        in FP32, per-point log-sum-exp, per-target sums and J in FP64.
+ *        in FP32, per-point log-sum-exp, per-target sums and J in FP64. The
+ *        FP32 exponential's per-term error (about 1e-7 relative) averages out
+ *        over many points; a problem whose effective number of points
+ *        (sum mu)^2 / sum mu^2 is below opt.fp64_below_points runs the FP64
+ *        pair loop instead, so J stays within 1e-9 of the exact value.
  * FP64 : everything in FP64 (software exp2). */
 typedef enum { RSOT_PREC_MIXED = 0, RSOT_PREC_FP64 = 1 } rsot_precision;
 
@@ -84,6 +88,8 @@ typedef struct {
                                  (dense: whole rows unless the tiles are too few to fill
                                  the device; truncated rules: 256)                     */
     int64_t mem_limit_bytes;  /* cap on library device memory; 0 = none            */
+    int64_t fp64_below_points;/* MIXED: FP64 pair loop when (sum mu)^2 / sum mu^2 is
+                                 below this; default 16384; 0 = never               */
 } rsot_options;
 
 typedef struct rsot_problem rsot_problem;
@@ -103,6 +109,7 @@ typedef struct {
     double pass1_ms;          /* objective pass (per-point log-sum-exp)            */
     double pass2_ms;          /* gradient pass (per-target masses)                 */
     int dense_fallback;       /* 1 if a truncated rule ran dense (no |J| yet)       */
+    int fp64_pairs;           /* 1 if the pair loops ran in FP64                   */
 } rsot_eval_info;
 
 /* Fills *opt with the defaults listed above. */
@@ -212,6 +219,26 @@ rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles);
  * the caller's point order. L_out: DEVICE pointer, n_quad doubles.
  */
 rsot_status rsot_get_lse(rsot_problem *p, double *L_out);
+
+/*
+ * Size of the kept set I_q of every point in the last evaluation: the number
+ * of targets whose terms entered the point's sum (Sec. 4.1: I_q = {j : c_qj <
+ * C} under the cutoff rules; N under DENSE; under TILE the targets of the
+ * blocks kept for the point's tile). A point dropped for an empty set has 0.
+ *   counts_out  DEVICE pointer, n_quad int32 in the caller's point order
+ * Errors: INVALID_ARG (NULL, or no evaluation yet), DEVICE.
+ */
+rsot_status rsot_get_kept_counts(rsot_problem *p, int32_t *counts_out);
+
+/*
+ * Culling decision of the last evaluation for every (point tile, target
+ * block) pair of rsot_get_partition's grouping, row-major by tile:
+ * 0 = skipped, 1 = kept with the per-pair test c < C (cutoff rules),
+ * 2 = every pair kept (DENSE: all 2; TILE: 0 or 2).
+ *   keep_out  DEVICE pointer, n_tiles * n_blocks bytes
+ * Errors: INVALID_ARG (NULL, or no evaluation yet), DEVICE.
+ */
+rsot_status rsot_get_tile_keep(rsot_problem *p, uint8_t *keep_out);
 
 /*
  * Covering cost C_0 = max_q min_j c(x_q, y_j) (Sec. 4.1 / App. B, maximum

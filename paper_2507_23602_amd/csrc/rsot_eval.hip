@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "rsot_device.h"
 #include "rsot_internal.h"
@@ -37,17 +38,28 @@
 #define CH 8   // pairs per chunk between FP64 flushes
 #define RSOT_SEG1_DEFAULT 256   // target blocks per objective-pass work item
 
-// v_exp_f32 is accurate to < 1 ulp (max relative error 8.4e-8 measured on
-// gfx950) but its error has a nonzero mean: -3.40e-9 relative over
-// arguments whose fractional parts are uniformly spread. Per-point sums
-// inherit that mean, and J = eps sum_q mu_q L_q picks it up as
-// eps * 3.4e-9 * sum mu. The FP32 chunk sums are therefore scaled by
-// 1 + 3.40e-9 (an FP64 multiply per chunk), which removes the mean and
-// leaves the zero-mean part, which averages out over points. The GPU tests
-// re-measure the mean on the device.
-#define RSOT_EXP2F_MEAN_CORR (1.0 + 3.40e-9)
+// v_exp_f32 is accurate to about 1 ulp, but its error has a nonzero mean over
+// arguments whose fractional parts are spread evenly (a few 1e-9 relative).
+// Per-point sums inherit that mean, and J = eps sum_q mu_q L_q would pick it up
+// as eps * mean * sum mu. rsot_device_exp_corr measures the mean on the device
+// the library runs on, with the same instruction, and the passes divide it out
+// once per point (objective) or per tile (gradient). Removing the mean needs
+// the dominant arguments' fractional parts spread over the points and tiles;
+// ref_offset spreads the log-sum-exp references, so this holds by
+// construction even on uniform meshes, where the geometry alone would
+// cluster them. What remains is zero-mean and averages out over points.
 
 enum { MODE_DENSE = 0, MODE_LIST = 1, MODE_MASK = 2 };
+
+// Fractional offset in [0, 1) of the reference grid of element i (a point of
+// the objective pass, a tile of the gradient pass): successive elements step
+// by the golden ratio, so the offsets are spread evenly over any run of
+// elements. References are ceil(value - offset) + offset; rescaling a sum
+// between two references of one element is an exact power of two.
+__device__ __forceinline__ double ref_offset(int64_t i) {
+    const double v = (double)(i + 1) * 0.6180339887498949;
+    return v - floor(v);
+}
 
 // constant (read-only) address space: loads at uniform addresses through it
 // may use the scalar cache
@@ -81,6 +93,58 @@ __device__ __forceinline__ double4 trec_at(P T, int k) {
         r.w = T[3 * k + 2];
         return r;
     }
+}
+
+// ---------------------------------------------------------------------------
+// mean error of the FP32 exponential on this device
+// ---------------------------------------------------------------------------
+// Each workgroup sums 2^u (v_exp_f32) / 2^u (FP64) - 1 over the FP32 arguments
+// u_i = FP32(-30 (i + 1/2) / n), whose fractional parts are spread evenly.
+__global__ __launch_bounds__(256) void k_exp2f_error(int64_t n, double *__restrict__ part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const float u = (float)(-30.0 * ((double)i + 0.5) / (double)n);
+        s += (double)__builtin_amdgcn_exp2f(u) / exp2((double)u) - 1.0;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Measured once per device (2^24 arguments, summed in a fixed order) and kept
+// for the life of the process.
+rsot_status rsot_device_exp_corr(hipStream_t st, double *corr) {
+    static std::mutex mu;
+    static double val[64];
+    static bool have[64];
+    int dev = 0;
+    RSOT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return RSOT_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!have[dev]) {
+        const int nwg = 256;
+        const int64_t n = int64_t(1) << 24;
+        double *d = nullptr;
+        if (hipMalloc((void **)&d, sizeof(double) * nwg) != hipSuccess) return RSOT_ERR_OOM;
+        double h[nwg];
+        hipLaunchKernelGGL(k_exp2f_error, dim3(nwg), dim3(256), 0, st, n, d);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(d);
+        if (e != hipSuccess) return RSOT_ERR_DEVICE;
+        double sum = 0.0;
+        for (int i = 0; i < nwg; ++i) sum += h[i];
+        const double mean = sum / (double)n;
+        if (!std::isfinite(mean) || std::fabs(mean) > 1e-6) return RSOT_ERR_DEVICE;
+        val[dev] = 1.0 / (1.0 + mean);
+        have[dev] = true;
+    }
+    *corr = val[dev];
+    return RSOT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +479,7 @@ __global__ void k_item_keys(const int64_t *__restrict__ wi_range, const uint32_t
 // when a chunk's max exceeds it, s is rescaled by an exact power of two.
 template <int D, bool F64, bool MASK, typename RP, typename GP>
 __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, double x2, double A,
-                                          double &m, double &s, double &kept) {
+                                          double rq, double &m, double &s, double &kept) {
     for (int k0 = 0; k0 < 64; k0 += CH) {
         double tv[CH];
         double cm = -INFINITY;
@@ -435,8 +499,8 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
             cm = fmax(cm, v);
         }
         if (cm > m) {
-            const double mn = ceil(cm);
-            s = ldexp(s, (int)fmax(m - mn, -2000.0));
+            const double mn = ceil(cm - rq) + rq;
+            s = ldexp(s, (int)rint(fmax(m - mn, -2000.0)));
             m = mn;
         }
         if (F64) {
@@ -448,7 +512,7 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
             float cs = 0.0f;
 #pragma unroll
             for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
-            s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+            s += (double)cs;
         }
     }
 }
@@ -484,7 +548,7 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
 #pragma unroll
             for (int k = 1; k < CH; ++k) mx = fmaxf(mx, u[k]);
             if (!(mx > 0.0f)) {
-                s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+                s += (double)cs;
                 continue;
             }
             const double dm = ceil((double)mx);
@@ -501,7 +565,7 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
                 cs += __builtin_amdgcn_exp2f((float)v);
             }
         }
-        s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+        s += (double)cs;
     }
 }
 
@@ -520,6 +584,7 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
     const double4 xr = qp[q];
     const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
     const double A = -kcs * (x0 * x0 + x1 * x1 + x2 * x2);
+    const double rq = ref_offset(q);
     double m = -1e300, s = 0.0, kept = 0.0;
     constexpr bool FAST = !F64 && MODE != MODE_MASK;
     if (FAST && e1 > e0) {
@@ -532,7 +597,7 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         double v = x0 * r.x;
         v = fma(x1, r.y, v);
         if (D == 3) v = fma(x2, r.z, v);
-        m = ceil(v + r.w);
+        m = ceil(v + r.w - rq) + rq;
     }
     // the next list entry is read one block ahead, and the block's pair
     // count before its pairs, so neither load waits at a block boundary
@@ -544,11 +609,11 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
         auto block = [&](auto T) {
             if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
-                lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, m, s, kept);
+                lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, rq, m, s, kept);
             } else {
                 const double cnt = (double)blk_cnt[b];
                 if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
-                else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, m, s, kept);
+                else lse_block<D, F64, false>(T, tG, x0, x1, x2, A, rq, m, s, kept);
                 kept += cnt;
             }
         };
@@ -592,15 +657,20 @@ __global__ __launch_bounds__(256) void k_pass1(
 }
 
 // One wavefront per tile: merge the tile's partial log-sum-exps (FP64) into
-// Lt = log2 sum_j 2^(B_j + x.Y_j), then S_q = log2 mu_q - Lt (for the
-// gradient pass), L_q = (Lt + A_q) ln 2, and the tile's objective, ln D,
-// kept-pair and empty-point partials.
+// Lt = log2 sum_j 2^(B_j + x.Y_j) (lcorr = log2 of the exponential's mean
+// correction), L_q = (Lt + A_q) ln 2, and the tile's objective, ln D,
+// kept-pair and empty-point partials. For the gradient pass: the tile's
+// reference R_T = ceil(max_q log2 mu_q - r_T) + r_T (r_T = ref_offset(T)),
+// S_q = log2 mu_q - Lt - R_T, so that the argument log2(mu_q p_qj) - R_T of a
+// dominant term is O(1) however small mu_q is, and tile_ref[T] =
+// {R_T, 2^R_T corr} to scale the tile's sums back.
 __global__ __launch_bounds__(256) void k_pass1_combine(
     double4 *__restrict__ qp, const double *__restrict__ qmu, const double *__restrict__ qlog2mu,
     const int32_t *__restrict__ qperm, const double *__restrict__ part,
     const double *__restrict__ partk, const int64_t *__restrict__ wi_ptr, int64_t n_seg1,
-    int64_t n_tiles, double kcs, int want_H, double *__restrict__ qH, double *__restrict__ qlse,
-    double *__restrict__ tile_part) {
+    int64_t n_tiles, double kcs, int want_H, double lcorr, double corr,
+    double *__restrict__ qH, double *__restrict__ qlse, int32_t *__restrict__ qkept,
+    double2 *__restrict__ tile_ref, double *__restrict__ tile_part) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -619,13 +689,17 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     const double A = -kcs * (xr.x * xr.x + xr.y * xr.y + xr.z * xr.z);
     const bool real = qperm[q] >= 0;
     const bool empty = !(mx > -INFINITY);
-    const double Lt = empty ? -INFINITY : mx + log2(sum);
+    const double Lt = empty ? -INFINITY : mx + log2(sum) + lcorr;
     const double lm = qlog2mu[q];
-    const double S = empty ? -INFINITY : lm - Lt;
+    const double lmax = wave_max(real && !empty ? lm : -INFINITY);
+    const double rT = ref_offset(t);
+    const double RT = lmax > -INFINITY ? ceil(lmax - rT) + rT : 0.0;
+    const double S = empty ? -INFINITY : lm - Lt - RT;
     reinterpret_cast<double *>(qp)[q * 4 + 3] = S;
     if (want_H) qH[q] = S - A;
     const double L2 = Lt + A;
     qlse[q] = empty ? -INFINITY : L2 * RSOT_LN2;
+    qkept[q] = real ? (int32_t)kept : 0;
     const double jp = (real && !empty) ? qmu[q] * L2 : 0.0;
     const double dl = (real && !empty && lm > -INFINITY) ? (lm - L2) * RSOT_LN2 : -INFINITY;
     const double js = wave_sum(jp);
@@ -634,6 +708,7 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     const double ks = wave_sum(real ? kept : 0.0);
     const double es = wave_sum(real && empty ? 1.0 : 0.0);
     if (lane == 0) {
+        tile_ref[t] = make_double2(RT, exp2(RT) * corr);
         tile_part[t * 4 + 0] = js;
         tile_part[t * 4 + 1] = dm > -INFINITY ? dm + log(ds) : -INFINITY;
         tile_part[t * 4 + 2] = ks;
@@ -674,14 +749,14 @@ __device__ __forceinline__ double mass_tile(QP Q, HP H, double Y0, double Y1, do
                 if (MASK) v = v > G + H[i0 + k] ? v : -INFINITY;
                 cs += __builtin_amdgcn_exp2f((float)v);
             }
-            acc += (double)cs * RSOT_EXP2F_MEAN_CORR;
+            acc += (double)cs;
         }
     }
     return acc;
 }
 
-template <int D, bool F64, int MODE, typename QP, typename HP, typename IP>
-__device__ __forceinline__ void pass2_item(QP qp, HP qH, const double4 *__restrict__ trec,
+template <int D, bool F64, int MODE, typename QP, typename HP, typename IP, typename RP>
+__device__ __forceinline__ void pass2_item(QP qp, HP qH, RP tref, const double4 *__restrict__ trec,
                                            const double *__restrict__ tG, IP col_idx, int64_t b,
                                            int64_t e0, int64_t e1, int64_t w, int lane,
                                            double *__restrict__ gpart) {
@@ -696,10 +771,11 @@ __device__ __forceinline__ void pass2_item(QP qp, HP qH, const double4 *__restri
         else if (e + 1 < e1) ent_next = col_idx[e + 1];
         const int64_t t = ent & ~RSOT_PARTIAL_BIT;
         const auto Q = qp + t * 64;
+        const double scale = tref[t].y;
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
-            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G);
+            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G) * scale;
         else
-            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G);
+            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G) * scale;
     }
     gpart[w * 64 + lane] = acc;
 }
@@ -707,8 +783,9 @@ __device__ __forceinline__ void pass2_item(QP qp, HP qH, const double4 *__restri
 template <int D, bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_pass2(
     const double4 *__restrict__ qp, const double *__restrict__ qH,
-    const double4 *__restrict__ trec, const double *__restrict__ tG,
-    const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
+    const double2 *__restrict__ tref, const double4 *__restrict__ trec,
+    const double *__restrict__ tG, const int32_t *__restrict__ wi_block,
+    const int64_t *__restrict__ wi_range,
     const int32_t *__restrict__ perm, const uint32_t *__restrict__ col_idx, int64_t n_tiles,
     int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
@@ -739,7 +816,7 @@ __global__ __launch_bounds__(256) void k_pass2(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    pass2_item<D, F64, MODE>(qp, qH, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
+    pass2_item<D, F64, MODE>(qp, qH, tref, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +828,7 @@ struct BatchDesc {
     int64_t n_tiles, n_blocks;
     const double4 *qp;
     const double *qH;
+    const double2 *tile_ref;
     const double4 *trec;
     const double *trec3;
     const double *tG;
@@ -847,7 +925,8 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
         e0 = uniform_const(d.wi_range)[2 * w];
         e1 = uniform_const(d.wi_range)[2 * w + 1];
     }
-    pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH), d.trec, d.tG,
+    pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH),
+                               uniform_const(d.tile_ref), d.trec, d.tG,
                                uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
 }
 
@@ -978,6 +1057,11 @@ struct Pass1Work {
     int64_t n_items, seg1, n_seg1;
 };
 
+// log2 of the exponential's mean correction, and the correction, for the
+// precision the pair loops run in
+static double pass_lcorr(const rsot_problem *p, bool f64) { return f64 ? 0.0 : std::log2(p->exp_corr); }
+static double pass_corr(const rsot_problem *p, bool f64) { return f64 ? 1.0 : p->exp_corr; }
+
 template <int D, bool F64, int MODE>
 static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
     const unsigned grid = MODE == MODE_DENSE ? (unsigned)((pw.n_items + 3) / 4)
@@ -990,7 +1074,8 @@ static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
     hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
                        p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                        MODE == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
-                       p->n_tiles, kcs, MODE == MODE_MASK ? 1 : 0, p->qH, p->qlse, p->tile_part);
+                       p->n_tiles, kcs, MODE == MODE_MASK ? 1 : 0, pass_lcorr(p, F64),
+                       pass_corr(p, F64), p->qH, p->qlse, p->qkept, p->tile_ref, p->tile_part);
 }
 
 template <int D, bool F64, int MODE>
@@ -1001,7 +1086,7 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
     else
         grid = xcd_run_grid(n_wi);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
-                       p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
+                       p->tile_ref, p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
                        p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
 }
 
@@ -1246,7 +1331,7 @@ static void plan_passes(EvalPlan &e) {
     rsot_problem *p = e.p;
     const hipStream_t keep = p->stream;
     p->stream = e.st;
-    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
+    const bool f64 = rsot_pairs_fp64(p);
     const bool grad = e.grad != nullptr;
     (void)hipEventRecord(p->ev_p1, e.st);
     if (p->dim == 2) {
@@ -1301,6 +1386,7 @@ static rsot_status plan_result(EvalPlan &e, bool timed_passes, double *J_out,
     }
     if (e.dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
     p->last_eval_valid = 1;
+    p->last_mode = e.mode;
     if (info) {
         const int rule = e.rule;
         info->total_pairs = p->nq * p->n;
@@ -1319,6 +1405,7 @@ static rsot_status plan_result(EvalPlan &e, bool timed_passes, double *J_out,
         info->pass1_ms = ms_p1;
         info->pass2_ms = grad ? ms_p2 : 0.0;
         info->dense_fallback = e.dense_fallback;
+        info->fp64_pairs = rsot_pairs_fp64(p) ? 1 : 0;
     }
     return RSOT_OK;
 }
@@ -1384,7 +1471,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
     for (int i = 0; i < n; ++i) {
         EvalPlan &e = plans[(size_t)i];
         rsot_problem *p = e.p;
-        const bool batchable = p->opt.precision == RSOT_PREC_MIXED &&
+        const bool batchable = !rsot_pairs_fp64(p) &&
                                (e.mode == MODE_DENSE || e.mode == MODE_LIST);
         if (!batchable) {
             plan_passes(e);
@@ -1397,6 +1484,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.n_blocks = p->n_blocks;
         d.qp = p->qp;
         d.qH = p->qH;
+        d.tile_ref = p->tile_ref;
         d.trec = p->trec;
         d.trec3 = p->trec3;
         d.tG = p->tG;
@@ -1498,7 +1586,9 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
             hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256),
                                0, st, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                                e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr,
-                               e.pw.n_seg1, p->n_tiles, e.kcs, 0, p->qH, p->qlse, p->tile_part);
+                               e.pw.n_seg1, p->n_tiles, e.kcs, 0, pass_lcorr(p, false),
+                               pass_corr(p, false), p->qH, p->qlse, p->qkept, p->tile_ref,
+                               p->tile_part);
         }
         for (int gi = 0; gi < ng; ++gi) {
             const int k0 = gstart[(size_t)gi], cnt = gstart[(size_t)gi + 1] - k0;
@@ -1543,6 +1633,56 @@ __global__ void k_unpermute_lse(const double *__restrict__ qlse, const int32_t *
     if (i >= nq_pad) return;
     const int32_t d = qperm[i];
     if (d >= 0) out[d] = qlse[i];
+}
+
+__global__ void k_unpermute_i32(const int32_t *__restrict__ v, const int32_t *__restrict__ perm,
+                                int64_t n_pad, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    const int32_t d = perm[i];
+    if (d >= 0) out[d] = v[i];
+}
+
+extern "C" rsot_status rsot_get_kept_counts(rsot_problem *p, int32_t *counts_out) {
+    if (!p || !counts_out || !p->last_eval_valid) return RSOT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_unpermute_i32, dim3((unsigned)((p->nq_pad + 255) / 256)), dim3(256), 0,
+                       p->stream, p->qkept, p->qperm, p->nq_pad, counts_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    return RSOT_OK;
+}
+
+__global__ void k_fill_u8(uint8_t *__restrict__ out, int64_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+// one thread per tile row: its list entries into the (tile, block) matrix
+__global__ void k_scatter_keep(const int64_t *__restrict__ row_ptr,
+                               const uint32_t *__restrict__ row_idx, int64_t n_tiles,
+                               int64_t n_blocks, uint8_t *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    for (int64_t e = row_ptr[t]; e < row_ptr[t + 1]; ++e) {
+        const uint32_t ent = row_idx[e];
+        out[t * n_blocks + (ent & ~RSOT_PARTIAL_BIT)] =
+            (ent & RSOT_PARTIAL_BIT) ? PAIR_PARTIAL : PAIR_FULL;
+    }
+}
+
+extern "C" rsot_status rsot_get_tile_keep(rsot_problem *p, uint8_t *keep_out) {
+    if (!p || !keep_out || !p->last_eval_valid) return RSOT_ERR_INVALID_ARG;
+    const int64_t nf = p->n_tiles * p->n_blocks;
+    const bool dense = p->last_mode == MODE_DENSE;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, p->stream,
+                       keep_out, nf, (uint8_t)(dense ? PAIR_FULL : PAIR_SKIP));
+    if (!dense)
+        hipLaunchKernelGGL(k_scatter_keep, dim3((unsigned)((p->n_tiles + 255) / 256)), dim3(256),
+                           0, p->stream, p->row_ptr, p->row_idx, p->n_tiles, p->n_blocks,
+                           keep_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    return RSOT_OK;
 }
 
 extern "C" rsot_status rsot_get_lse(rsot_problem *p, double *L_out) {
@@ -1680,7 +1820,7 @@ __global__ __launch_bounds__(256) void k_flags_refine(
 // integer that only grows (the objective pass's scheme, transposed)
 template <int D, bool F64>
 __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y0, double Y1,
-                                         double Y2, double B, double &m, double &s) {
+                                         double Y2, double B, double rk, double &m, double &s) {
     for (int i0 = 0; i0 < 64; i0 += CH) {
         double tv[CH];
         double cm = -INFINITY;
@@ -1695,8 +1835,8 @@ __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y
             cm = fmax(cm, v);
         }
         if (cm > m) {
-            const double mn = ceil(cm);
-            s = ldexp(s, (int)fmax(m - mn, -2000.0));
+            const double mn = ceil(cm - rk) + rk;
+            s = ldexp(s, (int)rint(fmax(m - mn, -2000.0)));
             m = mn;
         }
         if (F64) {
@@ -1708,7 +1848,7 @@ __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y
             float cs = 0.0f;
 #pragma unroll
             for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
-            s += (double)cs * RSOT_EXP2F_MEAN_CORR;
+            s += (double)cs;
         }
     }
 }
@@ -1716,19 +1856,22 @@ __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y
 // per work item and lane: log2 of the partial sum (or -inf)
 template <int D, bool F64>
 __global__ __launch_bounds__(256) void k_pass2_lse(
-    const double4 *__restrict__ qp, const double4 *__restrict__ frec,
-    const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
-    const uint32_t *__restrict__ col_idx, int64_t n_wi, double *__restrict__ out) {
+    const double4 *__restrict__ qp, const double2 *__restrict__ tref,
+    const double4 *__restrict__ frec, const int32_t *__restrict__ wi_block,
+    const int64_t *__restrict__ wi_range, const uint32_t *__restrict__ col_idx, int64_t n_wi,
+    double *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int64_t w =
         xcd_group((n_wi + 3) / 4) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= n_wi) return;
     const int64_t F = wi_block[w];
     const double4 rec = frec[F * 64 + lane];
+    const double rk = ref_offset(F * 64 + lane);
     double m = -1e300, s = 0.0;
     for (int64_t e = wi_range[2 * w]; e < wi_range[2 * w + 1]; ++e) {
         const int64_t t = col_idx[e] & ~RSOT_PARTIAL_BIT;
-        lse_tile<D, F64>(qp + t * 64, rec.x, rec.y, rec.z, rec.w, m, s);
+        // the point records carry S_q - R_T; R_T returns through B
+        lse_tile<D, F64>(qp + t * 64, rec.x, rec.y, rec.z, rec.w + tref[t].x, rk, m, s);
     }
     out[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
 }
@@ -1736,7 +1879,7 @@ __global__ __launch_bounds__(256) void k_pass2_lse(
 __global__ __launch_bounds__(256) void k_refine_reduce(const double *__restrict__ part,
                                                        const int64_t *__restrict__ wi_ptr,
                                                        const int32_t *__restrict__ fperm,
-                                                       int64_t n_fblocks, double eps,
+                                                       int64_t n_fblocks, double eps, double lcorr,
                                                        double *__restrict__ psi_out) {
     const int lane = threadIdx.x & 63;
     const int64_t F = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1748,7 +1891,7 @@ __global__ __launch_bounds__(256) void k_refine_reduce(const double *__restrict_
     if (mx > -INFINITY)
         for (int64_t w = w0; w < w1; ++w) s += exp2(part[w * 64 + lane] - mx);
     const int32_t dst = fperm[F * 64 + lane];
-    if (dst >= 0) psi_out[dst] = -eps * RSOT_LN2 * (mx + log2(s));
+    if (dst >= 0) psi_out[dst] = -eps * RSOT_LN2 * (mx + log2(s) + lcorr);
 }
 
 rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse,
@@ -1826,16 +1969,17 @@ rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coar
                        cptr, wptr, nfb, seg, wblk, wrng);
     // 4. log-sum-exp gradient-pass loop and merge
     const dim3 gw(xcd_grid((n_wi + 3) / 4));
-    const bool f64 = p->opt.precision == RSOT_PREC_FP64;
+    const bool f64 = rsot_pairs_fp64(p);
+    const double2 *tref = p->tile_ref;
     if (p->dim == 2) {
-        if (f64) hipLaunchKernelGGL((k_pass2_lse<2, true>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
-        else hipLaunchKernelGGL((k_pass2_lse<2, false>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+        if (f64) hipLaunchKernelGGL((k_pass2_lse<2, true>), gw, dim3(256), 0, p->stream, p->qp, tref, frec, wblk, wrng, cidx, n_wi, part);
+        else hipLaunchKernelGGL((k_pass2_lse<2, false>), gw, dim3(256), 0, p->stream, p->qp, tref, frec, wblk, wrng, cidx, n_wi, part);
     } else {
-        if (f64) hipLaunchKernelGGL((k_pass2_lse<3, true>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
-        else hipLaunchKernelGGL((k_pass2_lse<3, false>), gw, dim3(256), 0, p->stream, p->qp, frec, wblk, wrng, cidx, n_wi, part);
+        if (f64) hipLaunchKernelGGL((k_pass2_lse<3, true>), gw, dim3(256), 0, p->stream, p->qp, tref, frec, wblk, wrng, cidx, n_wi, part);
+        else hipLaunchKernelGGL((k_pass2_lse<3, false>), gw, dim3(256), 0, p->stream, p->qp, tref, frec, wblk, wrng, cidx, n_wi, part);
     }
     hipLaunchKernelGGL(k_refine_reduce, gfb, dim3(256), 0, p->stream, part, wptr, fperm, nfb, eps,
-                       psi_out);
+                       pass_lcorr(p, f64), psi_out);
     RSOT_HIP(hipGetLastError());
     RSOT_HIP(hipStreamSynchronize(p->stream));
     p->last_refine_pairs = ctot * 64 * 64;

@@ -40,6 +40,8 @@ struct rsot_problem {
     hipStream_t stream = nullptr;
     double shift[3] = {0, 0, 0};
     double sum_mu = 0, sum_nu = 0, nu_min = 0, nu_max = 0;
+    double sum_mu2 = 0;          // sum of mu_q^2: (sum mu)^2 / sum_mu2 = effective point count
+    double exp_corr = 1.0;       // 1 / (1 + mean relative error of v_exp_f32), this device
 
     // allocations (for cleanup and the memory cap)
     std::vector<void *> allocs;
@@ -52,6 +54,7 @@ struct rsot_problem {
     double *qlog2mu = nullptr;   // [nq_pad]
     double *qH = nullptr;        // [nq_pad] S_q - A_q (per-pair cutoff test)
     double *qlse = nullptr;      // [nq_pad] L_q (natural log)
+    int32_t *qkept = nullptr;    // [nq_pad] |I_q|: targets summed at the point (last evaluation)
     int32_t *qperm = nullptr;    // [nq_pad] sorted slot -> caller index (-1 pad)
     double *tile_lo = nullptr;   // [n_tiles*3]
     double *tile_hi = nullptr;   // [n_tiles*3]
@@ -75,6 +78,7 @@ struct rsot_problem {
 
     // per-evaluation partials and scalars
     double *tile_part = nullptr; // [n_tiles*4] sum mu L2, logD part, kept, empty
+    double2 *tile_ref = nullptr; // [n_tiles] gradient-pass reference {R_T, 2^R_T * corr}
     double *blk_gpart = nullptr; // [n_blocks*2] |g|_1, |g|_inf per block
     double *dscal = nullptr;     // [32] device scalars
     double *hscal = nullptr;     // [32] pinned host copy
@@ -127,6 +131,7 @@ struct rsot_problem {
     double log_D_prev = 0.0;     // ln D of the previous evaluation (INT rule)
     int have_D = 0;
     int last_eval_valid = 0;
+    int last_mode = 0;           // pair-loop mode of the last evaluation (dense, list, mask)
     int64_t last_refine_pairs = 0;   // (tile, fine block) pairs x 64 x 64 of the last refinement
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // batched call
@@ -157,6 +162,14 @@ rsot_status rsot_morton_order(rsot_problem *p, const double *x, int64_t n, int32
 rsot_status rsot_compute_covering_cost(rsot_problem *p);
 rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi_dev, double *J_out,
                            double *grad_dev, rsot_eval_info *info);
+
+// true when the pair loops run in FP64: FP64 precision, or MIXED precision on a
+// problem whose effective number of points is below opt.fp64_below_points
+bool rsot_pairs_fp64(const rsot_problem *p);
+
+// 1 / (1 + mean relative error of the FP32 exponential instruction) on the
+// current device, measured once per device (rsot_eval.hip)
+rsot_status rsot_device_exp_corr(hipStream_t st, double *corr);
 
 rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse, int64_t nf,
                              const double *yf, double eta, double *psi_out);

@@ -58,7 +58,7 @@ static rsot_status dalloc(rsot_problem *p, T **ptr, size_t count) {
 // non-finite values, number of masses below the allowed minimum.
 struct PointStats {
     double lo[3], hi[3];
-    double wsum, wmin, wmax;
+    double wsum, wmin, wmax, w2sum;
     double nonfinite, badmass;
 };
 
@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
         s.hi[k] = -INFINITY;
     }
     s.wsum = 0;
+    s.w2sum = 0;
     s.wmin = INFINITY;
     s.wmax = -INFINITY;
     s.nonfinite = 0;
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
         }
         if (strict_positive ? !(m > 0.0) : !(m >= 0.0)) s.badmass += 1;
         s.wsum += m;
+        s.w2sum += m * m;
         s.wmin = fmin(s.wmin, m);
         s.wmax = fmax(s.wmax, m);
     }
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
         s.hi[k] = wave_max(s.hi[k]);
     }
     s.wsum = wave_sum(s.wsum);
+    s.w2sum = wave_sum(s.w2sum);
     s.wmin = wave_min(s.wmin);
     s.wmax = wave_max(s.wmax);
     s.nonfinite = wave_sum(s.nonfinite);
@@ -118,6 +121,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
                 r.hi[k] = fmax(r.hi[k], red[i].hi[k]);
             }
             r.wsum += red[i].wsum;
+            r.w2sum += red[i].w2sum;
             r.wmin = fmin(r.wmin, red[i].wmin);
             r.wmax = fmax(r.wmax, red[i].wmax);
             r.nonfinite += red[i].nonfinite;
@@ -138,6 +142,7 @@ __global__ __launch_bounds__(64) void k_point_stats_final(const PointStats *__re
             r.hi[k] = fmax(r.hi[k], part[i].hi[k]);
         }
         r.wsum += part[i].wsum;
+        r.w2sum += part[i].w2sum;
         r.wmin = fmin(r.wmin, part[i].wmin);
         r.wmax = fmax(r.wmax, part[i].wmax);
         r.nonfinite += part[i].nonfinite;
@@ -429,7 +434,9 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     if (sq.nonfinite > 0 || st.nonfinite > 0) return RSOT_ERR_NONFINITE;
     if (sq.badmass > 0 || st.badmass > 0 || !(sq.wsum > 0.0)) return RSOT_ERR_INVALID_ARG;
     p->sum_mu = sq.wsum;
+    p->sum_mu2 = sq.w2sum;
     p->sum_nu = st.wsum;
+    RSOT_TRY(rsot_device_exp_corr(p->stream, &p->exp_corr));
     p->nu_min = st.wmin;
     p->nu_max = st.wmax;
     for (int k = 0; k < 3; ++k) p->shift[k] = k < p->dim ? 0.5 * (st.lo[k] + st.hi[k]) : 0.0;
@@ -447,11 +454,13 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_TRY(dalloc(p, &p->qlog2mu, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qH, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qlse, p->nq_pad));
+    RSOT_TRY(dalloc(p, &p->qkept, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qperm, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->tile_lo, p->n_tiles * 3));
     RSOT_TRY(dalloc(p, &p->tile_hi, p->n_tiles * 3));
     RSOT_TRY(dalloc(p, &p->tile_cnt, p->n_tiles));
     RSOT_TRY(dalloc(p, &p->tile_part, p->n_tiles * 4));
+    RSOT_TRY(dalloc(p, &p->tile_ref, p->n_tiles));
     RSOT_TRY(dalloc(p, &p->ty, p->n_pad * 3));
     RSOT_TRY(dalloc(p, &p->tnu, p->n_pad));
     RSOT_TRY(dalloc(p, &p->tlog2nu, p->n_pad));
@@ -566,6 +575,7 @@ extern "C" void rsot_options_default(rsot_options *opt) {
     opt->truncation = RSOT_TRUNC_DENSE;
     opt->tau = 1e-12;
     opt->delta_thr = 1e-12;
+    opt->fp64_below_points = 16384;
 }
 
 extern "C" const char *rsot_status_string(rsot_status s) {
@@ -589,6 +599,7 @@ static bool options_valid(const rsot_options &o) {
     if (o.truncation < RSOT_TRUNC_DENSE || o.truncation > RSOT_TRUNC_TILE) return false;
     if (!(o.tau > 0.0) || !(o.delta_thr > 0.0)) return false;
     if (o.seg_tiles < 0 || o.seg_blocks < 0 || o.mem_limit_bytes < 0) return false;
+    if (o.fp64_below_points < 0) return false;
     return true;
 }
 
@@ -666,6 +677,12 @@ extern "C" rsot_status rsot_set_precision(rsot_problem *p, int precision) {
     if (precision != RSOT_PREC_MIXED && precision != RSOT_PREC_FP64) return RSOT_ERR_INVALID_ARG;
     p->opt.precision = precision;
     return RSOT_OK;
+}
+
+bool rsot_pairs_fp64(const rsot_problem *p) {
+    if (p->opt.precision == RSOT_PREC_FP64) return true;
+    const double n_eff = p->sum_mu2 > 0.0 ? p->sum_mu * p->sum_mu / p->sum_mu2 : 0.0;
+    return n_eff < (double)p->opt.fp64_below_points;
 }
 
 extern "C" rsot_status rsot_set_reference(rsot_problem *p, double absJ_ref) {

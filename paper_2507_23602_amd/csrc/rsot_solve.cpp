@@ -206,8 +206,7 @@ rsot_status line_search(Evaluator &ev, const std::vector<double> &psi0, double f
     };
     // f noise allowance of the approximate-Wolfe acceptance: the objective of
     // the mixed path carries ~1e-10 relative noise, the FP64 path ~1e-15
-    const double fnoise =
-        (ev.p->opt.precision == RSOT_PREC_FP64 ? 1e-13 : 1e-9) * std::fabs(f0);
+    const double fnoise = (rsot_pairs_fp64(ev.p) ? 1e-13 : 1e-9) * std::fabs(f0);
     auto approx_wolfe = [&](const Point &pt) {
         return pt.f <= f0 + fnoise && pt.d >= c2 * d0 && pt.d <= (2.0 * c1 - 1.0) * d0;
     };

@@ -58,7 +58,7 @@ class Options(ctypes.Structure):
                 ("truncation", ctypes.c_int), ("tau", ctypes.c_double),
                 ("delta_thr", ctypes.c_double), ("inputs_on_device", ctypes.c_int),
                 ("seg_tiles", ctypes.c_int), ("seg_blocks", ctypes.c_int),
-                ("mem_limit_bytes", ctypes.c_int64)]
+                ("mem_limit_bytes", ctypes.c_int64), ("fp64_below_points", ctypes.c_int64)]
 
 
 class EvalInfo(ctypes.Structure):
@@ -68,7 +68,8 @@ class EvalInfo(ctypes.Structure):
                 ("grad_l1", ctypes.c_double), ("grad_linf", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("passes_ms", ctypes.c_double), ("pass1_ms", ctypes.c_double),
-                ("pass2_ms", ctypes.c_double), ("dense_fallback", ctypes.c_int)]
+                ("pass2_ms", ctypes.c_double), ("dense_fallback", ctypes.c_int),
+                ("fp64_pairs", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -170,6 +171,8 @@ SIGNATURES = {
                            ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "rsot_set_tuning": (_I, [_P, _I, _I]),
     "rsot_get_lse": (_I, [_P, _P]),
+    "rsot_get_kept_counts": (_I, [_P, _P]),
+    "rsot_get_tile_keep": (_I, [_P, _P]),
     "rsot_covering_cost": (_I, [_P, ctypes.POINTER(_D)]),
     "rsot_get_partition": (_I, [_P, _P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "rsot_softmax_refine": (_I, [_P, _D, _P, _I64, _P, _P]),
@@ -275,7 +278,7 @@ class Problem:
 
     def __init__(self, x, mu, y, nu, *, cost_scale=0.5, precision="mixed", truncation="dense",
                  tau=1e-12, delta_thr=1e-12, seg_tiles=0, seg_blocks=0, mem_limit_bytes=0,
-                 stream=None):
+                 fp64_below_points=None, stream=None):
         torch = _torch()
         lib = load_library()
         on_dev = isinstance(x, torch.Tensor) and x.is_cuda
@@ -289,10 +292,11 @@ class Problem:
             self._keep = (xs, mus, ys, nus)
         dim = xs.shape[1]
         nq, n = xs.shape[0], ys.shape[0]
+        extra = {} if fp64_below_points is None else {"fp64_below_points": fp64_below_points}
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
                               tau=tau, delta_thr=delta_thr, inputs_on_device=int(on_dev),
                               seg_tiles=seg_tiles, seg_blocks=seg_blocks,
-                              mem_limit_bytes=mem_limit_bytes)
+                              mem_limit_bytes=mem_limit_bytes, **extra)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -366,6 +370,25 @@ class Problem:
         torch = _torch()
         out = torch.empty(self.nq, dtype=torch.float64, device="cuda")
         _check(load_library().rsot_get_lse(self._h, out.data_ptr()), "rsot_get_lse")
+        return out
+
+    def kept_counts(self):
+        """|I_q| of every point in the last evaluation (int32 CUDA tensor)."""
+        torch = _torch()
+        out = torch.empty(self.nq, dtype=torch.int32, device="cuda")
+        _check(load_library().rsot_get_kept_counts(self._h, out.data_ptr()),
+               "rsot_get_kept_counts")
+        return out
+
+    def tile_keep(self):
+        """(tile, block) culling decisions of the last evaluation: uint8 CUDA
+        tensor (n_tiles, n_blocks), 0 skipped, 1 tested per pair, 2 kept."""
+        torch = _torch()
+        nt, nb = _I64(0), _I64(0)
+        _check(load_library().rsot_get_partition(self._h, None, None, ctypes.byref(nt),
+                                                 ctypes.byref(nb)), "rsot_get_partition")
+        out = torch.empty((nt.value, nb.value), dtype=torch.uint8, device="cuda")
+        _check(load_library().rsot_get_tile_keep(self._h, out.data_ptr()), "rsot_get_tile_keep")
         return out
 
     def softmax_refine(self, psi_coarse, eps, y_fine):
