@@ -174,6 +174,23 @@ rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi, doubl
                            double *grad_out, rsot_eval_info *info);
 
 /*
+ * rsot_dual_eval for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, results and errors, for a problem whose rule is DENSE. The
+ * evaluation's work-item partials live in a static device array of 64 MiB per
+ * device (held until the process ends) instead of the problem's own buffers;
+ * the call itself allocates nothing. The partials use rsot_dual_eval's
+ * default segmentation when they fit (results then equal rsot_dual_eval's
+ * bit for bit), else the coarsest segmentation that fits.
+ * Calls that overlap on one device share the array and race: serialise them.
+ * Errors: INVALID_ARG (NULL, eps, or a rule other than DENSE), NONFINITE,
+ * OOM (the partials exceed 64 MiB even at the coarsest segmentation: about
+ * more than 4 million points), DEVICE.
+ */
+rsot_status rsot_dual_eval_noalloc(rsot_problem *p, double eps, const double *psi,
+                                   double *J_out, double *grad_out, rsot_eval_info *info);
+
+/*
  * Evaluates n problems in one call (same quantities as rsot_dual_eval for
  * each): every problem's preparation and culling, one host synchronisation,
  * then one launch per pass over the (problem, work item) pairs of all

@@ -1427,6 +1427,57 @@ rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi, doubl
     return plan_result(e, true, J_out, info);
 }
 
+// Dense evaluation with the work-item partials in caller-provided device
+// memory (scratch, scratch_bytes) instead of the problem's own buffers. The
+// segmentation is the default one when its partials fit; otherwise one
+// objective-pass item per tile and as many gradient-pass point segments as
+// fit (never more than the default). Allocates nothing.
+rsot_status rsot_eval_dense_in(rsot_problem *p, double eps, const double *psi, double *J_out,
+                               double *grad_out, rsot_eval_info *info, double *scratch,
+                               size_t scratch_bytes) {
+    if (p->opt.truncation != RSOT_TRUNC_DENSE) return RSOT_ERR_INVALID_ARG;
+    EvalPlan e;
+    e.p = p;
+    e.st = p->stream;
+    e.eps = eps;
+    e.psi = psi;
+    e.grad = grad_out;
+    RSOT_TRY(plan_begin(e));
+    const bool grad = grad_out != nullptr;
+    const size_t cap = scratch_bytes / sizeof(double);
+    auto need = [&]() {
+        return (size_t)e.pw.n_items * 128 + (grad ? (size_t)e.n_wi * 64 : 0);
+    };
+    if (need() > cap) {
+        e.pw.seg1 = p->n_blocks;
+        e.pw.n_seg1 = 1;
+        e.pw.n_items = p->n_tiles;
+        const size_t used1 = (size_t)p->n_tiles * 128;
+        if (grad) {
+            const size_t left = cap > used1 ? cap - used1 : 0;
+            int64_t n_seg = (int64_t)(left / ((size_t)p->n_blocks * 64));
+            if (n_seg < 1) return RSOT_ERR_OOM;
+            n_seg = std::min(n_seg, e.n_seg);
+            e.seg = (p->n_tiles + n_seg - 1) / n_seg;
+            e.n_seg = (p->n_tiles + e.seg - 1) / e.seg;
+            e.n_wi = p->n_blocks * e.n_seg;
+        }
+        if (need() > cap) return RSOT_ERR_OOM;
+    }
+    double *keep1 = p->part1, *keep1k = p->part1k, *keepg = p->gpart;
+    p->part1 = scratch;
+    p->part1k = scratch + (size_t)e.pw.n_items * 64;
+    p->gpart = scratch + (size_t)e.pw.n_items * 128;
+    plan_passes(e);
+    const rsot_status s = plan_finish(e);
+    p->part1 = keep1;
+    p->part1k = keep1k;
+    p->gpart = keepg;
+    RSOT_TRY(s);
+    RSOT_HIP(hipStreamSynchronize(e.st));
+    return plan_result(e, true, J_out, info);
+}
+
 extern "C" rsot_status rsot_dual_eval(rsot_problem *p, double eps, const double *psi,
                                       double *J_out, double *grad_out, rsot_eval_info *info) {
     if (!p || !psi || !J_out) return RSOT_ERR_INVALID_ARG;

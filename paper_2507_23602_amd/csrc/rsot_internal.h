@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -170,6 +171,12 @@ bool rsot_pairs_fp64(const rsot_problem *p);
 // 1 / (1 + mean relative error of the FP32 exponential instruction) on the
 // current device, measured once per device (rsot_eval.hip)
 rsot_status rsot_device_exp_corr(hipStream_t st, double *corr);
+
+// dense evaluation with the work-item partials in caller-provided device
+// memory; allocates nothing (rsot_eval.hip)
+rsot_status rsot_eval_dense_in(rsot_problem *p, double eps, const double *psi, double *J_out,
+                               double *grad_out, rsot_eval_info *info, double *scratch,
+                               size_t scratch_bytes);
 
 rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse, int64_t nf,
                              const double *yf, double eta, double *psi_out);

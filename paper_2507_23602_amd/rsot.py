@@ -164,6 +164,8 @@ SIGNATURES = {
     "rsot_set_precision": (_I, [_P, _I]),
     "rsot_set_reference": (_I, [_P, _D]),
     "rsot_dual_eval": (_I, [_P, _D, _P, ctypes.POINTER(_D), _P, ctypes.POINTER(EvalInfo)]),
+    "rsot_dual_eval_noalloc": (_I, [_P, _D, _P, ctypes.POINTER(_D), _P,
+                                    ctypes.POINTER(EvalInfo)]),
     "rsot_dual_eval_batched": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_D), ctypes.POINTER(_P),
                                     ctypes.POINTER(_D), ctypes.POINTER(_P),
                                     ctypes.POINTER(EvalInfo), ctypes.POINTER(_D)]),
@@ -349,6 +351,22 @@ class Problem:
         _check(load_library().rsot_dual_eval(self._h, float(eps), psi_t.data_ptr(), ctypes.byref(J),
                                              grad.data_ptr() if grad is not None else None,
                                              ctypes.byref(info)), "rsot_dual_eval")
+        return EvalResult(J.value, grad, info.as_dict())
+
+    def dual_eval_noalloc(self, psi, eps, want_grad=True, out=None) -> EvalResult:
+        """rsot_dual_eval_noalloc: the dense evaluation with no device
+        allocation inside the call (psi and out must already be CUDA tensors)."""
+        torch = _torch()
+        psi_t = _dev_f64(psi, self.n)
+        grad = None
+        if want_grad:
+            grad = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        J = _D(0.0)
+        info = EvalInfo()
+        _check(load_library().rsot_dual_eval_noalloc(
+            self._h, float(eps), psi_t.data_ptr(), ctypes.byref(J),
+            grad.data_ptr() if grad is not None else None, ctypes.byref(info)),
+            "rsot_dual_eval_noalloc")
         return EvalResult(J.value, grad, info.as_dict())
 
     def autotune(self, psi, eps, reps=2):
