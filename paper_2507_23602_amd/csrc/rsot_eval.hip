@@ -260,76 +260,94 @@ __global__ __launch_bounds__(256) void k_pre_scalars(const double *__restrict__ 
 // ---------------------------------------------------------------------------
 // culling: (tile, block) flags, transposition, CSR lists
 // ---------------------------------------------------------------------------
-// Cutoff rules (Alg. 2 with I_q = {j : c < C}): a pair of boxes is skipped
-// when even its least distance reaches C, kept whole when its greatest
-// distance stays below C, and tested pair by pair otherwise.
+// Class of a (point box, target box) pair under a cost cutoff C (Alg. 2 with
+// I_q = {j : c < C}): skipped when even the least distance between the boxes
+// reaches C, kept whole when the greatest stays below C, tested pair by pair
+// otherwise. Every caller passes the point-side box first, so the row and the
+// column culling classify each (tile, block) pair identically.
 template <int D>
-__global__ __launch_bounds__(256) void k_flags_cutoff(
-    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
-    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi, int64_t n_tiles,
-    int64_t n_blocks, double cs, const double *__restrict__ dscal, uint8_t *__restrict__ flags) {
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= n_tiles) return;
-    const double C = dscal[SC_C];
-    double tl[3], th[3];
-    for (int k = 0; k < 3; ++k) {
-        tl[k] = tile_lo[t * 3 + k];
-        th[k] = tile_hi[t * 3 + k];
+__device__ __forceinline__ uint32_t cls_cutoff(const double *pl, const double *ph,
+                                               const double *tl, const double *th, double cs,
+                                               double C) {
+    double dmin2 = 0.0, dmax2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double g = box_gap(pl[k], ph[k], tl[k], th[k]);
+        const double f = box_far(pl[k], ph[k], tl[k], th[k]);
+        dmin2 += g * g;
+        dmax2 += f * f;
     }
-    for (int64_t b = lane; b < n_blocks; b += 64) {
-        double dmin2 = 0.0, dmax2 = 0.0;
-        for (int k = 0; k < D; ++k) {
-            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
-            const double f = box_far(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
-            dmin2 += g * g;
-            dmax2 += f * f;
-        }
-        uint8_t fl = PAIR_PARTIAL;
-        if (cs * dmin2 >= C) fl = PAIR_SKIP;
-        else if (cs * dmax2 < C) fl = PAIR_FULL;
-        flags[t * n_blocks + b] = fl;
-    }
+    if (cs * dmin2 >= C) return PAIR_SKIP;
+    return cs * dmax2 < C ? PAIR_FULL : PAIR_PARTIAL;
 }
 
-// Tile-local rule (derived from App. B). For tile T and block B:
-//   ln U_TB = ln nu(B) + (max_{j in B} psi_j - cs dmin^2(T,B)) / eps   (upper bound)
+// Chunk mask of a (tile, block) pair that needs the per-pair test, for the
+// objective pass: 2 bits per chunk of 8 targets of block b, the class of the
+// chunk's box against tile t's box. (The gradient pass has no such masks: its
+// lanes are the block's targets, and 8-point chunks of a straddling tile
+// almost always straddle the cutoff too, so their classes would save little.)
+template <int D>
+__device__ __forceinline__ uint32_t chunk_mask(int64_t t, int64_t b,
+                                               const double *__restrict__ tile_lo,
+                                               const double *__restrict__ tile_hi,
+                                               const double *__restrict__ tch_lo,
+                                               const double *__restrict__ tch_hi, double cs,
+                                               double C) {
+    uint32_t m = 0;
+    for (int c = 0; c < 8; ++c)
+        m |= cls_cutoff<D>(tile_lo + t * 3, tile_hi + t * 3, tch_lo + (b * 8 + c) * 3,
+                           tch_hi + (b * 8 + c) * 3, cs, C)
+             << (2 * c);
+    return m;
+}
+
+// Tile rule (derived from App. B), per tile T:
+//   ln U_TB = ln nu(B) + (max_{j in B} psi_j - cs dmin^2(T,B)) / eps  (upper bound)
 //   B* = argmax_B ln U_TB (lowest index on ties);
 //   ln L_T = max_{j in B*} ln nu_j + (psi_j - cs dmax^2(T, y_j)) / eps (lower bound of S)
 //   keep (T,B) iff B = B* or ln U_TB > ln L_T + ln(eta / n_blocks),
 //   eta = tau |J_ref| / (eps sum mu): then J_dense - J_trunc <= tau |J_ref|.
 template <int D>
-__global__ __launch_bounds__(256) void k_flags_tile(
+__device__ __forceinline__ double tile_lnU(const double *__restrict__ tile_lo,
+                                           const double *__restrict__ tile_hi,
+                                           const double *__restrict__ blk_lo,
+                                           const double *__restrict__ blk_hi,
+                                           const double *__restrict__ blk_lnnu,
+                                           const double *__restrict__ blk_stat, int64_t t,
+                                           int64_t b, double cs, double eps) {
+    double dmin2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double g = box_gap(tile_lo[t * 3 + k], tile_hi[t * 3 + k], blk_lo[b * 3 + k],
+                                 blk_hi[b * 3 + k]);
+        dmin2 += g * g;
+    }
+    return blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
+}
+
+// one wavefront per tile: B* and the skip threshold ln L_T + ln(eta / n_blocks)
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_ref(
     const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
     const double *__restrict__ blk_lo, const double *__restrict__ blk_hi,
     const double *__restrict__ blk_lnnu, const double *__restrict__ blk_stat,
     const int32_t *__restrict__ blk_cnt, const double *__restrict__ ty,
     const double *__restrict__ tnu, const double *__restrict__ tpsi, int64_t n_tiles,
-    int64_t n_blocks, double cs, double eps, double ln_eta_nb, uint8_t *__restrict__ flags) {
+    int64_t n_blocks, double cs, double eps, double ln_eta_nb, int32_t *__restrict__ bstar,
+    double *__restrict__ thr) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
-    double tl[3], th[3];
-    for (int k = 0; k < 3; ++k) {
-        tl[k] = tile_lo[t * 3 + k];
-        th[k] = tile_hi[t * 3 + k];
-    }
-    const double inv_eps = 1.0 / eps;
     double best = -INFINITY;
     int64_t bi = INT64_MAX;
     for (int64_t b = lane; b < n_blocks; b += 64) {
-        double dmin2 = 0.0;
-        for (int k = 0; k < D; ++k) {
-            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
-            dmin2 += g * g;
-        }
-        const double lnU = blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
+        const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
+                                       cs, eps);
         if (lnU > best) {
             best = lnU;
             bi = b;
         }
     }
-    // wavefront argmax, ties to the lowest block index
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
@@ -339,46 +357,121 @@ __global__ __launch_bounds__(256) void k_flags_tile(
             bi = oi;
         }
     }
-    // reference target: best lower bound among the targets of B*
+    // no finite bound at all (only when psi is not finite: the evaluation
+    // then reports it): keep nothing
+    const bool found = bi != INT64_MAX;
     double lb = -INFINITY;
-    if (lane < blk_cnt[bi]) {
+    if (found && lane < blk_cnt[bi]) {
         const int64_t j = bi * 64 + lane;
         double dmax2 = 0.0;
         for (int k = 0; k < D; ++k) {
-            const double f = box_far_pt(tl[k], th[k], ty[j * 3 + k]);
+            const double f = box_far_pt(tile_lo[t * 3 + k], tile_hi[t * 3 + k], ty[j * 3 + k]);
             dmax2 += f * f;
         }
-        lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) * inv_eps;
+        lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) / eps;
     }
-    const double thr = wave_max(lb) + ln_eta_nb;
-    for (int64_t b = lane; b < n_blocks; b += 64) {
-        double dmin2 = 0.0;
-        for (int k = 0; k < D; ++k) {
-            const double g = box_gap(tl[k], th[k], blk_lo[b * 3 + k], blk_hi[b * 3 + k]);
-            dmin2 += g * g;
-        }
-        const double lnU = blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
-        flags[t * n_blocks + b] = (b == bi || lnU > thr) ? PAIR_FULL : PAIR_SKIP;
+    const double th = wave_max(lb) + ln_eta_nb;
+    if (lane == 0) {
+        bstar[t] = found ? (int32_t)bi : -1;
+        thr[t] = found ? th : INFINITY;
     }
 }
 
-// out[c * R + r] = in[r * Cn + c], 64x64 byte tiles through LDS
-__global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t *__restrict__ in, int64_t R,
-                                                      int64_t Cn, uint8_t *__restrict__ out) {
-    __shared__ uint8_t s[64][65];
-    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
-    for (int i = 0; i < 16; ++i) {
-        const int e = threadIdx.x + i * 256;
-        const int rr = e >> 6, cc = e & 63;
-        const int64_t r = r0 + rr, c = c0 + cc;
-        s[rr][cc] = (r < R && c < Cn) ? in[r * Cn + c] : 0;
+// Culling of the truncated rules straight into CSR lists. Rows are tiles
+// (ROWS) or target blocks; each row is cut into nseg segments of seg_len
+// columns so that short lists of long rows still fill the device, and one
+// wavefront handles one (row, segment), lanes over its columns.
+// FILL = false counts the kept entries of each segment into scnt; FILL = true
+// writes them in increasing order, from the row's start ptr[row] plus the
+// counts of the row's earlier segments: the index (with RSOT_PARTIAL_BIT when
+// the pair needs the per-pair test) and, for such entries, the chunk mask.
+// TILE: the tile rule (kept pairs are whole); otherwise the cost cutoff C of
+// the T1 rules.
+template <int D, bool TILE, bool ROWS, bool FILL>
+__global__ __launch_bounds__(256) void k_cull(
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi,
+    const double *__restrict__ tch_lo, const double *__restrict__ tch_hi,
+    const double *__restrict__ blk_lnnu, const double *__restrict__ blk_stat,
+    const int32_t *__restrict__ bstar, const double *__restrict__ thr, int64_t n_tiles,
+    int64_t n_blocks, int nseg, int64_t seg_len, double cs, double eps,
+    const double *__restrict__ dscal, int32_t *__restrict__ scnt,
+    const int64_t *__restrict__ ptr, uint32_t *__restrict__ idx,
+    uint16_t *__restrict__ cmask) {
+    const int lane = threadIdx.x & 63;
+    const int64_t rs = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nrows = ROWS ? n_tiles : n_blocks, ncols = ROWS ? n_blocks : n_tiles;
+    if (rs >= nrows * nseg) return;
+    const int64_t r = rs / nseg;
+    const int sg = (int)(rs % nseg);
+    const int64_t kb = sg * seg_len, ke = std::min<int64_t>(kb + seg_len, ncols);
+    const double C = TILE ? 0.0 : dscal[SC_C];
+    int c = 0;
+    int64_t base = 0;
+    if (FILL) {
+        base = ptr[r];
+        for (int i = 0; i < sg; ++i) base += scnt[r * nseg + i];
     }
-    __syncthreads();
-    for (int i = 0; i < 16; ++i) {
-        const int e = threadIdx.x + i * 256;
-        const int cc = e >> 6, rr = e & 63;
-        const int64_t r = r0 + rr, c = c0 + cc;
-        if (r < R && c < Cn) out[c * R + r] = s[rr][cc];
+    for (int64_t k0 = kb; k0 < ke; k0 += 64) {
+        const int64_t k = k0 + lane;
+        const int64_t t = ROWS ? r : k, b = ROWS ? k : r;
+        uint32_t cls = PAIR_SKIP;
+        if (k < ke) {
+            if (TILE) {
+                const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
+                                               blk_stat, t, b, cs, eps);
+                cls = (b == bstar[t] || lnU > thr[t]) ? PAIR_FULL : PAIR_SKIP;
+            } else {
+                cls = cls_cutoff<D>(tile_lo + t * 3, tile_hi + t * 3, blk_lo + b * 3,
+                                    blk_hi + b * 3, cs, C);
+            }
+        }
+        if (!FILL) {
+            c += cls != PAIR_SKIP;
+        } else {
+            const uint64_t mask = __ballot(cls != PAIR_SKIP);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            if (cls != PAIR_SKIP) {
+                idx[base + below] = (uint32_t)k | (cls == PAIR_PARTIAL ? RSOT_PARTIAL_BIT : 0u);
+                if (!TILE && ROWS && cls == PAIR_PARTIAL)
+                    cmask[base + below] = (uint16_t)chunk_mask<D>(t, b, tile_lo, tile_hi, tch_lo,
+                                                                  tch_hi, cs, C);
+            }
+            base += __popcll(mask);
+        }
+    }
+    if (!FILL) {
+        c = wave_sum_int(c);
+        if (lane == 0) scnt[rs] = c;
+    }
+}
+
+// entries of each row: the sum of its segments' counts
+__global__ void k_seg_sum(const int32_t *__restrict__ scnt, int64_t nrows, int nseg,
+                          int32_t *__restrict__ cnt) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    int32_t c = 0;
+    for (int i = 0; i < nseg; ++i) c += scnt[r * nseg + i];
+    cnt[r] = c;
+}
+
+// bounding boxes of consecutive groups of 8 elements (coordinates with the
+// given stride), for the chunk masks
+__global__ void k_chunk_boxes(const double *__restrict__ x, int stride, int64_t n_chunks,
+                              double *__restrict__ lo, double *__restrict__ hi) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    for (int k = 0; k < 3; ++k) {
+        double a = INFINITY, b = -INFINITY;
+        for (int i = 0; i < 8; ++i) {
+            const double v = x[(c * 8 + i) * stride + k];
+            a = fmin(a, v);
+            b = fmax(b, v);
+        }
+        lo[c * 3 + k] = a;
+        hi[c * 3 + k] = b;
     }
 }
 
@@ -474,9 +567,22 @@ __global__ void k_item_keys(const int64_t *__restrict__ wi_range, const uint32_t
 // ---------------------------------------------------------------------------
 // objective pass
 // ---------------------------------------------------------------------------
-// Accumulates one 64-target block into the running (m, s) of this lane's point:
-// s = sum 2^(t_j - m) with t_j = B_j + x.Y_j. m is an integer that only grows;
-// when a chunk's max exceeds it, s is rescaled by an exact power of two.
+// The FP64 exponent t = B_j + x.Y_j of a (point, target) pair, always formed
+// in this order, so that the objective pass and the gradient pass take the
+// per-pair cutoff test t > G_j - A_q (c < C) on bitwise equal operands.
+template <int D>
+__device__ __forceinline__ double pair_exp(double x0, double x1, double x2, const double4 &r) {
+    double v = fma(x0, r.x, r.w);
+    v = fma(x1, r.y, v);
+    if (D == 3) v = fma(x2, r.z, v);
+    return v;
+}
+
+// Accumulates one 64-target block into the running (m, s) of this lane's
+// point: s = sum 2^(t_j - m). m is an online maximum on the grid
+// k + rq (k integer); when a chunk's max exceeds it, s is rescaled by an exact
+// power of two. Exact for any first value of m (m = -1e300: no reference yet).
+// MASK: only targets with t_j > G_j - A (c < C) enter, and are counted.
 template <int D, bool F64, bool MASK, typename RP, typename GP>
 __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, double x2, double A,
                                           double rq, double &m, double &s, double &kept) {
@@ -485,11 +591,7 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
         double cm = -INFINITY;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            const double4 r = trec_at<D>(T, k0 + k);
-            double v = x0 * r.x;
-            v = fma(x1, r.y, v);
-            if (D == 3) v = fma(x2, r.z, v);
-            v += r.w;
+            double v = pair_exp<D>(x0, x1, x2, trec_at<D>(T, k0 + k));
             if (MASK) {
                 const bool in = v > G[k0 + k] - A;
                 v = in ? v : -INFINITY;
@@ -517,40 +619,37 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
     }
 }
 
-// Mixed-precision fast path for blocks whose pairs are all kept: the
-// reference m enters the FMA chain's initial value (B_j - m), so each pair
-// costs the FP64 argument, one rounding, one v_exp_f32 and one FP32 add.
-// m starts at ceil(t) of a kept target, so m <= max_j t_j + 1 always. The
-// reference must also stay close to the running maximum: the FP32-rounded
-// argument u = t - m carries an absolute error ~|u| 2^-24, so the largest
-// terms need |u| < 1. A chunk whose FP32 sum exceeds 2 and whose largest u is
-// positive raises m to ceil of that u and is recomputed from the FP64
-// records; without the trigger every u < 1. Spurious triggers (several terms
-// just below the reference) cost the max over the chunk only.
+// Mixed-precision fast path for a chunk of 8 targets whose pairs are all
+// kept: the reference m enters the FMA chain's initial value (B_j - m), so
+// each pair costs the FP64 argument, one rounding, one v_exp_f32 and one FP32
+// add. m starts at ceil(t) of the first target of the item (kept under the
+// dense and tile rules), so there m <= max_j t_j + 1 always. The reference
+// must also stay close to the running maximum: the FP32-rounded argument
+// u = t - m carries an absolute error ~|u| 2^-24, so the largest terms need
+// |u| < 1. A chunk whose FP32 sum exceeds 2 and whose largest u is positive
+// raises m by ceil of that u and is recomputed from the FP64 records; without
+// the trigger every u < 1. Spurious triggers (several terms just below the
+// reference) cost the max over the chunk only.
 template <int D, typename RP>
-__device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, double x2, double &m,
-                                               double &s) {
-    for (int k0 = 0; k0 < 64; k0 += CH) {
-        float u[CH];
-        float cs = 0.0f;
+__device__ __forceinline__ void lse_chunk_fast(RP T, int k0, double x0, double x1, double x2,
+                                               double &m, double &s) {
+    float u[CH];
+    float cs = 0.0f;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const double4 r = trec_at<D>(T, k0 + k);
-            double v = r.w - m;
-            v = fma(x0, r.x, v);
-            v = fma(x1, r.y, v);
-            if (D == 3) v = fma(x2, r.z, v);
-            u[k] = (float)v;
-            cs += __builtin_amdgcn_exp2f(u[k]);
-        }
-        if (!(cs <= 2.0f)) {
-            float mx = u[0];
+    for (int k = 0; k < CH; ++k) {
+        const double4 r = trec_at<D>(T, k0 + k);
+        double v = r.w - m;
+        v = fma(x0, r.x, v);
+        v = fma(x1, r.y, v);
+        if (D == 3) v = fma(x2, r.z, v);
+        u[k] = (float)v;
+        cs += __builtin_amdgcn_exp2f(u[k]);
+    }
+    if (!(cs <= 2.0f)) {
+        float mx = u[0];
 #pragma unroll
-            for (int k = 1; k < CH; ++k) mx = fmaxf(mx, u[k]);
-            if (!(mx > 0.0f)) {
-                s += (double)cs;
-                continue;
-            }
+        for (int k = 1; k < CH; ++k) mx = fmaxf(mx, u[k]);
+        if (mx > 0.0f) {
             const double dm = ceil((double)mx);
             s = ldexp(s, -(int)fmin(dm, 2000.0));
             m += dm;
@@ -565,8 +664,54 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
                 cs += __builtin_amdgcn_exp2f((float)v);
             }
         }
-        s += (double)cs;
     }
+    s += (double)cs;
+}
+
+template <int D, typename RP>
+__device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, double x2, double &m,
+                                               double &s) {
+    for (int k0 = 0; k0 < 64; k0 += CH) lse_chunk_fast<D>(T, k0, x0, x1, x2, m, s);
+}
+
+// The same for a chunk that straddles the cutoff of a T1 rule: each pair
+// takes the test t_j > G_j - A (c < C), failing pairs enter as 2^-inf = 0;
+// kept pairs are counted. The chunk's records and cutoff constants are taken
+// in two halves of 4 targets, so that it holds fewer scalar registers than
+// the fast chunk. On a trigger the kept FP32 arguments are shifted by the
+// integer dm: exact for the terms near the new reference (Sterbenz), and for
+// the others an error of the size their argument's rounding already has.
+template <int D, typename RP, typename GP>
+__device__ __forceinline__ void lse_chunk_mask(RP T, int k0, GP G, double x0, double x1,
+                                               double x2, double A, double &m, double &s,
+                                               double &kept) {
+    float u[CH];
+    float cs = 0.0f;
+    int kc = 0;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const double t = pair_exp<D>(x0, x1, x2, trec_at<D>(T, k0 + k));
+        const bool in = t > G[k0 + k] - A;
+        kc += in;
+        u[k] = in ? (float)(t - m) : -INFINITY;
+        cs += __builtin_amdgcn_exp2f(u[k]);
+    }
+    if (!(cs <= 2.0f)) {
+        float mx = u[0];
+#pragma unroll
+        for (int k = 1; k < CH; ++k) mx = fmaxf(mx, u[k]);
+        if (mx > 0.0f) {
+            const double dm = ceil((double)mx);
+            s = ldexp(s, -(int)fmin(dm, 2000.0));
+            m += dm;
+            cs = 0.0f;
+            const float fdm = (float)dm;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f(u[k] - fdm);
+        }
+    }
+    s += (double)cs;
+    kept += (double)kc;
 }
 
 // Objective pass, one work item = (tile, segment of its block list): per
@@ -574,30 +719,36 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
 // targets, and the number of pairs it summed. Rows of very different length
 // (a tile far from every target keeps many blocks) are split into segments,
 // so no wavefront carries a whole long row.
+// Under the cutoff rules (MODE_MASK), a block kept whole runs the fast path;
+// a block that straddles the cutoff runs its 8-target chunks by their class
+// in the entry's chunk mask: skipped, fast, or tested pair by pair. There the
+// first reference comes from a target that may lie beyond the cutoff; if it
+// then exceeds every kept term by more than 60 (the lane's sum ends below
+// 2^-60), FP32 exponentials of kept terms may have underflowed: the lane is
+// marked in redo[w], and k_pass1_redo sums it again with the exact online
+// maximum.
 template <int D, bool F64, int MODE, typename RP, typename R3, typename GP, typename CP,
-          typename IP>
+          typename IP, typename MP>
 __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP trec, R3 trec3,
-                                           GP tG, CP blk_cnt, IP row_idx, int64_t t, int64_t e0,
-                                           int64_t e1, double kcs, int64_t w, int lane,
-                                           double *__restrict__ part, double *__restrict__ partk) {
+                                           GP tG, CP blk_cnt, IP row_idx, MP row_cm, int64_t t,
+                                           int64_t e0, int64_t e1, double kcs, int64_t w, int lane,
+                                           double *__restrict__ part, double *__restrict__ partk,
+                                           uint64_t *__restrict__ redo) {
     const int64_t q = t * 64 + lane;
     const double4 xr = qp[q];
     const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
     const double A = -kcs * (x0 * x0 + x1 * x1 + x2 * x2);
     const double rq = ref_offset(q);
     double m = -1e300, s = 0.0, kept = 0.0;
-    constexpr bool FAST = !F64 && MODE != MODE_MASK;
+    constexpr bool FAST = !F64;
     if (FAST && e1 > e0) {
-        // reference from the first target of the first block (a kept target)
+        // reference from the first target of the first block
         const uint32_t ent0 = MODE == MODE_DENSE ? (uint32_t)e0 : row_idx[e0];
         const int64_t b0 = (int64_t)(ent0 & ~RSOT_PARTIAL_BIT);
         double4 r;
         if constexpr (D == 3) r = trec_at<D>(trec + b0 * 64, 0);
         else r = trec_at<D>(trec3 + b0 * 192, 0);
-        double v = x0 * r.x;
-        v = fma(x1, r.y, v);
-        if (D == 3) v = fma(x2, r.z, v);
-        m = ceil(v + r.w - rq) + rq;
+        m = ceil(pair_exp<D>(x0, x1, x2, r) - rq) + rq;
     }
     // the next list entry is read one block ahead, and the block's pair
     // count before its pairs, so neither load waits at a block boundary
@@ -609,7 +760,21 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
         auto block = [&](auto T) {
             if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
-                lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, rq, m, s, kept);
+                if (!FAST) {
+                    lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, rq, m, s, kept);
+                } else {
+                    const uint32_t cm = row_cm[e];
+                    const int cnt = blk_cnt[b];
+                    for (int c = 0; c < 8; ++c) {
+                        const uint32_t k = (cm >> (2 * c)) & 3u;
+                        if (k == PAIR_FULL) {
+                            lse_chunk_fast<D>(T, 8 * c, x0, x1, x2, m, s);
+                            kept += (double)std::min(8, std::max(0, cnt - 8 * c));
+                        } else if (k == PAIR_PARTIAL) {
+                            lse_chunk_mask<D>(T, 8 * c, tG + b * 64, x0, x1, x2, A, m, s, kept);
+                        }
+                    }
+                }
             } else {
                 const double cnt = (double)blk_cnt[b];
                 if (FAST) lse_block_fast<D>(T, x0, x1, x2, m, s);
@@ -620,8 +785,78 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         if constexpr (D == 3) block(trec + b * 64);
         else block(trec3 + b * 192);
     }
+    if constexpr (MODE == MODE_MASK && FAST) {
+        const uint64_t lanes = __ballot(kept > 0.0 && !(s >= 0x1p-60));
+        if (lane == 0) redo[w] = lanes;
+    }
     part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
     partk[w * 64 + lane] = kept;
+}
+
+// Objective pass under the cutoff rules (mixed precision): items in the order
+// of their first target block, dealt to the XCDs in runs. Built for eight
+// waves per SIMD: the straddling-chunk path needs more registers than the
+// fast path, and at six or seven waves the pass lost more to exposed load
+// latency than a few spilled values cost.
+template <int D>
+__global__ __launch_bounds__(256) void k_pass1_cut(
+    const double4 *__restrict__ qp, const double4 *__restrict__ trec,
+    const double *__restrict__ trec3, const double *__restrict__ tG,
+    const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
+    const uint16_t *__restrict__ row_cm, const int32_t *__restrict__ wi_tile,
+    const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm, int64_t n_items,
+    double kcs, double *__restrict__ part, double *__restrict__ partk,
+    uint64_t *__restrict__ redo) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = xcd_run_item(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    if (k >= n_items) return;
+    const int64_t w = perm[k];
+    pass1_item<D, false, MODE_MASK>(qp, trec, trec3, tG, blk_cnt, row_idx, row_cm, wi_tile[w],
+                                    wi_range[2 * w], wi_range[2 * w + 1], kcs, w, lane, part,
+                                    partk, redo);
+}
+
+// The marked lanes of objective-pass items under the cutoff rules, summed
+// again with the exact online maximum (lse_block, every straddling pair
+// tested). One wavefront per item; items with no marked lane return at once.
+template <int D>
+__global__ __launch_bounds__(256) void k_pass1_redo(
+    const double4 *__restrict__ qp, const double4 *__restrict__ trec,
+    const double *__restrict__ trec3, const double *__restrict__ tG,
+    const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
+    const int32_t *__restrict__ wi_tile, const int64_t *__restrict__ wi_range, int64_t n_items,
+    double kcs, const uint64_t *__restrict__ redo, double *__restrict__ part,
+    double *__restrict__ partk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_items) return;
+    const uint64_t lanes = redo[w];
+    if (!lanes) return;
+    const int64_t t = wi_tile[w], e0 = wi_range[2 * w], e1 = wi_range[2 * w + 1];
+    const int64_t q = t * 64 + lane;
+    const double4 xr = qp[q];
+    const double x0 = xr.x, x1 = xr.y, x2 = D == 3 ? xr.z : 0.0;
+    const double A = -kcs * (x0 * x0 + x1 * x1 + x2 * x2);
+    const double rq = ref_offset(q);
+    double m = -1e300, s = 0.0, kept = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t ent = row_idx[e];
+        const int64_t b = ent & ~RSOT_PARTIAL_BIT;
+        auto block = [&](auto T) {
+            if (ent & RSOT_PARTIAL_BIT) {
+                lse_block<D, false, true>(T, tG + b * 64, x0, x1, x2, A, rq, m, s, kept);
+            } else {
+                lse_block<D, false, false>(T, tG, x0, x1, x2, A, rq, m, s, kept);
+                kept += (double)blk_cnt[b];
+            }
+        };
+        if constexpr (D == 3) block(trec + b * 64);
+        else block(trec3 + b * 192);
+    }
+    if ((lanes >> lane) & 1) {
+        part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
+        partk[w * 64 + lane] = kept;
+    }
 }
 
 template <int D, bool F64, int MODE>
@@ -629,10 +864,10 @@ __global__ __launch_bounds__(256) void k_pass1(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
     const double *__restrict__ trec3, const double *__restrict__ tG,
     const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
-    const int32_t *__restrict__ wi_tile,
+    const uint16_t *__restrict__ row_cm, const int32_t *__restrict__ wi_tile,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm, int64_t n_items,
     int64_t n_blocks, int64_t seg1, int64_t n_seg1, double kcs, double *__restrict__ part,
-    double *__restrict__ partk) {
+    double *__restrict__ partk, uint64_t *__restrict__ redo) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t w, t, e0, e1;
@@ -652,8 +887,8 @@ __global__ __launch_bounds__(256) void k_pass1(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    pass1_item<D, F64, MODE>(qp, trec, trec3, tG, blk_cnt, row_idx, t, e0, e1, kcs, w, lane, part,
-                             partk);
+    pass1_item<D, F64, MODE>(qp, trec, trec3, tG, blk_cnt, row_idx, row_cm, t, e0, e1, kcs, w,
+                             lane, part, partk, redo);
 }
 
 // One wavefront per tile: merge the tile's partial log-sum-exps (FP64) into
@@ -668,8 +903,8 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     double4 *__restrict__ qp, const double *__restrict__ qmu, const double *__restrict__ qlog2mu,
     const int32_t *__restrict__ qperm, const double *__restrict__ part,
     const double *__restrict__ partk, const int64_t *__restrict__ wi_ptr, int64_t n_seg1,
-    int64_t n_tiles, double kcs, int want_H, double lcorr, double corr,
-    double *__restrict__ qH, double *__restrict__ qlse, int32_t *__restrict__ qkept,
+    int64_t n_tiles, double kcs, int want_A, double lcorr, double corr,
+    double *__restrict__ qA, double *__restrict__ qlse, int32_t *__restrict__ qkept,
     double2 *__restrict__ tile_ref, double *__restrict__ tile_part) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -696,7 +931,7 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     const double RT = lmax > -INFINITY ? ceil(lmax - rT) + rT : 0.0;
     const double S = empty ? -INFINITY : lm - Lt - RT;
     reinterpret_cast<double *>(qp)[q * 4 + 3] = S;
-    if (want_H) qH[q] = S - A;
+    if (want_A) qA[q] = A;
     const double L2 = Lt + A;
     qlse[q] = empty ? -INFINITY : L2 * RSOT_LN2;
     qkept[q] = real ? (int32_t)kept : 0;
@@ -719,44 +954,69 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
 // ---------------------------------------------------------------------------
 // gradient pass
 // ---------------------------------------------------------------------------
-template <int D, bool F64, bool MASK, typename QP, typename HP>
-__device__ __forceinline__ double mass_tile(QP Q, HP H, double Y0, double Y1, double Y2, double B,
-                                            double G) {
-    double acc = 0.0;
-    for (int i0 = 0; i0 < 64; i0 += CH) {
-        if (F64) {
-            double cs = 0.0;
+// Sum over 8 points (a chunk of a tile) of 2^(B + S'_q + x_q.Y) for this
+// lane's target, S'_q = log2 mu_q - Lt_q - R_T carried in the point records.
+// MASK (cutoff rules): only pairs with t > G - A_q enter, t = B + x_q.Y formed
+// as in the objective pass (pair_exp), A_q from qA; both passes then decide
+// every pair's membership on the same FP64 operands.
+template <int D, bool F64, bool MASK, typename QP, typename AP>
+__device__ __forceinline__ double mass_chunk(QP Q, int i0, AP qA, double Y0, double Y1,
+                                             double Y2, double B, double G) {
+    const double4 rec = make_double4(Y0, Y1, Y2, B);
+    if (F64) {
+        double cs = 0.0;
 #pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                const double4 r = ld4(Q + i0 + k);
-                double v = B + r.w;
+        for (int k = 0; k < CH; ++k) {
+            const double4 r = ld4(Q + i0 + k);
+            double v;
+            if (MASK) {
+                const double t = pair_exp<D>(r.x, r.y, r.z, rec);
+                v = t > G - qA[i0 + k] ? t + r.w : -INFINITY;
+            } else {
+                v = B + r.w;
                 v = fma(r.x, Y0, v);
                 v = fma(r.y, Y1, v);
                 if (D == 3) v = fma(r.z, Y2, v);
-                if (MASK) v = v > G + H[i0 + k] ? v : -INFINITY;
-                cs += exp2(v);
             }
-            acc += cs;
-        } else {
-            float cs = 0.0f;
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                const double4 r = ld4(Q + i0 + k);
-                double v = B + r.w;
-                v = fma(r.x, Y0, v);
-                v = fma(r.y, Y1, v);
-                if (D == 3) v = fma(r.z, Y2, v);
-                if (MASK) v = v > G + H[i0 + k] ? v : -INFINITY;
-                cs += __builtin_amdgcn_exp2f((float)v);
-            }
-            acc += (double)cs;
+            cs += exp2(v);
         }
+        return cs;
+    } else {
+        float cs = 0.0f;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const double4 r = ld4(Q + i0 + k);
+            float u;
+            if (MASK) {
+                const double t = pair_exp<D>(r.x, r.y, r.z, rec);
+                u = (float)(t + r.w);
+                u = t > G - qA[i0 + k] ? u : -INFINITY;
+            } else {
+                double v = B + r.w;
+                v = fma(r.x, Y0, v);
+                v = fma(r.y, Y1, v);
+                if (D == 3) v = fma(r.z, Y2, v);
+                u = (float)v;
+            }
+            cs += __builtin_amdgcn_exp2f(u);
+        }
+        return (double)cs;
     }
+}
+
+template <int D, bool F64, typename QP>
+__device__ __forceinline__ double mass_tile(QP Q, double Y0, double Y1, double Y2, double B) {
+    double acc = 0.0;
+    for (int i0 = 0; i0 < 64; i0 += CH)
+        acc += mass_chunk<D, F64, false>(Q, i0, (const double *)nullptr, Y0, Y1, Y2, B, 0.0);
     return acc;
 }
 
-template <int D, bool F64, int MODE, typename QP, typename HP, typename IP, typename RP>
-__device__ __forceinline__ void pass2_item(QP qp, HP qH, RP tref, const double4 *__restrict__ trec,
+// Gradient pass, one work item = (target block, segment of its tile list).
+// Under the cutoff rules a tile that straddles the cutoff runs its 8-point
+// chunks by their class in the entry's chunk mask (FP64: every pair tested).
+template <int D, bool F64, int MODE, typename QP, typename AP, typename IP, typename RP>
+__device__ __forceinline__ void pass2_item(QP qp, AP qA, RP tref, const double4 *__restrict__ trec,
                                            const double *__restrict__ tG, IP col_idx, int64_t b,
                                            int64_t e0, int64_t e1, int64_t w, int lane,
                                            double *__restrict__ gpart) {
@@ -772,21 +1032,25 @@ __device__ __forceinline__ void pass2_item(QP qp, HP qH, RP tref, const double4 
         const int64_t t = ent & ~RSOT_PARTIAL_BIT;
         const auto Q = qp + t * 64;
         const double scale = tref[t].y;
-        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
-            acc += mass_tile<D, F64, true>(Q, qH + t * 64, rec.x, rec.y, rec.z, rec.w, G) * scale;
-        else
-            acc += mass_tile<D, F64, false>(Q, qH, rec.x, rec.y, rec.z, rec.w, G) * scale;
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
+            double a = 0.0;
+            for (int i0 = 0; i0 < 64; i0 += CH)
+                a += mass_chunk<D, F64, true>(Q, i0, qA + t * 64, rec.x, rec.y, rec.z, rec.w, G);
+            acc += a * scale;
+        } else {
+            acc += mass_tile<D, F64>(Q, rec.x, rec.y, rec.z, rec.w) * scale;
+        }
     }
     gpart[w * 64 + lane] = acc;
 }
 
 template <int D, bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_pass2(
-    const double4 *__restrict__ qp, const double *__restrict__ qH,
+    const double4 *__restrict__ qp, const double *__restrict__ qA,
     const double2 *__restrict__ tref, const double4 *__restrict__ trec,
     const double *__restrict__ tG, const int32_t *__restrict__ wi_block,
-    const int64_t *__restrict__ wi_range,
-    const int32_t *__restrict__ perm, const uint32_t *__restrict__ col_idx, int64_t n_tiles,
+    const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
+    const uint32_t *__restrict__ col_idx, int64_t n_tiles,
     int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -816,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_pass2(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    pass2_item<D, F64, MODE>(qp, qH, tref, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
+    pass2_item<D, F64, MODE>(qp, qA, tref, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,7 +1091,7 @@ struct BatchDesc {
     int dim, mode;
     int64_t n_tiles, n_blocks;
     const double4 *qp;
-    const double *qH;
+    const double *qA;
     const double2 *tile_ref;
     const double4 *trec;
     const double *trec3;
@@ -896,9 +1160,9 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
         e1 = uniform_const(d.wi1_range)[2 * w + 1];
     }
     pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.trec3),
-                               uniform_const(d.tG),
-                               uniform_const(d.blk_cnt), uniform_const(d.row_idx), t, e0, e1,
-                               d.kcs, w, lane, d.part1, d.part1k);
+                               uniform_const(d.tG), uniform_const(d.blk_cnt),
+                               uniform_const(d.row_idx), (const uint16_t *)nullptr, t, e0, e1,
+                               d.kcs, w, lane, d.part1, d.part1k, (uint64_t *)nullptr);
 }
 
 template <int D, int MODE>
@@ -925,7 +1189,7 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
         e0 = uniform_const(d.wi_range)[2 * w];
         e1 = uniform_const(d.wi_range)[2 * w + 1];
     }
-    pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qH),
+    pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qA),
                                uniform_const(d.tile_ref), d.trec, d.tG,
                                uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
 }
@@ -1066,16 +1330,26 @@ template <int D, bool F64, int MODE>
 static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
     const unsigned grid = MODE == MODE_DENSE ? (unsigned)((pw.n_items + 3) / 4)
                                              : xcd_run_grid(pw.n_items);
-    hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp,
-                       p->trec, p->trec3, p->tG, p->blk_cnt, p->row_idx, p->wi1_tile,
-                       p->wi1_range,
-                       p->wi1_perm, pw.n_items, p->n_blocks, pw.seg1, pw.n_seg1, kcs, p->part1,
-                       p->part1k);
+    if (MODE == MODE_MASK && !F64)
+        hipLaunchKernelGGL(k_pass1_cut<D>, dim3(grid), dim3(256), 0, p->stream, p->qp, p->trec,
+                           p->trec3, p->tG, p->blk_cnt, p->row_idx, p->row_cm, p->wi1_tile,
+                           p->wi1_range, p->wi1_perm, pw.n_items, kcs, p->part1, p->part1k,
+                           p->redo1);
+    else
+        hipLaunchKernelGGL((k_pass1<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp,
+                           p->trec, p->trec3, p->tG, p->blk_cnt, p->row_idx, p->row_cm,
+                           p->wi1_tile, p->wi1_range, p->wi1_perm, pw.n_items, p->n_blocks,
+                           pw.seg1, pw.n_seg1, kcs, p->part1, p->part1k, p->redo1);
+    if (MODE == MODE_MASK && !F64)
+        hipLaunchKernelGGL(k_pass1_redo<D>, dim3((unsigned)((pw.n_items + 3) / 4)), dim3(256), 0,
+                           p->stream, p->qp, p->trec, p->trec3, p->tG, p->blk_cnt, p->row_idx,
+                           p->wi1_tile, p->wi1_range, pw.n_items, kcs, p->redo1, p->part1,
+                           p->part1k);
     hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
                        p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                        MODE == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
                        p->n_tiles, kcs, MODE == MODE_MASK ? 1 : 0, pass_lcorr(p, F64),
-                       pass_corr(p, F64), p->qH, p->qlse, p->qkept, p->tile_ref, p->tile_part);
+                       pass_corr(p, F64), p->qA, p->qlse, p->qkept, p->tile_ref, p->tile_part);
 }
 
 template <int D, bool F64, int MODE>
@@ -1085,7 +1359,7 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
         grid = (unsigned)(((p->n_blocks + 3) / 4) * ((n_seg + 7) / 8) * 8);
     else
         grid = xcd_run_grid(n_wi);
-    hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qH,
+    hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qA,
                        p->tile_ref, p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
                        p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
 }
@@ -1103,18 +1377,92 @@ static void launch_passes(rsot_problem *p, int mode, bool grad, double kcs, int6
     else launch_pass2<D, F64, MODE_MASK>(p, n_wi, n_seg, seg);
 }
 
-static rsot_status ensure_cull_buffers(rsot_problem *p) {
-    if (p->flags_rm) return RSOT_OK;
-    const size_t nf = (size_t)p->n_tiles * (size_t)p->n_blocks;
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->flags_rm, nf));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->flags_cm, nf));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi1_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_cnt, sizeof(int32_t) * p->n_tiles));
-    RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_cnt, sizeof(int32_t) * p->n_blocks));
+// Segments per row: enough (row, segment) wavefronts to fill the device
+// (16,384), each segment at least 64 columns.
+static void cull_segments(int64_t nrows, int64_t ncols, int *nseg, int64_t *seg_len) {
+    const int64_t want = std::max<int64_t>(1, (16384 + nrows - 1) / nrows);
+    const int64_t most = std::max<int64_t>(1, (ncols + 63) / 64);
+    const int64_t ns = std::min(want, most);
+    int64_t len = (ncols + ns - 1) / ns;
+    len = (len + 63) / 64 * 64;
+    *seg_len = len;
+    *nseg = (int)((ncols + len - 1) / len);
+}
+
+// Buffers of the culling step: list pointers and counts; for the tile rule
+// the per-tile B* and threshold; for the cutoff rules the boxes of 8-target
+// chunks (made once).
+static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStream_t st) {
+    if (!p->row_ptr) {
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi_ptr, sizeof(int64_t) * (p->n_blocks + 1)));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi1_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_cnt, sizeof(int32_t) * p->n_tiles));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_cnt, sizeof(int32_t) * p->n_blocks));
+        int ns = 1;
+        int64_t len = 0;
+        cull_segments(p->n_tiles, p->n_blocks, &ns, &len);
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_scnt, sizeof(int32_t) * p->n_tiles * ns));
+        cull_segments(p->n_blocks, p->n_tiles, &ns, &len);
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_scnt, sizeof(int32_t) * p->n_blocks * ns));
+    }
+    if (tile_rule && !p->tile_bstar) {
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tile_bstar, sizeof(int32_t) * p->n_tiles));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tile_thr, sizeof(double) * p->n_tiles));
+    }
+    if (!tile_rule && !p->tch_lo) {
+        const int64_t ntc = p->n_pad / 8;
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tch_lo, sizeof(double) * 3 * ntc));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tch_hi, sizeof(double) * 3 * ntc));
+        hipLaunchKernelGGL(k_chunk_boxes, dim3((unsigned)((ntc + 255) / 256)), dim3(256), 0, st,
+                           p->ty, 3, ntc, p->tch_lo, p->tch_hi);
+        RSOT_HIP(hipGetLastError());
+    }
     return RSOT_OK;
+}
+
+// culling into the row (tile) or column (target block) lists: count or fill
+static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, bool rows,
+                        bool fill, double eps) {
+    const int64_t nrows = rows ? p->n_tiles : p->n_blocks;
+    int nseg = 1;
+    int64_t seg_len = 0;
+    cull_segments(nrows, rows ? p->n_blocks : p->n_tiles, &nseg, &seg_len);
+    const dim3 g((unsigned)((nrows * nseg + 3) / 4));
+    const double cs = p->opt.cost_scale;
+    int32_t *cnt = rows ? p->row_scnt : p->col_scnt;
+    const int64_t *ptr = rows ? p->row_ptr : p->col_ptr;
+    uint32_t *idx = rows ? p->row_idx : p->col_idx;
+    uint16_t *cm = rows ? p->row_cm : nullptr;
+#define RSOT_CULL(DD, TT, RR, FF)                                                              \
+    hipLaunchKernelGGL((k_cull<DD, TT, RR, FF>), g, dim3(256), 0, st, p->tile_lo, p->tile_hi,    \
+                       p->blk_lo, p->blk_hi, p->tch_lo, p->tch_hi,                               \
+                       p->blk_lnnu, p->blk_stat, p->tile_bstar, p->tile_thr, p->n_tiles,         \
+                       p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, ptr, idx, cm)
+#define RSOT_CULL_F(DD, TT, RR)                                                                \
+    do {                                                                                        \
+        if (fill) RSOT_CULL(DD, TT, RR, true);                                                  \
+        else RSOT_CULL(DD, TT, RR, false);                                                      \
+    } while (0)
+#define RSOT_CULL_R(DD, TT)                                                                    \
+    do {                                                                                        \
+        if (rows) RSOT_CULL_F(DD, TT, true);                                                    \
+        else RSOT_CULL_F(DD, TT, false);                                                        \
+    } while (0)
+    if (D == 2) {
+        if (tile_rule) RSOT_CULL_R(2, true);
+        else RSOT_CULL_R(2, false);
+    } else {
+        if (tile_rule) RSOT_CULL_R(3, true);
+        else RSOT_CULL_R(3, false);
+    }
+#undef RSOT_CULL_R
+#undef RSOT_CULL_F
+#undef RSOT_CULL
+    if (!fill)
+        hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, cnt,
+                           nrows, nseg, rows ? p->row_cnt : p->col_cnt);
 }
 
 // One evaluation in stages, so that a batch of problems can share host
@@ -1200,41 +1548,29 @@ static rsot_status plan_begin(EvalPlan &e) {
         e.n_wi = p->n_blocks * e.n_seg;
         return RSOT_OK;
     }
-    RSOT_TRY(ensure_cull_buffers(p));
+    const bool tile_rule = e.rule == RSOT_TRUNC_TILE;
+    RSOT_TRY(ensure_cull_buffers(p, tile_rule, st));
     e.culled = true;
-    e.mode = e.rule == RSOT_TRUNC_TILE ? MODE_LIST : MODE_MASK;
-    if (e.rule == RSOT_TRUNC_TILE) {
+    e.mode = tile_rule ? MODE_LIST : MODE_MASK;
+    if (tile_rule) {
         const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
                                  std::log((double)p->n_blocks);
         if (D == 2)
-            hipLaunchKernelGGL(k_flags_tile<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+            hipLaunchKernelGGL(k_tile_ref<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
                                p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
-                               p->flags_rm);
+                               p->tile_bstar, p->tile_thr);
         else
-            hipLaunchKernelGGL(k_flags_tile<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+            hipLaunchKernelGGL(k_tile_ref<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
                                p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
-                               p->flags_rm);
+                               p->tile_bstar, p->tile_thr);
     } else {
         hipLaunchKernelGGL(k_target_G, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0, st,
                            p->tpsi, p->tlog2nu, p->tperm, p->n_pad, e.kappa, p->dscal, p->tG);
-        if (D == 2)
-            hipLaunchKernelGGL(k_flags_cutoff<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
-                               p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs, p->dscal,
-                               p->flags_rm);
-        else
-            hipLaunchKernelGGL(k_flags_cutoff<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
-                               p->blk_lo, p->blk_hi, p->n_tiles, p->n_blocks, cs, p->dscal,
-                               p->flags_rm);
     }
-    hipLaunchKernelGGL(k_transpose_u8,
-                       dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
-                       dim3(256), 0, st, p->flags_rm, p->n_tiles, p->n_blocks, p->flags_cm);
-    hipLaunchKernelGGL(k_count_rows, gtile, dim3(256), 0, st, p->flags_rm, p->n_tiles, p->n_blocks,
-                       p->row_cnt);
-    hipLaunchKernelGGL(k_count_rows, gblk, dim3(256), 0, st, p->flags_cm, p->n_blocks, p->n_tiles,
-                       p->col_cnt);
+    launch_cull(p, st, D, tile_rule, true, false, eps);
+    launch_cull(p, st, D, tile_rule, false, false, eps);
     e.seg = seg_cfg > 0 ? seg_cfg : 64;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->row_cnt, p->n_tiles, 0, p->row_ptr,
                        p->dscal + SC_ROWTOT);
@@ -1286,10 +1622,12 @@ static rsot_status plan_lists(EvalPlan &e) {
         const int64_t rtot = (int64_t)p->hscal[SC_ROWTOT];
         const int64_t ctot = (int64_t)p->hscal[SC_COLTOT];
         e.n_wi = (int64_t)p->hscal[SC_NWI];
-        size_t cap_r = p->list_cap, cap_c = p->list_cap;
-        RSOT_TRY(grow(p, &p->row_idx, &cap_r, (size_t)std::max<int64_t>(rtot, 1)));
-        RSOT_TRY(grow(p, &p->col_idx, &cap_c, (size_t)std::max<int64_t>(ctot, 1)));
-        p->list_cap = std::min(cap_r, cap_c);
+        size_t cap_r = p->list_cap, cap_c = p->list_cap, cap_rm = p->list_cap;
+        const size_t want = (size_t)std::max<int64_t>(std::max(rtot, ctot), 1);
+        RSOT_TRY(grow(p, &p->row_idx, &cap_r, want));
+        RSOT_TRY(grow(p, &p->col_idx, &cap_c, want));
+        RSOT_TRY(grow(p, &p->row_cm, &cap_rm, want));
+        p->list_cap = std::min(std::min(cap_r, cap_c), cap_rm);
         size_t cap_b = p->wi_cap, cap_rg = p->wi_cap;
         RSOT_TRY(grow(p, &p->wi_block, &cap_b, (size_t)std::max<int64_t>(e.n_wi, 1)));
         RSOT_TRY(grow(p, &p->wi_range, &cap_rg, (size_t)std::max<int64_t>(2 * e.n_wi, 2)));
@@ -1302,10 +1640,8 @@ static rsot_status plan_lists(EvalPlan &e) {
         p->wi1_cap = std::min(cap_t, cap_tr / 2);
         const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
         const dim3 gtile((unsigned)((p->n_tiles + 3) / 4));
-        hipLaunchKernelGGL(k_fill_rows, gtile, dim3(256), 0, st, p->flags_rm, p->n_tiles,
-                           p->n_blocks, p->row_ptr, p->row_idx);
-        hipLaunchKernelGGL(k_fill_rows, gblk, dim3(256), 0, st, p->flags_cm, p->n_blocks,
-                           p->n_tiles, p->col_ptr, p->col_idx);
+        launch_cull(p, st, p->dim, e.mode == MODE_LIST, true, true, e.eps);
+        launch_cull(p, st, p->dim, e.mode == MODE_LIST, false, true, e.eps);
         hipLaunchKernelGGL(k_fill_work, dim3((unsigned)((p->n_blocks + 255) / 256)), dim3(256), 0,
                            st, p->col_ptr, p->wi_ptr, p->n_blocks, (int)e.seg, p->wi_block,
                            p->wi_range);
@@ -1323,6 +1659,8 @@ static rsot_status plan_lists(EvalPlan &e) {
     RSOT_TRY(grow(p, &p->part1, &c1, (size_t)std::max<int64_t>(e.pw.n_items, 1) * 64));
     RSOT_TRY(grow(p, &p->part1k, &c2, (size_t)std::max<int64_t>(e.pw.n_items, 1) * 64));
     p->part1_cap = std::min(c1, c2);
+    if (e.mode == MODE_MASK)
+        RSOT_TRY(grow(p, &p->redo1, &p->redo1_cap, (size_t)std::max<int64_t>(e.pw.n_items, 1)));
     if (grad) RSOT_TRY(grow(p, &p->gpart, &p->gpart_cap, (size_t)std::max<int64_t>(e.n_wi, 1) * 64));
     return RSOT_OK;
 }
@@ -1534,7 +1872,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.n_tiles = p->n_tiles;
         d.n_blocks = p->n_blocks;
         d.qp = p->qp;
-        d.qH = p->qH;
+        d.qA = p->qA;
         d.tile_ref = p->tile_ref;
         d.trec = p->trec;
         d.trec3 = p->trec3;
@@ -1638,7 +1976,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
                                0, st, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                                e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr,
                                e.pw.n_seg1, p->n_tiles, e.kcs, 0, pass_lcorr(p, false),
-                               pass_corr(p, false), p->qH, p->qlse, p->qkept, p->tile_ref,
+                               pass_corr(p, false), p->qA, p->qlse, p->qkept, p->tile_ref,
                                p->tile_part);
         }
         for (int gi = 0; gi < ng; ++gi) {

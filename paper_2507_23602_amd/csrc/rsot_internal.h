@@ -53,7 +53,7 @@ struct rsot_problem {
     double4 *qp = nullptr;       // [nq_pad] {x0,x1,x2,S}
     double *qmu = nullptr;       // [nq_pad]
     double *qlog2mu = nullptr;   // [nq_pad]
-    double *qH = nullptr;        // [nq_pad] S_q - A_q (per-pair cutoff test)
+    double *qA = nullptr;        // [nq_pad] A_q = -kappa cs |x_q|^2 (per-pair cutoff test)
     double *qlse = nullptr;      // [nq_pad] L_q (natural log)
     int32_t *qkept = nullptr;    // [nq_pad] |I_q|: targets summed at the point (last evaluation)
     int32_t *qperm = nullptr;    // [nq_pad] sorted slot -> caller index (-1 pad)
@@ -113,16 +113,23 @@ struct rsot_problem {
     double *part1 = nullptr;     // [items*64] partial log2-sum-exp
     double *part1k = nullptr;    // [items*64] kept pairs
     size_t part1_cap = 0;
+    uint64_t *redo1 = nullptr;   // [items] cutoff rules: lanes to sum again exactly
+    size_t redo1_cap = 0;
 
-    // culling (truncated rules)
-    uint8_t *flags_rm = nullptr; // [n_tiles*n_blocks]
-    uint8_t *flags_cm = nullptr; // [n_blocks*n_tiles]
+    // culling (truncated rules): CSR lists of kept (tile, block) pairs by tile
+    // (rows) and by block (columns), built directly from box tests
     int64_t *row_ptr = nullptr;  // [n_tiles+1]
     int64_t *col_ptr = nullptr;  // [n_blocks+1]
     int32_t *row_cnt = nullptr;  // [n_tiles]
     int32_t *col_cnt = nullptr;  // [n_blocks]
+    int32_t *row_scnt = nullptr; // kept entries per (tile, segment of its blocks)
+    int32_t *col_scnt = nullptr; // kept entries per (block, segment of its tiles)
     uint32_t *row_idx = nullptr; // kept entries per tile
     uint32_t *col_idx = nullptr; // kept entries per block
+    uint16_t *row_cm = nullptr;  // chunk masks of row entries that need the per-pair test
+    int32_t *tile_bstar = nullptr; // tile rule: B* of each tile
+    double *tile_thr = nullptr;  // tile rule: skip threshold of each tile
+    double *tch_lo = nullptr, *tch_hi = nullptr;   // [n_pad/8*3] boxes of 8-target chunks
     size_t list_cap = 0;
     int64_t *i64tmp = nullptr;   // small scratch for counts
 

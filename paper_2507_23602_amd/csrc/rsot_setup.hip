@@ -452,7 +452,7 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_TRY(dalloc(p, &p->qp, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qmu, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qlog2mu, p->nq_pad));
-    RSOT_TRY(dalloc(p, &p->qH, p->nq_pad));
+    RSOT_TRY(dalloc(p, &p->qA, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qlse, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qkept, p->nq_pad));
     RSOT_TRY(dalloc(p, &p->qperm, p->nq_pad));
