@@ -381,10 +381,13 @@ __global__ __launch_bounds__(256) void k_tile_ref(
 // (ROWS) or target blocks; each row is cut into nseg segments of seg_len
 // columns so that short lists of long rows still fill the device, and one
 // wavefront handles one (row, segment), lanes over its columns.
-// FILL = false counts the kept entries of each segment into scnt; FILL = true
-// writes them in increasing order, from the row's start ptr[row] plus the
-// counts of the row's earlier segments: the index (with RSOT_PARTIAL_BIT when
-// the pair needs the per-pair test) and, for such entries, the chunk mask.
+// FILL = false classifies every pair of the segment, counts the kept entries
+// into scnt and stores the classes as bits, one 64-bit word per 64 columns
+// (kbits: kept, pbits: needs the per-pair test); FILL = true reads the words
+// back and writes the entries in increasing order, from the row's start
+// ptr[row] plus the counts of the row's earlier segments: the index (with
+// RSOT_PARTIAL_BIT when the pair needs the per-pair test) and, for such
+// entries of the rows, the chunk mask.
 // TILE: the tile rule (kept pairs are whole); otherwise the cost cutoff C of
 // the T1 rules.
 template <int D, bool TILE, bool ROWS, bool FILL>
@@ -396,6 +399,7 @@ __global__ __launch_bounds__(256) void k_cull(
     const int32_t *__restrict__ bstar, const double *__restrict__ thr, int64_t n_tiles,
     int64_t n_blocks, int nseg, int64_t seg_len, double cs, double eps,
     const double *__restrict__ dscal, int32_t *__restrict__ scnt,
+    uint64_t *__restrict__ kbits, uint64_t *__restrict__ pbits,
     const int64_t *__restrict__ ptr, uint32_t *__restrict__ idx,
     uint16_t *__restrict__ cmask) {
     const int lane = threadIdx.x & 63;
@@ -412,11 +416,17 @@ __global__ __launch_bounds__(256) void k_cull(
         base = ptr[r];
         for (int i = 0; i < sg; ++i) base += scnt[r * nseg + i];
     }
+    const int64_t nwords = (ncols + 63) / 64;
     for (int64_t k0 = kb; k0 < ke; k0 += 64) {
         const int64_t k = k0 + lane;
         const int64_t t = ROWS ? r : k, b = ROWS ? k : r;
+        const int64_t wi = r * nwords + k0 / 64;
         uint32_t cls = PAIR_SKIP;
-        if (k < ke) {
+        if (FILL) {
+            const uint64_t kw = kbits[wi];
+            const uint64_t pw = TILE ? 0 : pbits[wi];
+            if ((kw >> lane) & 1) cls = ((pw >> lane) & 1) ? PAIR_PARTIAL : PAIR_FULL;
+        } else if (k < ke) {
             if (TILE) {
                 const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
                                                blk_stat, t, b, cs, eps);
@@ -428,6 +438,12 @@ __global__ __launch_bounds__(256) void k_cull(
         }
         if (!FILL) {
             c += cls != PAIR_SKIP;
+            const uint64_t kw = __ballot(cls != PAIR_SKIP);
+            const uint64_t pw = __ballot(cls == PAIR_PARTIAL);
+            if (lane == 0) {
+                kbits[wi] = kw;
+                if (!TILE) pbits[wi] = pw;
+            }
         } else {
             const uint64_t mask = __ballot(cls != PAIR_SKIP);
             const uint32_t below = __builtin_amdgcn_mbcnt_hi(
@@ -1406,6 +1422,16 @@ static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStrea
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_scnt, sizeof(int32_t) * p->n_tiles * ns));
         cull_segments(p->n_blocks, p->n_tiles, &ns, &len);
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_scnt, sizeof(int32_t) * p->n_blocks * ns));
+        const size_t rw = (size_t)p->n_tiles * (size_t)((p->n_blocks + 63) / 64);
+        const size_t cw = (size_t)p->n_blocks * (size_t)((p->n_tiles + 63) / 64);
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_kbits, sizeof(uint64_t) * rw));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_kbits, sizeof(uint64_t) * cw));
+    }
+    if (!tile_rule && !p->row_pbits) {
+        const size_t rw = (size_t)p->n_tiles * (size_t)((p->n_blocks + 63) / 64);
+        const size_t cw = (size_t)p->n_blocks * (size_t)((p->n_tiles + 63) / 64);
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_pbits, sizeof(uint64_t) * rw));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_pbits, sizeof(uint64_t) * cw));
     }
     if (tile_rule && !p->tile_bstar) {
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tile_bstar, sizeof(int32_t) * p->n_tiles));
@@ -1435,11 +1461,13 @@ static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, 
     const int64_t *ptr = rows ? p->row_ptr : p->col_ptr;
     uint32_t *idx = rows ? p->row_idx : p->col_idx;
     uint16_t *cm = rows ? p->row_cm : nullptr;
+    uint64_t *kb = rows ? p->row_kbits : p->col_kbits;
+    uint64_t *pb = rows ? p->row_pbits : p->col_pbits;
 #define RSOT_CULL(DD, TT, RR, FF)                                                              \
     hipLaunchKernelGGL((k_cull<DD, TT, RR, FF>), g, dim3(256), 0, st, p->tile_lo, p->tile_hi,    \
                        p->blk_lo, p->blk_hi, p->tch_lo, p->tch_hi,                               \
                        p->blk_lnnu, p->blk_stat, p->tile_bstar, p->tile_thr, p->n_tiles,         \
-                       p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, ptr, idx, cm)
+                       p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, kb, pb, ptr, idx, cm)
 #define RSOT_CULL_F(DD, TT, RR)                                                                \
     do {                                                                                        \
         if (fill) RSOT_CULL(DD, TT, RR, true);                                                  \

@@ -124,6 +124,11 @@ struct rsot_problem {
     int32_t *col_cnt = nullptr;  // [n_blocks]
     int32_t *row_scnt = nullptr; // kept entries per (tile, segment of its blocks)
     int32_t *col_scnt = nullptr; // kept entries per (block, segment of its tiles)
+    // culling classes of the count pass, read back by the fill pass: one bit
+    // per (tile, block) pair, row-major by tile (row_*) and by block (col_*);
+    // kbits = kept, pbits = needs the per-pair test
+    uint64_t *row_kbits = nullptr, *row_pbits = nullptr;
+    uint64_t *col_kbits = nullptr, *col_pbits = nullptr;
     uint32_t *row_idx = nullptr; // kept entries per tile
     uint32_t *col_idx = nullptr; // kept entries per block
     uint16_t *row_cm = nullptr;  // chunk masks of row entries that need the per-pair test
