@@ -17,7 +17,8 @@ Functions and the passage each follows:
                        cost_cutoff_delta
   softmax_refine    -- Eq. softmax_refinement_formula (log domain)
   lbfgs_solve       -- Alg. 1 with a textbook L-BFGS (Sec. 3.4; memory 10,
-                       Armijo backtracking), stop on ||grad||_1 (Remark 3.2)
+                       strong-Wolfe or Armijo line search), stop on
+                       ||grad||_1 (Remark 3.2)
   sinkhorn_psi      -- log-domain Sinkhorn on the discrete problem of
                        Remark 3.1 (independent route to psi*)
   power_cell_masses -- eps -> 0 limit (Remark 2.1): mass of each Laguerre
@@ -217,10 +218,88 @@ def softmax_refine(x, mu, L_coarse, y_fine, eps, cost_scale=0.5, threads=0):
 # ---------------------------------------------------------------------------
 # solver side: L-BFGS (Alg. 1) and an independent Sinkhorn route to psi*
 # ---------------------------------------------------------------------------
-def lbfgs_solve(fun, psi0, tol=1e-6, max_iter=5000, m=10, c1=1e-4):
-    """Minimise J with textbook L-BFGS (two-loop recursion, H0 = s'y/y'y,
-    Armijo backtracking), stopping when ||grad||_1 <= tol (Remark 3.2).
+def _cubic_min(a, fa, da, b, fb, db):
+    """Minimiser of the cubic interpolating f and f' at a and b, kept in the
+    middle 80 % of [min(a, b), max(a, b)] (bisection if the cubic has none)."""
+    lo, hi = min(a, b), max(a, b)
+    d1 = da + db - 3.0 * (fa - fb) / (a - b)
+    disc = d1 * d1 - da * db
+    x = 0.5 * (a + b)
+    if disc >= 0.0 and np.isfinite(disc):
+        d2 = math.copysign(math.sqrt(disc), b - a)
+        den = db - da + 2.0 * d2
+        if den != 0.0:
+            x = b - (b - a) * (db + d2 - d1) / den
+    if not np.isfinite(x):
+        x = 0.5 * (a + b)
+    w = hi - lo
+    return min(max(x, lo + 0.1 * w), hi - 0.1 * w)
 
+
+def _wolfe_search(fun, psi, J, g, p, alpha1, c1, c2, max_ls, fnoise):
+    """Strong-Wolfe line search (Nocedal & Wright, Algs. 3.5 and 3.6):
+    bracket by doubling, then zoom by safeguarded cubic interpolation. Near
+    the minimiser, where differences of J sink into its rounding noise, a
+    point that meets Hager and Zhang's approximate Wolfe conditions
+    (f <= J + fnoise, c2 d0 <= d <= (2 c1 - 1) d0) is accepted as well.
+    Returns (alpha, J, g, evaluations), alpha = 0 when no step was found."""
+    d0 = float(g.dot(p))
+    ev = 0
+
+    def approx(f, d):
+        return f <= J + fnoise and c2 * d0 <= d <= (2.0 * c1 - 1.0) * d0
+
+    a_prev, f_prev, d_prev = 0.0, J, d0
+    a = alpha1
+    lo = hi = None
+    for i in range(max_ls):
+        f, gn = fun(psi + a * p)
+        ev += 1
+        d = float(gn.dot(p))
+        if f > J + c1 * a * d0 or (i > 0 and f >= f_prev):
+            if approx(f, d):
+                return a, f, gn, ev
+            lo, hi = (a_prev, f_prev, d_prev), (a, f, d)
+            break
+        if abs(d) <= -c2 * d0:
+            return a, f, gn, ev
+        if d >= 0.0:
+            lo, hi = (a, f, d), (a_prev, f_prev, d_prev)
+            break
+        a_prev, f_prev, d_prev, g_prev = a, f, d, gn
+        a *= 2.0
+    else:
+        return (a_prev, f_prev, g_prev, ev) if a_prev > 0.0 else (0.0, J, g, ev)
+    best = None
+    while ev < max_ls:
+        a = _cubic_min(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2])
+        f, gn = fun(psi + a * p)
+        ev += 1
+        d = float(gn.dot(p))
+        if f > J + c1 * a * d0 or f >= lo[1]:
+            if approx(f, d):
+                return a, f, gn, ev
+            hi = (a, f, d)
+        else:
+            if abs(d) <= -c2 * d0:
+                return a, f, gn, ev
+            if d * (hi[0] - lo[0]) >= 0.0:
+                hi = lo
+            lo = (a, f, d)
+            best = (a, f, gn)
+    if best is not None and best[1] < J:
+        return best[0], best[1], best[2], ev
+    return 0.0, J, g, ev
+
+
+def lbfgs_solve(fun, psi0, tol=1e-6, max_iter=5000, m=10, c1=1e-4, c2=0.9, max_ls=20,
+                h0=1.0, line_search="wolfe"):
+    """Minimise J with textbook L-BFGS (two-loop recursion, H0 = s'y/y'y, and
+    h0 I before the first pair), stopping when ||grad||_1 <= tol (Remark 3.2;
+    Alg. 1 leaves the quasi-Newton details open).
+
+    line_search: "wolfe" (strong Wolfe conditions, c1, c2, at most max_ls
+    evaluations per search) or "armijo" (backtracking by halves).
     ``fun(psi) -> (J, grad)``. Returns (psi, J, grad, iterations, evaluations).
     """
     psi = np.array(psi0, dtype=np.float64)
@@ -236,8 +315,7 @@ def lbfgs_solve(fun, psi0, tol=1e-6, max_iter=5000, m=10, c1=1e-4):
             a = rho * s.dot(q)
             alphas.append((rho, a))
             q -= a * yv
-        if S:
-            q *= S[-1].dot(Y[-1]) / Y[-1].dot(Y[-1])
+        q *= S[-1].dot(Y[-1]) / Y[-1].dot(Y[-1]) if S else h0
         for (s, yv), (rho, a) in zip(zip(S, Y), reversed(alphas)):
             b = rho * yv.dot(q)
             q += (a - b) * s
@@ -245,16 +323,27 @@ def lbfgs_solve(fun, psi0, tol=1e-6, max_iter=5000, m=10, c1=1e-4):
         slope = g.dot(p)
         if slope >= 0:                      # not a descent direction: reset
             S, Y = [], []
-            p = -g
+            p = -h0 * g
             slope = g.dot(p)
-        t = 1.0
-        while True:
-            psi_new = psi + t * p
-            J_new, g_new = fun(psi_new)
-            nev += 1
-            if J_new <= J + c1 * t * slope or t < 1e-20:
+        if line_search == "wolfe":
+            t, J_new, g_new, ne = _wolfe_search(fun, psi, J, g, p, 1.0, c1, c2, max_ls,
+                                                1e-13 * abs(J))
+            nev += ne
+            if t == 0.0:
+                if S:                       # restart from the scaled gradient once
+                    S, Y = [], []
+                    continue
                 break
-            t *= 0.5
+            psi_new = psi + t * p
+        else:
+            t = 1.0
+            while True:
+                psi_new = psi + t * p
+                J_new, g_new = fun(psi_new)
+                nev += 1
+                if J_new <= J + c1 * t * slope or t < 1e-20:
+                    break
+                t *= 0.5
         s = psi_new - psi
         yv = g_new - g
         if s.dot(yv) > 1e-300:

@@ -200,12 +200,39 @@ def test_lbfgs_matches_sinkhorn():
         r = oracle.dual_eval(x, mu, y, nu, p, eps)
         return r.J, r.grad
 
-    psi, J, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(16), tol=1e-11)
-    assert np.abs(g).sum() <= 1e-11
     ps = oracle.sinkhorn_psi(x, mu, y, nu, eps)
-    c1 = psi - np.dot(nu, psi)
     c2 = ps - np.dot(nu, ps)
-    np.testing.assert_allclose(c1, c2, rtol=0, atol=1e-9)
+    # both line searches reach the Sinkhorn potential (up to the constant)
+    for ls in ("wolfe", "armijo"):
+        psi, J, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(16), tol=1e-11, line_search=ls)
+        assert np.abs(g).sum() <= 1e-11, ls
+        c1 = psi - np.dot(nu, psi)
+        np.testing.assert_allclose(c1, c2, rtol=0, atol=1e-9)
+
+
+def test_wolfe_search_accepts_only_wolfe_points():
+    """Every step the strong-Wolfe search accepts away from the noise floor
+    meets both conditions: sufficient decrease and |phi'(a)| <= c2 |phi'(0)|."""
+    x, mu = W.quadrature(W.square_mesh(6))
+    rng = np.random.default_rng(8)
+    y = rng.uniform(0, 1, size=(9, 2))
+    nu = np.full(9, 1 / 9)
+    eps = 0.03
+
+    def fun(p):
+        r = oracle.dual_eval(x, mu, y, nu, p, eps)
+        return r.J, r.grad
+
+    psi = 0.05 * rng.standard_normal(9)
+    J, g = fun(psi)
+    for _ in range(6):
+        p = -g / np.abs(g).max() * 0.1
+        a, Jn, gn, ev = oracle._wolfe_search(fun, psi, J, g, p, 1.0, 1e-4, 0.9, 20, 0.0)
+        assert a > 0.0
+        d0 = g.dot(p)
+        assert Jn <= J + 1e-4 * a * d0
+        assert abs(gn.dot(p)) <= 0.9 * abs(d0)
+        psi, J, g = psi + a * p, Jn, gn
 
 
 # -- truncation: sign and bound (App. B) ----------------------------------------------
