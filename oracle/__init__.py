@@ -16,6 +16,9 @@ Functions and the passage each follows:
   cutoff_geom/int/pw-- Eqs. truncation_cutoff_geom, truncation_cutoff_int,
                        cost_cutoff_delta
   softmax_refine    -- Eq. softmax_refinement_formula (log domain)
+  plan_moments      -- nu~_j and sum_q mu_q p_qj x_q (Sec. 6.2, Eq. barycenter_fixed_point)
+  transport_maps    -- barycentric and modal maps (Sec. 6.3, Eqs.
+                       barycentric_map_registration / modal_map_registration)
   lbfgs_solve       -- Alg. 1 with a textbook L-BFGS (Sec. 3.4; memory 10,
                        strong-Wolfe or Armijo line search), stop on
                        ||grad||_1 (Remark 3.2)
@@ -82,6 +85,12 @@ def _load():
         lib.oracle_integral_D.argtypes = [_I64, _P, _P]
         lib.oracle_softmax_refine.restype = _I
         lib.oracle_softmax_refine.argtypes = [_I, _I64, _P, _P, _P, _I64, _P, _D, _D, _I, _P]
+        lib.oracle_plan_moments.restype = _I
+        lib.oracle_plan_moments.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D, _P, _P,
+                                            _I64, _P, _I, _P, _P]
+        lib.oracle_transport_maps.restype = _I
+        lib.oracle_transport_maps.argtypes = [_I, _I64, _P, _I64, _P, _P, _P, _D, _D, _P, _P,
+                                              _I64, _P, _I, _P, _P, _P]
         lib.oracle_dual_eval_tile.restype = _I
         lib.oracle_dual_eval_tile.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D,
                                               _P, _I64, _P, _I64, _D, _D, _I,
@@ -171,6 +180,52 @@ def kept_counts(x, y, cutoff, cost_scale=0.5, rel_band=0.0, threads=0):
     if rc != 0:
         raise ValueError("oracle_kept_counts: invalid arguments")
     return kept, near
+
+
+def _keep_args(keep):
+    """(tile_of, block_of, n_blocks, keep matrix) of a truncated plan, or Nones."""
+    if keep is None:
+        return None, None, 0, None
+    tile_of, block_of, mat = keep
+    mat = np.ascontiguousarray(mat, dtype=np.uint8)
+    return _c(tile_of, np.int32), _c(block_of, np.int32), mat.shape[1], mat
+
+
+def plan_moments(x, mu, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
+    """Target moments of the plan (Sec. 6.2): (nu~, first) with
+    nu~_j = sum_q mu_q p_qj and first[j] = sum_q mu_q p_qj x_q. keep =
+    (tile_of, block_of, keep matrix) restricts the plan to kept pairs."""
+    lib = _load()
+    x, mu, y, nu, psi = _c(x), _c(mu), _c(y), _c(nu), _c(psi)
+    d, nq, n = x.shape[1], x.shape[0], y.shape[0]
+    mass = np.empty(n)
+    first = np.empty((n, d))
+    to, bo, nb, km = _keep_args(keep)
+    rc = lib.oracle_plan_moments(d, nq, _ptr(x), _ptr(mu), n, _ptr(y), _ptr(nu), _ptr(psi),
+                                 float(eps), float(cost_scale), _ptr(to), _ptr(bo), int(nb),
+                                 _ptr(km), int(threads), _ptr(mass), _ptr(first))
+    if rc != 0:
+        raise ValueError("oracle_plan_moments: invalid arguments")
+    return mass, first
+
+
+def transport_maps(x, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
+    """Maps of the plan (Sec. 6.3): barycentric map (nq x d), modal target
+    index (nq, lowest index on ties, -1 if a point has no kept pair) and the
+    maximum of psi_j - c_qj + eps ln nu_j it attains."""
+    lib = _load()
+    x, y, nu, psi = _c(x), _c(y), _c(nu), _c(psi)
+    d, nq, n = x.shape[1], x.shape[0], y.shape[0]
+    bary = np.empty((nq, d))
+    modal = np.empty(nq, dtype=np.int32)
+    val = np.empty(nq)
+    to, bo, nb, km = _keep_args(keep)
+    rc = lib.oracle_transport_maps(d, nq, _ptr(x), n, _ptr(y), _ptr(nu), _ptr(psi), float(eps),
+                                   float(cost_scale), _ptr(to), _ptr(bo), int(nb), _ptr(km),
+                                   int(threads), _ptr(bary), _ptr(modal), _ptr(val))
+    if rc != 0:
+        raise ValueError("oracle_transport_maps: invalid arguments")
+    return bary, modal, val
 
 
 def covering_cost(x, y, cost_scale=0.5, threads=0) -> float:

@@ -452,3 +452,135 @@ int oracle_dual_eval_tile(int d, int64_t nq, const double *x, const double *mu,
     free(lognu); free(gpart); free(Jpart); free(kpart);
     return 0;
 }
+
+/*
+ * Pair membership shared by the plan-moment and map functions: all pairs, or
+ * (keep != NULL) the pairs whose (tile_of[q], block_of[j]) entry of the
+ * row-major n_tiles x n_blocks keep matrix is nonzero (a truncated plan).
+ */
+static int pair_kept(const uint8_t *keep, const int32_t *tile_of, const int32_t *block_of,
+                     int64_t n_blocks, int64_t q, int64_t j)
+{
+    if (!keep) return 1;
+    return keep[(int64_t)tile_of[q] * n_blocks + block_of[j]] != 0;
+}
+
+/*
+ * Moments of the plan pi_qj = mu_q p_qj(psi) over the targets (Sec. 6.2):
+ *   mass_out[j]       = sum_q mu_q p_qj                 (= nu~_j, Eq. discretized_gradient)
+ *   first_out[j*d+k]  = sum_q mu_q p_qj x_q[k]          (the integral in Eq. barycenter_fixed_point;
+ *                                                        T_j = first_j / nu_j)
+ * with p_qj = nu_j exp((psi_j - c_qj)/eps) / S_q over the kept pairs. Plain
+ * loops: per point its log-sum-exp, then its weights scattered to the
+ * targets; per-thread arrays summed in thread order. Either output may be NULL.
+ */
+int oracle_plan_moments(int d, int64_t nq, const double *x, const double *mu,
+                        int64_t n, const double *y, const double *nu,
+                        const double *psi, double eps, double cost_scale,
+                        const int32_t *tile_of, const int32_t *block_of,
+                        int64_t n_blocks, const uint8_t *keep, int nthreads,
+                        double *mass_out, double *first_out)
+{
+    if (d < 1 || nq < 0 || n < 1 || !(eps > 0.0)) return -1;
+    const int T = oracle_threads(nthreads);
+    const size_t per = (size_t)n * (size_t)(d + 1);
+    double *part = (double *)calloc((size_t)T * per, sizeof(double));
+    if (!part) return -1;
+#pragma omp parallel num_threads(T)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+        double *acc = part + (size_t)tid * per;
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < nq; ++q) {
+            double zmax = -INFINITY;
+            for (int64_t j = 0; j < n; ++j) {
+                z[j] = -INFINITY;
+                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j)) continue;
+                z[j] = (psi[j] - cost(d, x + q * d, y + j * d, cost_scale)) / eps + log(nu[j]);
+                if (z[j] > zmax) zmax = z[j];
+            }
+            if (!(zmax > -INFINITY)) continue;
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += exp(z[j] - zmax);
+            const double L = zmax + log(s);
+            for (int64_t j = 0; j < n; ++j) {
+                if (!(z[j] > -INFINITY)) continue;
+                const double w = mu[q] * exp(z[j] - L);
+                acc[j * (d + 1)] += w;
+                for (int k = 0; k < d; ++k) acc[j * (d + 1) + 1 + k] += w * x[q * d + k];
+            }
+        }
+        free(z);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double m = 0.0, f[3] = {0.0, 0.0, 0.0};
+        for (int t = 0; t < T; ++t) {
+            const double *a = part + (size_t)t * per + (size_t)j * (d + 1);
+            m += a[0];
+            for (int k = 0; k < d && k < 3; ++k) f[k] += a[1 + k];
+        }
+        if (mass_out) mass_out[j] = m;
+        if (first_out)
+            for (int k = 0; k < d && k < 3; ++k) first_out[j * d + k] = f[k];
+    }
+    free(part);
+    return 0;
+}
+
+/*
+ * Transport maps of the plan (Sec. 6.3), per quadrature point:
+ *   bary_out[q*d+k] = sum_j p_qj y_j[k]               (Eq. barycentric_map_registration)
+ *   modal_out[q]    = argmax_j (psi_j - c_qj + eps ln nu_j)   (Eq. modal_map_registration;
+ *                     the lowest index on ties; -1 for a point with no kept pair)
+ *   val_out[q]      = that maximum (may be NULL)
+ * over the kept pairs. Either output may be NULL.
+ */
+int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const double *y,
+                          const double *nu, const double *psi, double eps,
+                          double cost_scale, const int32_t *tile_of,
+                          const int32_t *block_of, int64_t n_blocks,
+                          const uint8_t *keep, int nthreads, double *bary_out,
+                          int32_t *modal_out, double *val_out)
+{
+    if (d < 1 || nq < 0 || n < 1 || !(eps > 0.0) || d > 3) return -1;
+    const int T = oracle_threads(nthreads);
+#pragma omp parallel num_threads(T)
+    {
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < nq; ++q) {
+            double zmax = -INFINITY, vmax = -INFINITY;
+            int64_t jbest = -1;
+            for (int64_t j = 0; j < n; ++j) {
+                z[j] = -INFINITY;
+                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j)) continue;
+                const double c = cost(d, x + q * d, y + j * d, cost_scale);
+                z[j] = (psi[j] - c) / eps + log(nu[j]);
+                if (z[j] > zmax) zmax = z[j];
+                const double v = psi[j] - c + eps * log(nu[j]);
+                if (v > vmax) {
+                    vmax = v;
+                    jbest = j;
+                }
+            }
+            if (modal_out) modal_out[q] = (int32_t)jbest;
+            if (val_out) val_out[q] = vmax;
+            if (!bary_out) continue;
+            double s = 0.0, b[3] = {0.0, 0.0, 0.0};
+            if (zmax > -INFINITY)
+                for (int64_t j = 0; j < n; ++j) {
+                    if (!(z[j] > -INFINITY)) continue;
+                    const double w = exp(z[j] - zmax);
+                    s += w;
+                    for (int k = 0; k < d; ++k) b[k] += w * y[j * d + k];
+                }
+            for (int k = 0; k < d; ++k) bary_out[q * d + k] = s > 0.0 ? b[k] / s : NAN;
+        }
+        free(z);
+    }
+    return 0;
+}

@@ -16,6 +16,16 @@ double oracle_covering_cost(int d, int64_t nq, const double *x, int64_t n, const
 int oracle_kept_counts(int d, int64_t nq, const double *x, int64_t n, const double *y,
                        double cost_scale, double cutoff, double rel_band, int nthreads,
                        int32_t *kept_out, int32_t *near_out);
+int oracle_plan_moments(int d, int64_t nq, const double *x, const double *mu, int64_t n,
+                        const double *y, const double *nu, const double *psi, double eps,
+                        double cost_scale, const int32_t *tile_of, const int32_t *block_of,
+                        int64_t n_blocks, const uint8_t *keep, int nthreads, double *mass_out,
+                        double *first_out);
+int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const double *y,
+                          const double *nu, const double *psi, double eps, double cost_scale,
+                          const int32_t *tile_of, const int32_t *block_of, int64_t n_blocks,
+                          const uint8_t *keep, int nthreads, double *bary_out,
+                          int32_t *modal_out, double *val_out);
 double oracle_cutoff_geom(double C0, double M, double m, double nu_min, double tau,
                           double absJ, double eps);
 double oracle_cutoff_int(double C0, double M, double D, double tau, double absJ, double eps);
@@ -100,6 +110,20 @@ static void run(int d, int64_t nq, int64_t n, double eps) {
     for (int64_t q = 0; q < nq; ++q) ks += kq[q] + nr[q];
     printf("counts rc=%d sum=%ld\n", rc, ks);
     free(kq); free(nr);
+    /* plan moments and maps, dense and over the tile rule's kept pairs */
+    double *mass = alloc_fill(n, 0, 0), *first = alloc_fill(n * d, 0, 0);
+    double *bary = alloc_fill(nq * d, 0, 0), *mval = alloc_fill(nq, 0, 0);
+    int32_t *modal = (int32_t *)malloc(sizeof(int32_t) * (size_t)nq);
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint8_t *kp = pass ? keep : NULL;
+        rc = oracle_plan_moments(d, nq, x, mu, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp, 2,
+                                 mass, first);
+        printf("moments rc=%d mass0=%.15e\n", rc, mass[0]);
+        rc = oracle_transport_maps(d, nq, x, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp, 2, bary,
+                                   modal, mval);
+        printf("maps rc=%d modal0=%d\n", rc, (int)modal[0]);
+    }
+    free(mass); free(first); free(bary); free(mval); free(modal);
     /* softmax refinement onto 7 fine targets */
     double *yf = alloc_fill(7 * d, 0.0, 1.0), *pf = alloc_fill(7, 0, 0);
     oracle_dual_eval(d, nq, x, mu, n, y, nu, psi, eps, 0.5, INFINITY, 1, &J, NULL, L, &kept,
