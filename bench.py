@@ -7,11 +7,16 @@ on the 3D workload: unit cube, 64^3 cells x 6 Kuhn tetrahedra x 4 points =
 6,291,456 quadrature points, 3-Gaussian-mixture source, 65,536 mixture
 targets, eps = 1e-3, psi a seeded N(0, eps^2) perturbation. Inputs are
 resident in device memory before the timed region. The JSON line (stdout)
-reports dense pairs/s as ``value`` plus the truncated rules, the FP64 path,
-the time to ||grad||_1 < 1e-6 on the 2D workload and on this 3D workload (from
-psi = 0 with the eps schedule), the roofline of the dominant kernel and the
-CPU oracle on a bounded sample. Progress goes to
-stderr.
+reports dense pairs/s as ``value``, the roofline of the dominant kernel and
+the CPU oracle on a bounded sample, and under "extras" every other workload:
+the truncated rules and the FP64 path on this workload; time to
+||grad||_1 < 1e-6 on the 2D square (FP64), on this workload from psi = 0 and
+from the multilevel start; the multilevel disk workload; 64 uneven batched
+instances against single calls; the learned warm start against the zero and
+multilevel starts on held-out instances; the network kernels. Each solve's
+returned potential is re-checked independently (the oracle where it finishes
+in seconds, else the FP64 path). --quick skips the disk, batched and learned
+legs. Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -31,11 +36,11 @@ sys.path.insert(0, ROOT)
 
 # MI355X figures used by the roofline (256 CUs at 2.4 GHz):
 #   FP32 vector 157.3 TFLOP/s -> 7.86e13 lane-ops/s (128 lanes/clk/CU, an FMA
-#   counted as one op); the rate probe reaches 6.26e13/s with non-packed
-#   v_fma_f32, so no packed instructions are needed to approach it.
-#   v_exp_f32 at a quarter of that: 32 lanes/clk/CU = 1.966e13/s (probe:
-#   1.905e13/s). These are the published FP32 rate and the transcendental
-#   quarter rate; the per-pair op counts are the algorithm's, not the kernel's.
+#   counted as one op); a rate microbenchmark reached 6.26e13/s with
+#   non-packed v_fma_f32.
+#   v_exp_f32 at 32 lanes/clk/CU = 1.966e13/s: a quarter of the 128-lane FP32
+#   rate (the microbenchmark measured 1.905e13/s). The per-pair op counts are
+#   the algorithm's, not the kernel's.
 PEAK_VALU_OPS = 256 * 2.4e9 * 128          # 7.86e13 FP32 lane-ops/s
 PEAK_EXP = 256 * 2.4e9 * 32                # 1.966e13 exp/s
 
@@ -75,20 +80,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the disk multilevel, batched and learned legs")
     ap.add_argument("--ml-spread", action="store_true",
                     help="multilevel leg with the eps stages spread over all four levels")
-    ap.add_argument("--multilevel", action="store_true",
-                    help="also time the combined multilevel solve of the 2D disk workload")
-    ap.add_argument("--batched", type=int, default=0,
-                    help="also time N uneven 3D instances: one batched call vs single calls")
+    ap.add_argument("--no-multilevel", action="store_true",
+                    help="skip the combined multilevel solve of the 2D disk workload")
+    ap.add_argument("--batched", type=int, default=64,
+                    help="N uneven 3D instances: one batched call vs single calls (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM counters)")
-    ap.add_argument("--mlp", type=str, default="",
+    ap.add_argument("--mlp", type=str, default="65536,20",
                     help="time the warm-start network kernels: 'ROWS,STEPS' training steps "
-                         "and forward passes on synthetic rows (e.g. 65536,20)")
-    ap.add_argument("--learned", type=str, default="",
-                    help="learned warm start on the blob family: 'TRAIN,TEST,EPOCHS' "
-                         "(e.g. 448,64,20): dataset from the solver, training, comparison")
+                         "and forward passes on synthetic rows ('' to skip)")
+    ap.add_argument("--learned", type=str, default="448,64,30",
+                    help="learned warm start on the blob family: 'TRAIN,TEST,EPOCHS': dataset "
+                         "from the solver, training, comparison ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -206,6 +213,18 @@ def main():
         g64 = grad.clone()
         prob.set_precision("mixed")
         rm = prob.dual_eval(psi, p.eps, out=grad)
+        # plan moments and transport maps (Secs. 6.2, 6.3), dense, at the same
+        # psi: device time of the moment / map kernels after the evaluation
+        prob.plan_moments(psi, p.eps)
+        prob.transport_maps(psi, p.eps)
+        mom_ms = min(prob.plan_moments(psi, p.eps)[3] for _ in range(3))
+        map_ms = min(prob.transport_maps(psi, p.eps)[3] for _ in range(3))
+        extras["plan_moments"] = {"moments_ms": mom_ms, "moments_pairs_s": pairs / (mom_ms * 1e-3),
+                                  "maps_ms": map_ms, "maps_pairs_s": pairs / (map_ms * 1e-3),
+                                  "note": "kernels after the evaluation that gives L_q; "
+                                          "dense, mixed precision"}
+        log(f"[bench] plan moments {mom_ms:.1f} ms ({pairs / (mom_ms * 1e-3):.3e} pairs/s), "
+            f"maps {map_ms:.1f} ms ({pairs / (map_ms * 1e-3):.3e} pairs/s)")
         nu_t = torch.as_tensor(p.nu, device=dev)
         eg = torch.max(torch.abs(grad - g64) / (nu_t + g64 + nu_t)).item()
         extras["fp64_dense"]["grad_err_mixed_vs_fp64"] = eg
@@ -236,7 +255,7 @@ def main():
         sched = [p.eps * 2.0 ** k for k in range(K, 0, -1)] + [p.eps]
         pr2 = rsot.Problem(p.x, p.mu, p.y, p.nu, truncation="tile", tau=1e-12)
         ts = time.perf_counter()
-        _, info2 = pr2.solve(sched, tol=1e-6, stage_tol=1e-5)
+        psi2, info2 = pr2.solve(sched, tol=1e-6, stage_tol=1e-5)
         t2 = time.perf_counter() - ts
         extras["time_to_tol_config2"] = {"workload": p.name, "seconds": t2, "eps_schedule": sched,
                                          "truncation": "tile", "tau": 1e-12,
@@ -244,7 +263,8 @@ def main():
                                          "evaluations": info2["evaluations"],
                                          "grad_l1": info2["grad_l1"],
                                          "kept_frac": info2["kept_frac"],
-                                         "status": info2["status"]}
+                                         "status": info2["status"],
+                                         "recheck": fp64_recheck(p, psi2)}
         log(f"[bench] config2 solve: {t2:.2f} s, {info2['iterations']} it, "
             f"{info2['evaluations']} evals, |g|_1={info2['grad_l1']:.2e}")
         pr2.close()
@@ -260,8 +280,8 @@ def main():
                                      torch.as_tensor(p.nu, device=dev),
                                      [4096, 16384, p.n], lloyd_iters=20, seed=6)
         ml2 = rsot.Multilevel(srcs, hier, precision="mixed", truncation="tile", tau=1e-12)
-        _, info3 = ml2.solve(sched + [p.eps] * 2, [0] * len(sched) + [1, 2], tol=1e-6,
-                             stage_tol=1e-5)
+        psi3, info3 = ml2.solve(sched + [p.eps] * 2, [0] * len(sched) + [1, 2], tol=1e-6,
+                                stage_tol=1e-5)
         torch.cuda.synchronize()
         t3 = time.perf_counter() - ts
         ml2.close()
@@ -269,26 +289,60 @@ def main():
             "workload": p.name, "seconds": t3, "source_cells": [16, 32, 64],
             "targets": [int(h[1].numel()) for h in hier], "iterations": info3["iterations"],
             "seconds_per_level": info3["seconds"], "grad_l1": info3["grad_l1"],
-            "status": info3["status"]}
+            "status": info3["status"], "recheck": fp64_recheck(p, psi3)}
         log(f"[bench] config2 multilevel solve: {t3:.2f} s (hierarchy included), iterations "
             f"{info3['iterations']}, |g|_1={info3['grad_l1']:.2e}")
         out["extras"] = extras
 
-    if args.multilevel:
-        out.setdefault("extras", {})["multilevel"] = multilevel_leg(spread=args.ml_spread)
-    if args.batched:
-        out.setdefault("extras", {})["batched"] = batched_leg(args.batched)
-    if args.mlp:
-        rows, steps = (int(v) for v in args.mlp.split(","))
-        out.setdefault("extras", {})["mlp"] = mlp_leg(rows, steps)
-    if args.learned:
-        n_train, n_test, epochs = (int(v) for v in args.learned.split(","))
-        out.setdefault("extras", {})["learned"] = learned_leg(n_train, n_test, epochs)
+    legs = []
+    if not args.no_extras:
+        if not (args.quick or args.no_multilevel):
+            legs.append(("multilevel", lambda: multilevel_leg(spread=args.ml_spread)))
+        if args.batched and not args.quick:
+            legs.append(("batched", lambda: batched_leg(args.batched)))
+        if args.mlp:
+            rows, steps = (int(v) for v in args.mlp.split(","))
+            legs.append(("mlp", lambda: mlp_leg(rows, steps)))
+        if args.learned and not args.quick:
+            n_train, n_test, epochs = (int(v) for v in args.learned.split(","))
+            legs.append(("learned", lambda: learned_leg(n_train, n_test, epochs)))
+    for name, leg in legs:
+        ts = time.perf_counter()
+        try:
+            res = leg()
+        except Exception as e:          # a failing leg is reported, the line still printed
+            log(f"[bench] {name} leg failed: {e!r}")
+            res = {"error": repr(e)}
+        res["leg_seconds"] = time.perf_counter() - ts
+        out.setdefault("extras", {})[name] = res
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
                                            psi1 if not args.no_extras else None)
     print(json.dumps(out), flush=True)
+
+
+def fp64_recheck(p, psi, n_sample=256, seed=0):
+    """Independent check of a solve's returned potential: ||grad||_1 and J by
+    the library's FP64 dense path (which the oracle pins in the tests; a dense
+    oracle pass at these sizes would take minutes to hours), and the largest
+    difference of that path's per-point L_q from the oracle's at n_sample
+    seeded points. p: x, mu, y, nu, eps."""
+    import torch
+    import oracle
+    from paper_2507_23602_amd import rsot
+    pr = rsot.Problem(*[torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)],
+                      precision="fp64")
+    r = pr.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    L = pr.lse().cpu().numpy()
+    pr.close()
+    idx = np.random.default_rng(seed).choice(p.x.shape[0], n_sample, replace=False)
+    ref = oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, want_grad=False,
+                           want_L=True)
+    el = float(np.max(np.abs(L[idx] - ref.L) / np.maximum(1.0, np.abs(ref.L))))
+    log(f"[bench] re-check: FP64 ||g||_1 {r.info['grad_l1']:.3e}, sampled L vs oracle {el:.1e}")
+    return {"fp64_grad_l1": r.info["grad_l1"], "fp64_J": r.J, "fp64_ms": r.info["kernel_ms"],
+            "sampled_L_err_vs_oracle": el, "n_sample": n_sample}
 
 
 MLP_FWD_FLOP_PER_ROW = 2 * (6 * 256 + 3 * 256 * 256 + 256)      # multiply-adds x 2
@@ -347,6 +401,7 @@ def learned_leg(n_train, n_test, epochs):
     multilevel start, to ||grad||_1 < 1e-6."""
     import torch
     from paper_2507_23602_amd import warmstart as WS
+    from paper_2507_23602_amd import workloads as W4
     t0 = time.perf_counter()
     train_ids = list(range(n_train))
     test_ids = list(range(n_train, n_train + n_test))
@@ -359,8 +414,21 @@ def learned_leg(n_train, n_test, epochs):
     t_train = time.perf_counter() - t1
     rows = target.numel()
     del feats, target
-    recs = WS.compare(m, test_ids)
+    recs = WS.compare(m, test_ids, keep_psi=2)
     summ = WS.summarize(recs)
+    # the oracle re-checks ||grad||_1 at the learned-start solutions of the
+    # first two held-out instances
+    import oracle
+    rechecks = []
+    for r in recs[:2]:
+        q = W4.config4_instance(r["id"])
+        psi = r["learned"].pop("psi")
+        ev = oracle.dual_eval(q.x, q.mu, q.y, q.nu, psi, q.eps,
+                              threads=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        rechecks.append({"id": r["id"], "oracle_grad_l1": float(np.abs(ev.grad).sum())})
+    for r in recs[2:]:
+        r["learned"].pop("psi", None)
+    log(f"[bench] learned: oracle re-check of ||g||_1 {[round(c['oracle_grad_l1'], 9) for c in rechecks]}")
     log(f"[bench] learned: dataset {t_data:.1f}s ({n_train} solves), training {t_train:.1f}s "
         f"({epochs} epochs x {rows} rows); test {summ}")
     return {"workload": "blob_square128_tri3_nq98304_n65536", "train_instances": n_train,
@@ -368,7 +436,9 @@ def learned_leg(n_train, n_test, epochs):
             "train_rows": rows, "epochs": epochs, "train_log": tlog, "summary": summ,
             "dataset_mean_iterations": float(np.mean([r["iterations"] for r in drecs])),
             "dataset_mean_seconds": float(np.mean([r["seconds"] for r in drecs])),
-            "per_instance": recs}
+            "learned_vs_multilevel_seconds": [summ["learned"]["total_seconds"],
+                                              summ.get("multilevel", {}).get("total_seconds")],
+            "oracle_recheck": rechecks, "per_instance": recs}
 
 
 def batched_leg(k):
@@ -431,6 +501,31 @@ def batched_leg(k):
                     "tune_seconds": t_tune}
     res.update(instances=k, dense_pairs=dense_pairs, kept_frac=kept / dense_pairs,
                effective_pairs_s_batched=dense_pairs / tb)
+    # the oracle on the four smallest members, against the batched call's
+    # results (tile rule: the oracle applies the same rule to the same
+    # partition and |J_ref|)
+    import oracle
+    J, grads, infos, _ = rsot.dual_eval_batched(probs, eps, psis)
+    order = sorted(range(k), key=lambda i: insts[i].nq * insts[i].n)[:4]
+    checks = []
+    for i in order:
+        q = insts[i]
+        tile_of, block_of, nt, nb = probs[i].partition()
+        ref = oracle.dual_eval_tile(q.x, q.mu, q.y, q.nu, psis[i].cpu().numpy(), q.eps,
+                                    tile_of.cpu().numpy(), nt, block_of.cpu().numpy(), nb,
+                                    1e-12, infos[i]["absJ_ref"],
+                                    threads=int(os.environ.get("OMP_NUM_THREADS",
+                                                               os.cpu_count() or 1)))
+        g = grads[i].cpu().numpy()
+        checks.append({"instance": i, "nq": q.nq, "n": q.n,
+                       "J_rel_err": abs(J[i] - ref.J) / abs(ref.J),
+                       "grad_err": float(np.max(np.abs(g - ref.grad) / (q.nu + ref.grad + q.nu))),
+                       "kept_equal": infos[i]["kept_pairs"] == ref.kept})
+    res["oracle_check"] = checks
+    worst_j = max(c["J_rel_err"] for c in checks)
+    worst_g = max(c["grad_err"] for c in checks)
+    log(f"[bench] batched: oracle on the 4 smallest members: J rel err <= {worst_j:.1e}, "
+        f"e_g <= {worst_g:.1e}, kept sets equal: {all(c['kept_equal'] for c in checks)}")
     log(f"[bench] batched {k}: kept {kept/dense_pairs:.4f} of {dense_pairs:.3e}; untuned singles "
         f"{res['untuned']['singles_s']*1e3:.1f} ms, batched {res['untuned']['batched_s']*1e3:.1f} ms; "
         f"tuned singles {ts*1e3:.1f} ms, batched {tb*1e3:.1f} ms (tuning {t_tune:.1f}s)")
@@ -468,37 +563,71 @@ def multilevel_leg(spread=False):
     psi, info = ml.solve(c3["eps" + key], c3["level" + key], tol=1e-6,
                          level_tol=1e-5 if spread else 0.0, stage_tol=1e-5, callback=progress)
     t_s = time.perf_counter() - t0
+    ml.close()
+    from types import SimpleNamespace
+    fin = SimpleNamespace(x=c3["sources"][-1][0], mu=c3["sources"][-1][1], y=c3["y"],
+                          nu=c3["nu"], eps=c3["eps" + key][-1])
+    recheck = fp64_recheck(fin, psi)
     log(f"[bench] multilevel: hierarchy {t_h:.2f}s, solve {t_s:.2f}s, status {info['status']}, "
         f"|g|_1 {info['grad_l1']:.2e}, iterations {info['iterations']}, "
         f"seconds {[round(v, 3) for v in info['seconds']]}, "
         f"refine {[round(v, 3) for v in info['refine_seconds']]}")
-    ml.close()
     return {"workload": c3["name"], "schedule": "spread" if spread else "coarse",
             "hierarchy_seconds": t_h, "solve_seconds": t_s,
+            "time_to_tol_seconds": t_h + t_s, "recheck": recheck,
             "target_sizes": [int(l[1].numel()) for l in levels], **info}
+
+
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(p, psi, psi_c1):
     """The oracle (plain FP64 C, OpenMP) on a bounded sample of the same
     workload: a seeded subset of quadrature points against all targets,
-    sized to take ~15 s; pairs/s scaled to the sample."""
+    sized to take ~15 s on all threads and ~4 s on one. value is the rate on
+    that sample; the time of a full evaluation is extrapolated from it (and
+    labelled so). The config-1 solve runs the oracle's strong-Wolfe L-BFGS,
+    the line search the GPU solver uses."""
     import oracle
     from paper_2507_23602_amd import workloads as W
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(0)
-    probe = rng.choice(p.nq, size=2048, replace=False)
-    ts = time.perf_counter()
-    oracle.dual_eval(p.x[probe], p.mu[probe], p.y, p.nu, psi, p.eps, threads=threads)
-    tp = time.perf_counter() - ts
-    m = int(min(p.nq, max(2048, 2048 * 15.0 / max(tp, 1e-3))))
-    idx = rng.choice(p.nq, size=m, replace=False)
-    ts = time.perf_counter()
-    oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, threads=threads)
-    t = time.perf_counter() - ts
-    res = {"value": m * p.n / t, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+
+    def rate(seconds, nth):
+        probe = rng.choice(p.nq, size=512 if nth == 1 else 2048, replace=False)
+        ts = time.perf_counter()
+        oracle.dual_eval(p.x[probe], p.mu[probe], p.y, p.nu, psi, p.eps, threads=nth)
+        tp = time.perf_counter() - ts
+        m = int(min(p.nq, max(probe.size, probe.size * seconds / max(tp, 1e-3))))
+        idx = rng.choice(p.nq, size=m, replace=False)
+        ts = time.perf_counter()
+        oracle.dual_eval(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, threads=nth)
+        return m, time.perf_counter() - ts
+
+    m, t = rate(15.0, threads)
+    m1, t1 = rate(4.0, 1)
+    value = m * p.n / t
+    res = {"value": value, "unit": "pairs/s", "cores": threads, "kind": "oracle",
            "sample": f"{m} random quadrature points of the workload x all {p.n} targets "
-                     f"(dense objective + gradient), {t:.1f} s"}
-    log(f"[bench] cpu oracle: {res['value']:.3e} pairs/s on {threads} threads ({t:.1f}s)")
+                     f"(dense objective + gradient) in {t:.1f} s on {threads} threads; "
+                     f"pairs/s measured on that sample",
+           "extrapolated": True,
+           "full_eval_seconds_extrapolated": p.nq * p.n / value,
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "single_thread_pairs_s": m1 * p.n / t1,
+           "single_thread_sample": f"{m1} points x {p.n} targets in {t1:.1f} s"}
+    log(f"[bench] cpu oracle ({res['cpu_model']}): {value:.3e} pairs/s on {threads} threads "
+        f"({t:.1f}s), {res['single_thread_pairs_s']:.3e} on one; a full evaluation would take "
+        f"{res['full_eval_seconds_extrapolated']:.0f} s (extrapolated)")
     if psi_c1 is not None:
         c1 = W.config1()
 
@@ -506,13 +635,18 @@ def cpu_baseline(p, psi, psi_c1):
             e = oracle.dual_eval(c1.x, c1.mu, c1.y, c1.nu, v, c1.eps, threads=threads)
             return e.J, e.grad
         ts = time.perf_counter()
-        _, _, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(c1.n), tol=1e-6)
+        _, _, g, it, nev = oracle.lbfgs_solve(fun, np.zeros(c1.n), tol=1e-6,
+                                              h0=c1.eps * c1.n / c1.nu.sum(),
+                                              line_search="wolfe")
         res["config1_solve_seconds"] = time.perf_counter() - ts
         res["config1_solve_iterations"] = it
+        res["config1_solve_evaluations"] = nev
+        res["config1_solve_line_search"] = "strong Wolfe (c1 1e-4, c2 0.9, <= 20 evaluations)"
         recheck = oracle.dual_eval(c1.x, c1.mu, c1.y, c1.nu, psi_c1, c1.eps, threads=threads)
         res["config1_gpu_psi_grad_l1_recheck"] = float(np.abs(recheck.grad).sum())
-        log(f"[bench] cpu oracle config1 solve {res['config1_solve_seconds']:.2f}s ({it} it); "
-            f"recheck of GPU psi: |g|_1 = {res['config1_gpu_psi_grad_l1_recheck']:.2e}")
+        log(f"[bench] cpu oracle config1 solve {res['config1_solve_seconds']:.2f}s ({it} it, "
+            f"{nev} evaluations); recheck of GPU psi: |g|_1 = "
+            f"{res['config1_gpu_psi_grad_l1_recheck']:.2e}")
     return res
 
 

@@ -113,14 +113,16 @@ def _ml_stages(eps):
 
 
 def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
-            multilevel=True, coarse_cells=(32, 64), target_levels=(4096, 16384)):
+            multilevel=True, coarse_cells=(32, 64), target_levels=(4096, 16384), keep_psi=0):
     """Held-out instances: wall-clock seconds and iterations to ||g||_1 < tol
     from (a) zero with the eps schedule, (b) zero at the final eps alone,
     (c) the learned start (rsot_solve_learned), (d) the combined multilevel
     start (Sec. 5.3): the eps schedule on the coarsest level, the final eps on
     the finer ones. Levels and eps stages before the last stop at 10 tol
     (the three levels cost about the same, and solving the coarser two to
-    tol measured slower: 6.60 s against 5.92 s over the 64 test instances)."""
+    tol measured slower: 6.60 s against 5.92 s over the 64 test instances).
+    The first keep_psi records also carry the learned-start solution
+    (rec["learned"]["psi"], numpy) for an independent re-check."""
     import torch
     out = []
     hier = None
@@ -161,6 +163,8 @@ def compare(m, ids, n_cells=128, n_targets=65536, tol=1e-6, truncation="tile",
         pr.close()
         scale = float(np.max(np.abs(psi_a)))
         rec["learned"]["max_dpsi_vs_zero_sched"] = float(np.max(np.abs(psi_c - psi_a))) / scale
+        if k < keep_psi:
+            rec["learned"]["psi"] = psi_c
         if multilevel:
             srcs = []
             for nc in coarse_cells:
