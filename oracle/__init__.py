@@ -87,10 +87,10 @@ def _load():
         lib.oracle_softmax_refine.argtypes = [_I, _I64, _P, _P, _P, _I64, _P, _D, _D, _I, _P]
         lib.oracle_plan_moments.restype = _I
         lib.oracle_plan_moments.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D, _P, _P,
-                                            _I64, _P, _I, _P, _P]
+                                            _I64, _P, _D, _I, _P, _P]
         lib.oracle_transport_maps.restype = _I
         lib.oracle_transport_maps.argtypes = [_I, _I64, _P, _I64, _P, _P, _P, _D, _D, _P, _P,
-                                              _I64, _P, _I, _P, _P, _P]
+                                              _I64, _P, _D, _I, _P, _P, _P]
         lib.oracle_dual_eval_tile.restype = _I
         lib.oracle_dual_eval_tile.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D,
                                               _P, _I64, _P, _I64, _D, _D, _I,
@@ -191,10 +191,12 @@ def _keep_args(keep):
     return _c(tile_of, np.int32), _c(block_of, np.int32), mat.shape[1], mat
 
 
-def plan_moments(x, mu, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
+def plan_moments(x, mu, y, nu, psi, eps, cost_scale=0.5, keep=None, cutoff=math.inf,
+                 threads=0):
     """Target moments of the plan (Sec. 6.2): (nu~, first) with
     nu~_j = sum_q mu_q p_qj and first[j] = sum_q mu_q p_qj x_q. keep =
-    (tile_of, block_of, keep matrix) restricts the plan to kept pairs."""
+    (tile_of, block_of, keep matrix) restricts the plan to kept pairs, a
+    finite cutoff to pairs with c < cutoff."""
     lib = _load()
     x, mu, y, nu, psi = _c(x), _c(mu), _c(y), _c(nu), _c(psi)
     d, nq, n = x.shape[1], x.shape[0], y.shape[0]
@@ -203,13 +205,14 @@ def plan_moments(x, mu, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
     to, bo, nb, km = _keep_args(keep)
     rc = lib.oracle_plan_moments(d, nq, _ptr(x), _ptr(mu), n, _ptr(y), _ptr(nu), _ptr(psi),
                                  float(eps), float(cost_scale), _ptr(to), _ptr(bo), int(nb),
-                                 _ptr(km), int(threads), _ptr(mass), _ptr(first))
+                                 _ptr(km), float(cutoff), int(threads), _ptr(mass),
+                                 _ptr(first))
     if rc != 0:
         raise ValueError("oracle_plan_moments: invalid arguments")
     return mass, first
 
 
-def transport_maps(x, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
+def transport_maps(x, y, nu, psi, eps, cost_scale=0.5, keep=None, cutoff=math.inf, threads=0):
     """Maps of the plan (Sec. 6.3): barycentric map (nq x d), modal target
     index (nq, lowest index on ties, -1 if a point has no kept pair) and the
     maximum of psi_j - c_qj + eps ln nu_j it attains."""
@@ -222,7 +225,8 @@ def transport_maps(x, y, nu, psi, eps, cost_scale=0.5, keep=None, threads=0):
     to, bo, nb, km = _keep_args(keep)
     rc = lib.oracle_transport_maps(d, nq, _ptr(x), n, _ptr(y), _ptr(nu), _ptr(psi), float(eps),
                                    float(cost_scale), _ptr(to), _ptr(bo), int(nb), _ptr(km),
-                                   int(threads), _ptr(bary), _ptr(modal), _ptr(val))
+                                   float(cutoff), int(threads), _ptr(bary), _ptr(modal),
+                                   _ptr(val))
     if rc != 0:
         raise ValueError("oracle_transport_maps: invalid arguments")
     return bary, modal, val

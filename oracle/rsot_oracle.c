@@ -454,13 +454,15 @@ int oracle_dual_eval_tile(int d, int64_t nq, const double *x, const double *mu,
 }
 
 /*
- * Pair membership shared by the plan-moment and map functions: all pairs, or
+ * Pair membership shared by the plan-moment and map functions: all pairs; or
  * (keep != NULL) the pairs whose (tile_of[q], block_of[j]) entry of the
- * row-major n_tiles x n_blocks keep matrix is nonzero (a truncated plan).
+ * row-major n_tiles x n_blocks keep matrix is nonzero (the tile rule); and,
+ * with a finite cutoff > 0, only pairs with c_qj < cutoff (Sec. 4.1).
  */
 static int pair_kept(const uint8_t *keep, const int32_t *tile_of, const int32_t *block_of,
-                     int64_t n_blocks, int64_t q, int64_t j)
+                     int64_t n_blocks, int64_t q, int64_t j, double c, double cutoff)
 {
+    if (cutoff > 0.0 && isfinite(cutoff) && !(c < cutoff)) return 0;
     if (!keep) return 1;
     return keep[(int64_t)tile_of[q] * n_blocks + block_of[j]] != 0;
 }
@@ -478,7 +480,7 @@ int oracle_plan_moments(int d, int64_t nq, const double *x, const double *mu,
                         int64_t n, const double *y, const double *nu,
                         const double *psi, double eps, double cost_scale,
                         const int32_t *tile_of, const int32_t *block_of,
-                        int64_t n_blocks, const uint8_t *keep, int nthreads,
+                        int64_t n_blocks, const uint8_t *keep, double cutoff, int nthreads,
                         double *mass_out, double *first_out)
 {
     if (d < 1 || nq < 0 || n < 1 || !(eps > 0.0)) return -1;
@@ -499,8 +501,9 @@ int oracle_plan_moments(int d, int64_t nq, const double *x, const double *mu,
             double zmax = -INFINITY;
             for (int64_t j = 0; j < n; ++j) {
                 z[j] = -INFINITY;
-                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j)) continue;
-                z[j] = (psi[j] - cost(d, x + q * d, y + j * d, cost_scale)) / eps + log(nu[j]);
+                const double c = cost(d, x + q * d, y + j * d, cost_scale);
+                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j, c, cutoff)) continue;
+                z[j] = (psi[j] - c) / eps + log(nu[j]);
                 if (z[j] > zmax) zmax = z[j];
             }
             if (!(zmax > -INFINITY)) continue;
@@ -543,7 +546,7 @@ int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const d
                           const double *nu, const double *psi, double eps,
                           double cost_scale, const int32_t *tile_of,
                           const int32_t *block_of, int64_t n_blocks,
-                          const uint8_t *keep, int nthreads, double *bary_out,
+                          const uint8_t *keep, double cutoff, int nthreads, double *bary_out,
                           int32_t *modal_out, double *val_out)
 {
     if (d < 1 || nq < 0 || n < 1 || !(eps > 0.0) || d > 3) return -1;
@@ -557,8 +560,8 @@ int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const d
             int64_t jbest = -1;
             for (int64_t j = 0; j < n; ++j) {
                 z[j] = -INFINITY;
-                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j)) continue;
                 const double c = cost(d, x + q * d, y + j * d, cost_scale);
+                if (!pair_kept(keep, tile_of, block_of, n_blocks, q, j, c, cutoff)) continue;
                 z[j] = (psi[j] - c) / eps + log(nu[j]);
                 if (z[j] > zmax) zmax = z[j];
                 const double v = psi[j] - c + eps * log(nu[j]);

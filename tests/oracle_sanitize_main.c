@@ -19,12 +19,12 @@ int oracle_kept_counts(int d, int64_t nq, const double *x, int64_t n, const doub
 int oracle_plan_moments(int d, int64_t nq, const double *x, const double *mu, int64_t n,
                         const double *y, const double *nu, const double *psi, double eps,
                         double cost_scale, const int32_t *tile_of, const int32_t *block_of,
-                        int64_t n_blocks, const uint8_t *keep, int nthreads, double *mass_out,
-                        double *first_out);
+                        int64_t n_blocks, const uint8_t *keep, double cutoff, int nthreads,
+                        double *mass_out, double *first_out);
 int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const double *y,
                           const double *nu, const double *psi, double eps, double cost_scale,
                           const int32_t *tile_of, const int32_t *block_of, int64_t n_blocks,
-                          const uint8_t *keep, int nthreads, double *bary_out,
+                          const uint8_t *keep, double cutoff, int nthreads, double *bary_out,
                           int32_t *modal_out, double *val_out);
 double oracle_cutoff_geom(double C0, double M, double m, double nu_min, double tau,
                           double absJ, double eps);
@@ -116,11 +116,11 @@ static void run(int d, int64_t nq, int64_t n, double eps) {
     int32_t *modal = (int32_t *)malloc(sizeof(int32_t) * (size_t)nq);
     for (int pass = 0; pass < 2; ++pass) {
         const uint8_t *kp = pass ? keep : NULL;
-        rc = oracle_plan_moments(d, nq, x, mu, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp, 2,
-                                 mass, first);
+        rc = oracle_plan_moments(d, nq, x, mu, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp,
+                                 pass ? 0.05 : INFINITY, 2, mass, first);
         printf("moments rc=%d mass0=%.15e\n", rc, mass[0]);
-        rc = oracle_transport_maps(d, nq, x, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp, 2, bary,
-                                   modal, mval);
+        rc = oracle_transport_maps(d, nq, x, n, y, nu, psi, eps, 0.5, tof, bof, nb, kp,
+                                   pass ? 0.05 : INFINITY, 2, bary, modal, mval);
         printf("maps rc=%d modal0=%d\n", rc, (int)modal[0]);
     }
     free(mass); free(first); free(bary); free(mval); free(modal);

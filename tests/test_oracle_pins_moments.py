@@ -128,3 +128,18 @@ def test_truncated_moments_follow_the_tile_rule():
     b0, mo0, _ = oracle.transport_maps(x, y, nu, psi, eps)
     np.testing.assert_array_equal(b1, b0)
     np.testing.assert_array_equal(mo1, mo0)
+
+
+def test_cutoff_moments_follow_the_truncated_gradient():
+    """With a cost cutoff C (Sec. 4.1) the moments' masses are the truncated
+    evaluation's gradient plus nu, and the maps see only pairs with c < C."""
+    x, mu, y, nu, psi = _problem(3, 91, n=30)
+    eps, C = 0.01, 0.08
+    r = oracle.dual_eval(x, mu, y, nu, psi, eps, cutoff=C)
+    assert r.nempty == 0 and r.kept < x.shape[0] * y.shape[0]
+    mass, _ = oracle.plan_moments(x, mu, y, nu, psi, eps, cutoff=C)
+    np.testing.assert_allclose(mass - nu, r.grad, rtol=0, atol=1e-15)
+    bary, modal, val = oracle.transport_maps(x, y, nu, psi, eps, cutoff=C)
+    c = 0.5 * cdist(x, y, "sqeuclidean")
+    V = np.where(c < C, psi[None, :] - c + eps * np.log(nu)[None, :], -np.inf)
+    np.testing.assert_array_equal(modal, np.argmax(V, axis=1))
