@@ -53,8 +53,11 @@ typedef enum {
  *        in FP32, per-point log-sum-exp, per-target sums and J in FP64. The
  *        FP32 exponential's per-term error (about 1e-7 relative) averages out
  *        over many points; a problem whose effective number of points
- *        (sum mu)^2 / sum mu^2 is below opt.fp64_below_points runs the FP64
- *        pair loop instead, so J stays within 1e-9 of the exact value.
+ *        (sum mu)^2 / sum mu^2 is below opt.fp64_below_points and whose pair
+ *        count is below 2^27 runs the FP64 pair loop instead, so J stays
+ *        within 1e-9 of the exact value. (A larger problem with concentrated
+ *        masses keeps the FP32 loop; its J error is about
+ *        1.5e-7 eps sum(mu) / sqrt(effective points).)
  * FP64 : everything in FP64 (software exp2). */
 typedef enum { RSOT_PREC_MIXED = 0, RSOT_PREC_FP64 = 1 } rsot_precision;
 
@@ -89,7 +92,8 @@ typedef struct {
                                  the device; truncated rules: 256)                     */
     int64_t mem_limit_bytes;  /* cap on library device memory; 0 = none            */
     int64_t fp64_below_points;/* MIXED: FP64 pair loop when (sum mu)^2 / sum mu^2 is
-                                 below this; default 16384; 0 = never               */
+                                 below this (and N_q N < 2^27); default 16384;
+                                 0 = never                                          */
 } rsot_options;
 
 typedef struct rsot_problem rsot_problem;
@@ -287,6 +291,45 @@ rsot_status rsot_get_partition(rsot_problem *p, int32_t *tile_of_point, int32_t 
 rsot_status rsot_softmax_refine(rsot_problem *p, double eps, const double *psi_coarse,
                                 int64_t n_fine, const double *y_fine, double *psi_fine_out);
 
+/*
+ * Target moments of the plan pi_qj = mu_q p_qj(psi) (Sec. 6.2), over the
+ * pairs of the problem's truncation rule:
+ *   mass_out[j]          = nu~_j = sum_q mu_q p_qj          (Eq. discretized_gradient + nu)
+ *   first_out[j*dim + k] = sum_q mu_q p_qj x_q[k]
+ * At the optimum first_j / nu_j is the conditional barycentre T_j of
+ * Eq. barycenter_fixed_point (the damped Lloyd step of Eq. damped_lloyd
+ * moves y_j towards it), and 2 cost_scale (nu~_j y_j - first_j) is Danskin's
+ * gradient of the transport cost in y_j (Eq. barycenter_gradient_general).
+ *   psi        DEVICE pointer, n_target doubles (caller order)
+ *   mass_out   DEVICE pointer, n_target doubles, or NULL
+ *   first_out  DEVICE pointer, n_target x dim doubles (row-major), or NULL
+ *              (not both NULL)
+ *   info       HOST pointer or NULL: the evaluation's statistics
+ *   kernel_ms  HOST pointer or NULL: device time of the moment kernels
+ * The call evaluates J at psi first (it leaves L_q for rsot_get_lse).
+ * Errors: INVALID_ARG, NONFINITE (psi), DEVICE, OOM.
+ */
+rsot_status rsot_plan_moments(rsot_problem *p, double eps, const double *psi, double *mass_out,
+                              double *first_out, rsot_eval_info *info, double *kernel_ms);
+
+/*
+ * Transport maps of the plan (Sec. 6.3), per quadrature point, over the pairs
+ * of the problem's truncation rule:
+ *   bary_out[q*dim + k] = sum_j p_qj y_j[k]        (Eq. barycentric_map_registration)
+ *   modal_out[q]        = argmax_j (psi_j - c_qj + eps ln nu_j), a target index
+ *                         in the caller's order   (Eq. modal_map_registration)
+ * The argmax is decided on FP64 exponents; where two targets tie to within
+ * FP64 rounding either may be returned. A point with no kept pair (pointwise
+ * rule) gets NaN and -1.
+ *   psi        DEVICE pointer, n_target doubles (caller order)
+ *   bary_out   DEVICE pointer, n_quad x dim doubles, or NULL
+ *   modal_out  DEVICE pointer, n_quad int32, or NULL (not both NULL)
+ *   info, kernel_ms as for rsot_plan_moments
+ * Errors: INVALID_ARG, NONFINITE (psi), DEVICE, OOM.
+ */
+rsot_status rsot_transport_maps(rsot_problem *p, double eps, const double *psi, double *bary_out,
+                                int32_t *modal_out, rsot_eval_info *info, double *kernel_ms);
+
 /* ------------------------------------------------------------------------ */
 /* Solver (Alg. 1): L-BFGS on J with an eps schedule (Sec. 4.2).            */
 /* ------------------------------------------------------------------------ */
@@ -302,6 +345,7 @@ typedef struct {
 
 /* Return nonzero to cancel the solve. */
 typedef int (*rsot_callback)(const rsot_iter_info *it, void *user);
+
 
 typedef struct {
     const double *eps_schedule; /* HOST array: eps_0 > ... > eps_final (Sec. 4.2)  */

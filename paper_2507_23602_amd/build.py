@@ -20,8 +20,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librsot.so")
 ARCH = os.environ.get("RSOT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["rsot_setup.hip", "rsot_eval.hip", "rsot_noalloc.hip", "rsot_solve.cpp",
-           "rsot_multilevel.cpp", "rsot_hierarchy.hip", "rsot_mlp.hip"]
+SOURCES = ["rsot_setup.hip", "rsot_eval.hip", "rsot_noalloc.hip", "rsot_moments.hip",
+           "rsot_solve.cpp", "rsot_multilevel.cpp", "rsot_hierarchy.hip", "rsot_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

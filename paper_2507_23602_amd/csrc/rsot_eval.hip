@@ -32,10 +32,8 @@
 
 #include "rsot_device.h"
 #include "rsot_internal.h"
+#include "rsot_pairs.h"
 
-#define RSOT_LN2 0.69314718055994530942
-#define RSOT_LOG2E 1.44269504088896340736
-#define CH 8   // pairs per chunk between FP64 flushes
 #define RSOT_SEG1_DEFAULT 256   // target blocks per objective-pass work item
 
 // v_exp_f32 is accurate to about 1 ulp, but its error has a nonzero mean over
@@ -48,52 +46,6 @@
 // ref_offset spreads the log-sum-exp references, so this holds by
 // construction even on uniform meshes, where the geometry alone would
 // cluster them. What remains is zero-mean and averages out over points.
-
-enum { MODE_DENSE = 0, MODE_LIST = 1, MODE_MASK = 2 };
-
-// Fractional offset in [0, 1) of the reference grid of element i (a point of
-// the objective pass, a tile of the gradient pass): successive elements step
-// by the golden ratio, so the offsets are spread evenly over any run of
-// elements. References are ceil(value - offset) + offset; rescaling a sum
-// between two references of one element is an exact power of two.
-__device__ __forceinline__ double ref_offset(int64_t i) {
-    const double v = (double)(i + 1) * 0.6180339887498949;
-    return v - floor(v);
-}
-
-// constant (read-only) address space: loads at uniform addresses through it
-// may use the scalar cache
-#define RSOT_CAS __attribute__((address_space(4)))
-
-__device__ __forceinline__ double4 ld4(const double4 *p) { return *p; }
-__device__ __forceinline__ double4 ld4(const RSOT_CAS double4 *p) {
-    const RSOT_CAS double *q = (const RSOT_CAS double *)p;
-    double4 r;
-    r.x = q[0];
-    r.y = q[1];
-    r.z = q[2];
-    r.w = q[3];
-    return r;
-}
-
-// Target record k of a block for the objective pass. 3D: the 32-byte
-// records {Y0, Y1, Y2, B}. 2D: the packed 24-byte copies {Y0, Y1, B}, so the
-// eight records of a chunk are 192 contiguous bytes that load as three
-// 64-byte scalar loads (the 32-byte records with their unused third
-// component would load as sixteen 8- and 16-byte pieces).
-template <int D, typename P>
-__device__ __forceinline__ double4 trec_at(P T, int k) {
-    if constexpr (D == 3) {
-        return ld4(T + k);
-    } else {
-        double4 r;
-        r.x = T[3 * k + 0];
-        r.y = T[3 * k + 1];
-        r.z = 0.0;
-        r.w = T[3 * k + 2];
-        return r;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // mean error of the FP32 exponential on this device
@@ -583,17 +535,6 @@ __global__ void k_item_keys(const int64_t *__restrict__ wi_range, const uint32_t
 // ---------------------------------------------------------------------------
 // objective pass
 // ---------------------------------------------------------------------------
-// The FP64 exponent t = B_j + x.Y_j of a (point, target) pair, always formed
-// in this order, so that the objective pass and the gradient pass take the
-// per-pair cutoff test t > G_j - A_q (c < C) on bitwise equal operands.
-template <int D>
-__device__ __forceinline__ double pair_exp(double x0, double x1, double x2, const double4 &r) {
-    double v = fma(x0, r.x, r.w);
-    v = fma(x1, r.y, v);
-    if (D == 3) v = fma(x2, r.z, v);
-    return v;
-}
-
 // Accumulates one 64-target block into the running (m, s) of this lane's
 // point: s = sum 2^(t_j - m). m is an online maximum on the grid
 // k + rq (k integer); when a chunk's max exceeds it, s is rescaled by an exact
@@ -1753,6 +1694,10 @@ static rsot_status plan_result(EvalPlan &e, bool timed_passes, double *J_out,
     if (e.dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
     p->last_eval_valid = 1;
     p->last_mode = e.mode;
+    p->last_n_wi = e.n_wi;
+    p->last_n_seg = e.n_seg;
+    p->last_seg = e.seg;
+    p->last_kcs = e.kcs;
     if (info) {
         const int rule = e.rule;
         info->total_pairs = p->nq * p->n;

@@ -145,6 +145,13 @@ struct rsot_problem {
     int have_D = 0;
     int last_eval_valid = 0;
     int last_mode = 0;           // pair-loop mode of the last evaluation (dense, list, mask)
+    // work decomposition of the last evaluation's gradient pass (the plan
+    // moments follow it): items, point segments per block and their length
+    int64_t last_n_wi = 0, last_n_seg = 1, last_seg = 1;
+    double last_kcs = 0.0;       // kappa * cost_scale of the last evaluation
+    double *mpart = nullptr;     // plan moments: per-item partial first moments
+    size_t mpart_cap = 0;
+    float *tyf = nullptr;        // transport maps: FP32 target coordinates {y0, y1, y2, 0}
     int64_t last_refine_pairs = 0;   // (tile, fine block) pairs x 64 x 64 of the last refinement
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // batched call

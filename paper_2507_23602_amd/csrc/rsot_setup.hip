@@ -679,10 +679,16 @@ extern "C" rsot_status rsot_set_precision(rsot_problem *p, int precision) {
     return RSOT_OK;
 }
 
+// MIXED problems run the FP64 pair loop when both their effective number of
+// points is below opt.fp64_below_points (too few for the FP32 exponentials'
+// per-point errors to average below 1e-9 of J) and their pair count is below
+// 2^27 (where the FP64 loop costs well under a millisecond). Larger problems
+// with concentrated masses keep the FP32 loop: there the error of J is the
+// per-point one averaged over n_eff points, 1.5e-7 eps sum(mu) / sqrt(n_eff).
 bool rsot_pairs_fp64(const rsot_problem *p) {
     if (p->opt.precision == RSOT_PREC_FP64) return true;
     const double n_eff = p->sum_mu2 > 0.0 ? p->sum_mu * p->sum_mu / p->sum_mu2 : 0.0;
-    return n_eff < (double)p->opt.fp64_below_points;
+    return n_eff < (double)p->opt.fp64_below_points && (double)p->nq * (double)p->n < 0x1p27;
 }
 
 extern "C" rsot_status rsot_set_reference(rsot_problem *p, double absJ_ref) {

@@ -95,6 +95,7 @@ class SolveParams(ctypes.Structure):
                 ("cancel", ctypes.POINTER(ctypes.c_int)), ("absJ_start", ctypes.c_double)]
 
 
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int),
                 ("stages", ctypes.c_int), ("J", ctypes.c_double), ("grad_l1", ctypes.c_double),
@@ -178,6 +179,9 @@ SIGNATURES = {
     "rsot_covering_cost": (_I, [_P, ctypes.POINTER(_D)]),
     "rsot_get_partition": (_I, [_P, _P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "rsot_softmax_refine": (_I, [_P, _D, _P, _I64, _P, _P]),
+    "rsot_plan_moments": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(EvalInfo), ctypes.POINTER(_D)]),
+    "rsot_transport_maps": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(EvalInfo),
+                                 ctypes.POINTER(_D)]),
     "rsot_solve_params_default": (None, [ctypes.POINTER(SolveParams)]),
     "rsot_target_hierarchy": (_I, [_I, _I64, _P, _P, _I, ctypes.POINTER(_I64), _I, ctypes.c_uint64,
                                    _P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
@@ -421,6 +425,34 @@ class Problem:
                                                   yf.data_ptr(), out.data_ptr()),
                "rsot_softmax_refine")
         return out
+
+    def plan_moments(self, psi, eps):
+        """rsot_plan_moments: (nu~ (N,), first moments (N, dim), info, kernel ms)
+        as CUDA float64 tensors."""
+        torch = _torch()
+        pt = _dev_f64(psi, self.n)
+        mass = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        first = torch.empty((self.n, self.dim), dtype=torch.float64, device="cuda")
+        info, ms = EvalInfo(), _D(0.0)
+        _check(load_library().rsot_plan_moments(self._h, float(eps), pt.data_ptr(),
+                                                mass.data_ptr(), first.data_ptr(),
+                                                ctypes.byref(info), ctypes.byref(ms)),
+               "rsot_plan_moments")
+        return mass, first, info.as_dict(), ms.value
+
+    def transport_maps(self, psi, eps):
+        """rsot_transport_maps: (barycentric map (nq, dim), modal target index
+        (nq,) int32, info, kernel ms) as CUDA tensors."""
+        torch = _torch()
+        pt = _dev_f64(psi, self.n)
+        bary = torch.empty((self.nq, self.dim), dtype=torch.float64, device="cuda")
+        modal = torch.empty(self.nq, dtype=torch.int32, device="cuda")
+        info, ms = EvalInfo(), _D(0.0)
+        _check(load_library().rsot_transport_maps(self._h, float(eps), pt.data_ptr(),
+                                                  bary.data_ptr(), modal.data_ptr(),
+                                                  ctypes.byref(info), ctypes.byref(ms)),
+               "rsot_transport_maps")
+        return bary, modal, info.as_dict(), ms.value
 
     def covering_cost(self) -> float:
         c = _D(0.0)
