@@ -346,6 +346,24 @@ typedef struct {
 /* Return nonzero to cancel the solve. */
 typedef int (*rsot_callback)(const rsot_iter_info *it, void *user);
 
+/*
+ * Solver state to resume from: the eps stage (Sec. 4.2), the accepted
+ * iterations done in it, the L-BFGS history of Alg. 1's quasi-Newton step and
+ * the |J| reference of the truncation rules. Together with the returned
+ * potential it continues a stopped solve exactly where it stopped. The
+ * caller owns every buffer.
+ */
+typedef struct {
+    int64_t n_target;         /* length of the potential the pairs belong to      */
+    int capacity;             /* pairs the buffers hold (lbfgs_m keeps them all)  */
+    double *s, *y;            /* HOST: capacity x n_target doubles each; pair i   */
+                              /* at offset i * n_target, oldest first             */
+    int n_pairs;              /* pairs held (<= capacity)                          */
+    int stage;                /* eps stage the solve was in                        */
+    int iteration;            /* accepted iterations done in that stage            */
+    double absJ_ref;          /* |J| reference of the truncation rules             */
+    int valid;                /* 1 once a solve has written the state              */
+} rsot_checkpoint;
 
 typedef struct {
     const double *eps_schedule; /* HOST array: eps_0 > ... > eps_final (Sec. 4.2)  */
@@ -365,6 +383,12 @@ typedef struct {
                                    accepted iterate, and each eps stage starts
                                    from the previous stage's); 0 = evaluate the
                                    warm start densely to obtain it; >= 0      */
+    rsot_checkpoint *checkpoint;/* NULL, or written on every exit of the solve   */
+    int resume;                 /* 1: continue from *checkpoint (stage, history,
+                                   |J| reference) and psi_inout                 */
+    int test_flip_gradient;     /* test hook, 0 in use: the solver sees -grad, so
+                                   no step decreases J and the first line search
+                                   ends with RSOT_ERR_LINESEARCH                 */
 } rsot_solve_params;
 
 typedef struct {
@@ -390,7 +414,12 @@ void rsot_solve_params_default(rsot_solve_params *sp);
  *   psi_inout HOST pointer, n_target doubles: warm start in (zeros allowed),
  *             solution out, centred so that sum_j nu_j psi_j = 0
  *             (App. A: the minimiser is unique up to a constant).
- * Errors: INVALID_ARG, UNBALANCED, NONFINITE, LINESEARCH, NOT_CONVERGED,
+ * With sp->checkpoint the solver state is written on every exit; with
+ * sp->resume the solve continues from it (its stage, its L-BFGS pairs, its
+ * |J| reference, its iteration count against max_iter) at psi_inout, which
+ * must be the potential that solve returned.
+ * Errors: INVALID_ARG (also: resume without a valid checkpoint of this size
+ * and schedule), UNBALANCED, NONFINITE, LINESEARCH, NOT_CONVERGED,
  * CANCELLED, DEVICE; psi_inout and info hold the best accepted iterate.
  */
 rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp, double *psi_inout,
@@ -481,6 +510,8 @@ typedef struct {
  * potential is transferred by softmax refinement at the eps of the last
  * stage of step l-1 (Eq. softmax_refinement_formula_combined), otherwise it is
  * kept. psi_out: HOST pointer, n_target of the finest level, centred.
+ * mp->base must carry no checkpoint and no resume (INVALID_ARG): the levels
+ * differ in size.
  */
 rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_params *mp, double *psi_out,
                                   rsot_ml_info *info);

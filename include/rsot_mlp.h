@@ -122,7 +122,8 @@ typedef struct {
  * psi = 0. If it is finite and gives the lower J, the solve runs at that eps
  * alone from the prediction; otherwise it runs sp's whole schedule from
  * zero. psi_out HOST n doubles (centred solution); info and linfo may be
- * NULL. Errors as rsot_solve.
+ * NULL. sp->checkpoint is written as in rsot_solve; sp->resume is rejected
+ * (INVALID_ARG): the start is the prediction. Errors as rsot_solve.
  */
 rsot_status rsot_solve_learned(rsot_problem *p, rsot_mlp *m, const double *cond,
                                const rsot_solve_params *sp, double *psi_out, rsot_solve_info *info,

@@ -1235,6 +1235,7 @@ extern "C" rsot_status rsot_solve_learned(rsot_problem *p, rsot_mlp *m, const do
                                           rsot_solve_info *info, rsot_learned_info *linfo) {
     if (!p || !m || !cond || !sp || !psi_out || !sp->eps_schedule || sp->n_eps < 1)
         return RSOT_ERR_INVALID_ARG;
+    if (sp->resume) return RSOT_ERR_INVALID_ARG;   // the start is the network's, not a checkpoint
     if (p->dim != 2 || !(cond[3] > 0.0) || !std::isfinite(cond[3])) return RSOT_ERR_INVALID_ARG;
     const double eps_f = sp->eps_schedule[sp->n_eps - 1];
     if (!(eps_f > 0.0) || !std::isfinite(eps_f)) return RSOT_ERR_INVALID_ARG;

@@ -125,6 +125,7 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
                                              double *psi_out, rsot_ml_info *info) {
     if (!ml || !mp || !psi_out || !mp->eps || !mp->level || mp->n_stages < 1)
         return RSOT_ERR_INVALID_ARG;
+    if (mp->base.checkpoint || mp->base.resume) return RSOT_ERR_INVALID_ARG;  // per level n differs
     const int ns = (int)ml->nq.size(), nt = (int)ml->nt.size();
     const int Lmax = std::max(ns, nt) - 1;
     for (int k = 0; k < mp->n_stages; ++k) {

@@ -124,6 +124,7 @@ struct Evaluator {
     rsot_problem *p;
     Par *par;
     double eps;
+    bool flip = false;           // test hook: hand the solver -grad
     int evals = 0;
     double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept = 0.0;
     volatile int *cancel = nullptr;
@@ -143,6 +144,8 @@ struct Evaluator {
         RSOT_HIP(hipStreamSynchronize(p->stream));
         par->chunks(n, [&](size_t a, size_t b) {
             std::memcpy(g.data() + a, p->hgrad + a, (b - a) * sizeof(double));
+            if (flip)
+                for (size_t i = a; i < b; ++i) g[i] = -g[i];
         });
         ++evals;
         eval_ms += last.kernel_ms;
@@ -303,6 +306,14 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
             return RSOT_ERR_INVALID_ARG;
     if (std::fabs(p->sum_mu - p->sum_nu) > 1e-12 * p->sum_nu) return RSOT_ERR_UNBALANCED;
     const size_t n = (size_t)p->n;
+    rsot_checkpoint *ck = sp.checkpoint;
+    if (ck && (ck->n_target != (int64_t)n || ck->capacity < 0 ||
+               (ck->capacity > 0 && (!ck->s || !ck->y))))
+        return RSOT_ERR_INVALID_ARG;
+    if (sp.resume && (!ck || !ck->valid || ck->stage < 0 || ck->stage >= sp.n_eps ||
+                      ck->n_pairs < 0 || ck->n_pairs > ck->capacity || ck->iteration < 0 ||
+                      !(ck->absJ_ref >= 0.0)))
+        return RSOT_ERR_INVALID_ARG;
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(psi_inout[i])) return RSOT_ERR_NONFINITE;
 
@@ -314,8 +325,25 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
     double J = 0.0;
     double eval_ms = 0.0, cull_ms = 0.0, p1_ms = 0.0, p2_ms = 0.0, kept_sum = 0.0;
     int total_it = 0, total_ev = 0;
+    // L-BFGS memory of the current stage, and where the solve stands
+    std::vector<std::vector<double>> S, Y;
+    std::vector<double> rho;
+    int cur_stage = sp.resume ? ck->stage : 0, cur_it = 0;
 
     auto finish = [&](rsot_status st) {
+        if (ck) {
+            const int keep = std::min<int>((int)S.size(), ck->capacity);
+            const int first = (int)S.size() - keep;
+            for (int i = 0; i < keep; ++i) {
+                std::memcpy(ck->s + (size_t)i * n, S[first + i].data(), n * sizeof(double));
+                std::memcpy(ck->y + (size_t)i * n, Y[first + i].data(), n * sizeof(double));
+            }
+            ck->n_pairs = keep;
+            ck->stage = cur_stage;
+            ck->iteration = cur_it;
+            ck->absJ_ref = p->absJ_ref;
+            ck->valid = 1;
+        }
         std::memcpy(psi_inout, psi.data(), n * sizeof(double));
         inf.iterations = total_it;
         inf.evaluations = total_ev;
@@ -331,9 +359,16 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         return st;
     };
 
-    for (int stage = 0; stage < sp.n_eps; ++stage) {
+    for (int stage = cur_stage; stage < sp.n_eps; ++stage) {
         Evaluator ev{p, &par, sp.eps_schedule[stage]};
         ev.cancel = sp.cancel;
+        ev.flip = sp.test_flip_gradient != 0;
+        const bool resumed = sp.resume && stage == ck->stage;
+        cur_stage = stage;
+        S.clear();
+        Y.clear();
+        rho.clear();
+        cur_it = 0;
         const bool final_stage = stage == sp.n_eps - 1;
         const double tol = (!final_stage && sp.stage_tol > 0.0) ? sp.stage_tol : sp.tol;
         // |J| reference of the truncation rules: for the first stage the
@@ -341,7 +376,8 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
         // later ones the last accepted iterate's, which the previous stage
         // left (the new stage's warm start is that iterate). D of the INT
         // rule depends on eps and is taken afresh.
-        if (stage == 0) p->absJ_ref = sp.absJ_start;
+        if (resumed) p->absJ_ref = ck->absJ_ref;
+        else if (stage == 0) p->absJ_ref = sp.absJ_start;
         p->have_D = 0;
         rsot_status s = ev(psi, J, g);
         if (s != RSOT_OK) {
@@ -354,9 +390,24 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
             return finish(s);
         }
         double gl1 = ev.last.grad_l1, glinf = ev.last.grad_linf;
-        std::vector<std::vector<double>> S, Y;
-        std::vector<double> rho, sv, yv;
+        std::vector<double> sv, yv;
         int it = 0;
+        if (resumed) {              // the stopped solve's history and count
+            for (int i = 0; i < ck->n_pairs; ++i) {
+                S.emplace_back(ck->s + (size_t)i * n, ck->s + (size_t)(i + 1) * n);
+                Y.emplace_back(ck->y + (size_t)i * n, ck->y + (size_t)(i + 1) * n);
+                const double sy = par.dot(S.back(), Y.back());
+                if (!(sy > 1e-300)) return finish(RSOT_ERR_INVALID_ARG);
+                rho.push_back(1.0 / sy);
+            }
+            while ((int)S.size() > sp.lbfgs_m) {
+                S.erase(S.begin());
+                Y.erase(Y.begin());
+                rho.erase(rho.begin());
+            }
+            it = ck->iteration;
+        }
+        cur_it = it;
         rsot_status st = RSOT_OK;
         while (gl1 > tol) {
             if (it >= sp.max_iter) {
@@ -446,6 +497,7 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
             gl1 = np.gl1;
             glinf = np.glinf;
             ++it;
+            cur_it = it;
             if (sp.callback) {
                 rsot_iter_info ii{};
                 ii.stage = stage;

@@ -86,14 +86,43 @@ class IterInfo(ctypes.Structure):
 CALLBACK = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(IterInfo), ctypes.c_void_p)
 
 
+class CheckpointStruct(ctypes.Structure):
+    _fields_ = [("n_target", ctypes.c_int64), ("capacity", ctypes.c_int),
+                ("s", ctypes.POINTER(ctypes.c_double)), ("y", ctypes.POINTER(ctypes.c_double)),
+                ("n_pairs", ctypes.c_int), ("stage", ctypes.c_int), ("iteration", ctypes.c_int),
+                ("absJ_ref", ctypes.c_double), ("valid", ctypes.c_int)]
+
+
 class SolveParams(ctypes.Structure):
     _fields_ = [("eps_schedule", ctypes.POINTER(ctypes.c_double)), ("n_eps", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("lbfgs_m", ctypes.c_int), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("max_ls", ctypes.c_int), ("stage_tol", ctypes.c_double),
                 ("callback", CALLBACK), ("user", ctypes.c_void_p),
-                ("cancel", ctypes.POINTER(ctypes.c_int)), ("absJ_start", ctypes.c_double)]
+                ("cancel", ctypes.POINTER(ctypes.c_int)), ("absJ_start", ctypes.c_double),
+                ("checkpoint", ctypes.POINTER(CheckpointStruct)), ("resume", ctypes.c_int),
+                ("test_flip_gradient", ctypes.c_int)]
 
+
+class Checkpoint:
+    """Host buffers of an rsot_checkpoint: the solver state (eps stage,
+    iterations in it, L-BFGS pairs, |J| reference) a stopped solve leaves,
+    which a later solve resumes from together with the returned potential."""
+
+    def __init__(self, n_target, capacity=10):
+        self.s = np.zeros((capacity, n_target))
+        self.y = np.zeros((capacity, n_target))
+        self.c = CheckpointStruct()
+        self.c.n_target = n_target
+        self.c.capacity = capacity
+        self.c.s = self.s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.c.y = self.y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def as_dict(self):
+        k = self.c.n_pairs
+        return dict(valid=self.c.valid, stage=self.c.stage, iteration=self.c.iteration,
+                    n_pairs=k, absJ_ref=self.c.absJ_ref, s=self.s[:k].copy(),
+                    y=self.y[:k].copy())
 
 
 class SolveInfo(ctypes.Structure):
@@ -491,15 +520,23 @@ class Problem:
         return sp, cb
 
     def solve(self, eps_schedule, psi0=None, tol=1e-6, max_iter=10000, lbfgs_m=10,
-              stage_tol=0.0, callback=None, max_ls=20, absJ_start=0.0):
+              stage_tol=0.0, callback=None, max_ls=20, absJ_start=0.0, checkpoint=None,
+              resume=False, test_flip_gradient=False):
         """rsot_solve: returns (psi numpy array, info dict). Raises on error
         codes other than NOT_CONVERGED (reported in info['status']).
         ``absJ_start``: |J| reference of the truncation rules for the first
-        evaluation (0: that evaluation runs dense to obtain it)."""
+        evaluation (0: that evaluation runs dense to obtain it).
+        ``checkpoint``: a Checkpoint the solver state is written to on exit;
+        with ``resume`` the solve continues from it at ``psi0``.
+        ``test_flip_gradient``: test hook, the solver is handed -grad."""
         eps_arr = np.ascontiguousarray(np.atleast_1d(eps_schedule), dtype=np.float64)
         psi = np.zeros(self.n) if psi0 is None else np.array(psi0, dtype=np.float64)
         sp, _keep = self._solve_params(eps_arr, tol, max_iter, lbfgs_m, stage_tol, callback,
                                        max_ls, absJ_start)
+        if checkpoint is not None:
+            sp.checkpoint = ctypes.pointer(checkpoint.c)
+        sp.resume = int(bool(resume))
+        sp.test_flip_gradient = int(bool(test_flip_gradient))
         info = SolveInfo()
         rc = load_library().rsot_solve(self._h, ctypes.byref(sp), psi.ctypes.data,
                                        ctypes.byref(info))

@@ -182,6 +182,79 @@ def test_cancel_and_resume_from_the_returned_iterate():
     assert err_psi < 1e-5 * p.eps * p.n ** 0.5
 
 
+def test_checkpoint_resume_continues_the_iteration():
+    """With a checkpoint the stopped solve leaves its stage, iteration count,
+    L-BFGS pairs and |J| reference; resumed from it (and the returned
+    potential) the solve takes the same steps as the uninterrupted one: the
+    J of every later iteration agrees, and the iteration counts add up."""
+    from paper_2507_23602_amd import rsot
+    _say("checkpoint + resume")
+    p = W.square_uniform(16, 64, seed=3, eps=2.5e-3)
+    prob = rsot.Problem(p.x, p.mu, p.y, p.nu, precision="fp64")
+    sched = [0.04, 0.02, 0.01, 0.005, 0.0025]
+    trace_ref = []
+
+    def rec(into):
+        def cb(it):
+            into.append((it.stage, it.iteration, it.J))
+            return 0
+        return cb
+
+    ref, info_ref = prob.solve(sched, tol=1e-9, stage_tol=1e-6, callback=rec(trace_ref))
+    assert info_ref["status"] == rsot.OK
+    ck = rsot.Checkpoint(p.n, capacity=10)
+
+    def stop(it):
+        return it.stage == 2 and it.iteration == 4
+
+    with pytest.raises(rsot.RsotError) as e:
+        prob.solve(sched, tol=1e-9, stage_tol=1e-6, callback=stop, checkpoint=ck)
+    assert e.value.code == rsot.ERR_CANCELLED
+    d = ck.as_dict()
+    _say(f"  checkpoint: stage {d['stage']} it {d['iteration']} pairs {d['n_pairs']} "
+         f"|J|ref {d['absJ_ref']:.6e}")
+    assert d["valid"] == 1 and d["stage"] == 2 and d["iteration"] == 4
+    assert 1 <= d["n_pairs"] <= 4
+    assert np.all(np.einsum("ij,ij->i", d["s"], d["y"]) > 0)   # curvature pairs
+    trace = []
+    psi, info = prob.solve(sched, psi0=e.value.psi, tol=1e-9, stage_tol=1e-6,
+                           callback=rec(trace), checkpoint=ck, resume=True)
+    assert info["status"] == rsot.OK
+    later = [t for t in trace_ref if (t[0], t[1]) > (2, 4)]
+    _say(f"  resumed: {len(trace)} iterations, uninterrupted after the stop: {len(later)}")
+    assert [t[:2] for t in trace] == [t[:2] for t in later]
+    for a, b in zip(trace, later):
+        assert abs(a[2] - b[2]) <= 1e-11 * abs(b[2])
+    assert np.max(np.abs(psi - ref)) < 1e-7 * p.eps * p.n ** 0.5
+    d2 = ck.as_dict()
+    assert d2["stage"] == len(sched) - 1 and d2["valid"] == 1
+    # resume asks for a checkpoint written by a solve of this size
+    with pytest.raises(rsot.RsotError) as e2:
+        prob.solve(sched, resume=True, checkpoint=rsot.Checkpoint(p.n, 10))
+    assert e2.value.code == rsot.ERR_INVALID_ARG
+    with pytest.raises(rsot.RsotError) as e3:
+        prob.solve(sched, checkpoint=rsot.Checkpoint(p.n + 1, 10))
+    assert e3.value.code == rsot.ERR_INVALID_ARG
+
+
+def test_flipped_gradient_ends_with_line_search_error():
+    """Failure detection: handed -grad (a host-side test hook), no step
+    decreases J, so the first line search gives up after max_ls evaluations
+    with RSOT_ERR_LINESEARCH and the start is returned unchanged."""
+    from paper_2507_23602_amd import rsot
+    _say("flipped gradient -> line-search error")
+    p = W.config1()
+    prob = rsot.Problem(p.x, p.mu, p.y, p.nu, precision="fp64")
+    with pytest.raises(rsot.RsotError) as e:
+        prob.solve([p.eps], tol=1e-9, max_ls=8, test_flip_gradient=True)
+    err = e.value
+    _say(f"  status {err.code}, {err.info['iterations']} it, {err.info['evaluations']} evals")
+    assert err.code == rsot.ERR_LINESEARCH
+    assert err.info["iterations"] == 0
+    assert err.info["evaluations"] <= 2 + 8
+    assert np.all(err.psi == 0.0)
+
+
 def test_line_search_failure_ends_the_solve():
     """Asked for a gradient norm below what FP64 can resolve, the solve must
     end (line-search failure at the noise floor, or the iteration cap), not
