@@ -1,4 +1,4 @@
-"""GPU tests of the batched evaluation (one launch per pass)."""
+"""GPU tests of the batched evaluation (one launch per pass) and of the\nautotuner's work granularities."""
 import sys
 
 import numpy as np
@@ -7,7 +7,12 @@ import pytest
 import oracle
 from paper_2507_23602_amd import workloads as W
 
+
 pytestmark = pytest.mark.gpu
+
+
+def grad_err(g, gref, nu):
+    return float(np.max(np.abs(g - gref) / (nu + (gref + nu))))
 
 
 def _say(*a):
@@ -99,6 +104,51 @@ def test_autotune_choice_is_valid_and_equivalent():
     assert abs(r2.J - r1.J) <= 1e-9 * abs(r1.J)
     g1, g2 = r1.grad.cpu().numpy(), r2.grad.cpu().numpy()
     assert np.max(np.abs(g1 - g2) / (p.nu + g1 + p.nu)) < 1e-6
+
+
+@pytest.mark.parametrize("rule", ["dense", "tile"])
+def test_autotune_candidates_against_oracle(rule):
+    """Every work granularity the autotuner may choose, on a 98,304 x 8,192
+    problem: the evaluation under each (objective-pass segment x gradient-pass
+    segment) equals the oracle's (J 1e-9, e_g 1e-6) with the same kept pairs,
+    and the tuner's own choice is one of them and is kept by the problem."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    _say(f"autotune candidates vs oracle, {rule}")
+    p = W.cube_mixture(16, 8192, 2e-3)
+    assert p.nq == 98304 and p.n == 8192
+    psi = W.random_psi(5, p.n, p.eps)
+    pt = torch.as_tensor(psi, device="cuda")
+    dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    tau = 1e-10
+    pr = rsot.Problem(p.x, p.mu, p.y, p.nu, truncation=rule, tau=tau)
+    pr.set_reference(abs(dense.J))
+    if rule == "tile":
+        tile_of, block_of, nt, nb = (v.cpu().numpy() if hasattr(v, "cpu") else v
+                                     for v in pr.partition())
+        ref = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, block_of, nb,
+                                    tau, abs(dense.J))
+    else:
+        ref = dense
+    res = pr.autotune(pt, p.eps, reps=1)
+    _say(f"  tuner: {res}")
+    chosen = pr.dual_eval(pt, p.eps)
+    worst_j = worst_g = 0.0
+    n_cfg = 0
+    for sb in (0, 64, 128, 256, 512, 1024):
+        for st in (0, 16, 32, 64, 128, 256, 512, 1024, 4096):
+            pr.set_tuning(sb, st)
+            r = pr.dual_eval(pt, p.eps)
+            assert r.info["kept_pairs"] == ref.kept, (sb, st)
+            ej = abs(r.J - ref.J) / abs(ref.J)
+            eg = grad_err(r.grad.cpu().numpy(), ref.grad, p.nu)
+            worst_j, worst_g = max(worst_j, ej), max(worst_g, eg)
+            assert ej <= 1e-9 and eg <= 1e-6, (sb, st, ej, eg)
+            if (sb, st) == (res["seg_blocks"], res["seg_tiles"]):
+                assert r.J == chosen.J
+                assert torch.equal(r.grad, chosen.grad)
+            n_cfg += 1
+    _say(f"  {n_cfg} configurations: worst J {worst_j:.2e}, worst e_g {worst_g:.2e}")
 
 
 def test_batched_full_size_smallest_instances_against_oracle():
