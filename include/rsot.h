@@ -94,6 +94,14 @@ typedef struct {
     int64_t fp64_below_points;/* MIXED: FP64 pair loop when (sum mu)^2 / sum mu^2 is
                                  below this (and N_q N < 2^27); default 16384;
                                  0 = never                                          */
+    int64_t tile_group;       /* TILE: targets per culling group, 8, 16, 32 or 64
+                                 (the rule decides per (point tile, group) pair;
+                                 the passes still run 64-target blocks, skipping
+                                 the dropped groups' 8-target chunks); 0 = default
+                                 (64). Finer groups have tighter bounds but each
+                                 gets a smaller share of the budget tau |J|, so
+                                 which keeps fewer pairs depends on the problem:
+                                 rsot_autotune picks it                             */
 } rsot_options;
 
 typedef struct rsot_problem rsot_problem;
@@ -217,22 +225,25 @@ rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, const double 
                                    double *batch_ms);
 
 /*
- * Autotuner: picks the work granularity of both passes for this problem by
- * timing evaluations at (eps, psi): objective-pass segment in
- * {64,128,256,512,1024} target blocks, then gradient-pass segment in
+ * Autotuner: picks the granularity of the culling and of both passes for
+ * this problem by timing evaluations at (eps, psi): under the TILE rule first
+ * the culling group in {64, 32, 16, 8} targets (finer groups keep fewer
+ * pairs and cost more culling), then the objective-pass segment in
+ * {64,128,256,512,1024} target blocks, then the gradient-pass segment in
  * {16,...,4096} point tiles (0 = library default), each the best of `reps`
- * device timings. The problem keeps the fastest pair.
+ * device timings. The problem keeps the fastest triple.
  *   psi             DEVICE pointer (n_target doubles)
- *   seg_*_out       HOST, chosen values (0 = default); may be NULL
+ *   seg_*_out, tile_group_out  HOST, chosen values (0 = default); may be NULL
  *   best_ms_out     HOST, time of the chosen configuration; may be NULL
  *   default_ms_out  HOST, time of the default configuration; may be NULL
  */
 rsot_status rsot_autotune(rsot_problem *p, double eps, const double *psi, int reps,
-                          int *seg_blocks_out, int *seg_tiles_out, double *best_ms_out,
-                          double *default_ms_out);
+                          int *seg_blocks_out, int *seg_tiles_out, int *tile_group_out,
+                          double *best_ms_out, double *default_ms_out);
 
-/* Sets the work granularity directly (e.g. from a cache of autotuner results). */
-rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles);
+/* Sets the granularities directly (e.g. from a cache of autotuner results);
+ * tile_group 0, 8, 16, 32 or 64 (else INVALID_ARG). */
+rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles, int tile_group);
 
 /*
  * Per-point log-sum-exp L_q = ln sum_j nu_j exp((psi_j - c_qj)/eps) of the
@@ -245,7 +256,8 @@ rsot_status rsot_get_lse(rsot_problem *p, double *L_out);
  * Size of the kept set I_q of every point in the last evaluation: the number
  * of targets whose terms entered the point's sum (Sec. 4.1: I_q = {j : c_qj <
  * C} under the cutoff rules; N under DENSE; under TILE the targets of the
- * blocks kept for the point's tile). A point dropped for an empty set has 0.
+ * blocks, or groups, kept for the point's tile). A point dropped for an empty
+ * set has 0.
  *   counts_out  DEVICE pointer, n_quad int32 in the caller's point order
  * Errors: INVALID_ARG (NULL, or no evaluation yet), DEVICE.
  */
@@ -254,12 +266,34 @@ rsot_status rsot_get_kept_counts(rsot_problem *p, int32_t *counts_out);
 /*
  * Culling decision of the last evaluation for every (point tile, target
  * block) pair of rsot_get_partition's grouping, row-major by tile:
- * 0 = skipped, 1 = kept with the per-pair test c < C (cutoff rules),
- * 2 = every pair kept (DENSE: all 2; TILE: 0 or 2).
+ * 0 = skipped, 1 = kept in part (cutoff rules: with the per-pair test
+ * c < C; TILE with culling groups below 64: some of the block's groups
+ * dropped, see rsot_get_tile_chunk_keep), 2 = every pair kept (DENSE: all 2).
  *   keep_out  DEVICE pointer, n_tiles * n_blocks bytes
  * Errors: INVALID_ARG (NULL, or no evaluation yet), DEVICE.
  */
 rsot_status rsot_get_tile_keep(rsot_problem *p, uint8_t *keep_out);
+
+/*
+ * The same at the granularity of 8-target chunks: per (tile, block) a byte
+ * whose bit c is set when the pairs of the block's targets 8c..8c+7 (in
+ * rsot_get_target_slots order) entered the last evaluation: all of them
+ * under DENSE and TILE; under the cutoff rules the chunk was not skipped and
+ * its pairs took the test c < C. Bits of chunks holding only padding may be
+ * set.
+ *   mask_out  DEVICE pointer, n_tiles * n_blocks bytes, row-major by tile
+ * Errors: INVALID_ARG (NULL, or no evaluation yet), DEVICE.
+ */
+rsot_status rsot_get_tile_chunk_keep(rsot_problem *p, uint8_t *mask_out);
+
+/*
+ * Position of every target in the library's sorted, padded target order:
+ * target i sits in block slot[i] / 64, chunk slot[i] / 8, culling group
+ * slot[i] / tile_group.
+ *   slot_out  DEVICE pointer, n_target int32 (caller order)
+ * Errors: INVALID_ARG, DEVICE.
+ */
+rsot_status rsot_get_target_slots(rsot_problem *p, int32_t *slot_out);
 
 /*
  * Covering cost C_0 = max_q min_j c(x_q, y_j) (Sec. 4.1 / App. B, maximum

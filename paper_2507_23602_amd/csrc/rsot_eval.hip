@@ -153,6 +153,40 @@ __global__ void k_target_G(const double *__restrict__ tpsi, const double *__rest
     tG[j] = tperm[j] >= 0 ? kappa * (tpsi[j] - C) + tlog2nu[j] : INFINITY;
 }
 
+// Tile rule with culling groups of g targets (8, 16 or 32; g divides the
+// 64-target block): per group the box of its real targets, ln nu(G) and the
+// largest finite psi, the inputs of its bound ln U_TG. A group without a real
+// target gets ln nu = -inf (never kept) and the box of its first record.
+__global__ void k_group_tables(const double *__restrict__ ty, const double *__restrict__ tnu,
+                               const double *__restrict__ tpsi, const int32_t *__restrict__ tperm,
+                               int64_t n_groups, int g, double *__restrict__ lo,
+                               double *__restrict__ hi, double *__restrict__ lnnu,
+                               double *__restrict__ psimax) {
+    const int64_t G = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (G >= n_groups) return;
+    double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double nu = 0.0, pm = -INFINITY;
+    for (int i = 0; i < g; ++i) {
+        const int64_t j = G * g + i;
+        if (tperm[j] < 0) continue;
+        for (int k = 0; k < 3; ++k) {
+            l[k] = fmin(l[k], ty[j * 3 + k]);
+            h[k] = fmax(h[k], ty[j * 3 + k]);
+        }
+        nu += tnu[j];
+        const double ps = tpsi[j];
+        if (isfinite(ps)) pm = fmax(pm, ps);
+    }
+    if (!(nu > 0.0))
+        for (int k = 0; k < 3; ++k) l[k] = h[k] = ty[G * g * 3 + k];
+    for (int k = 0; k < 3; ++k) {
+        lo[G * 3 + k] = l[k];
+        hi[G * 3 + k] = h[k];
+    }
+    lnnu[G] = nu > 0.0 ? log(nu) : -INFINITY;
+    psimax[G] = pm;
+}
+
 // Single workgroup: psi statistics and the cutoff of the T1 rules.
 //   GEOM (Eq. truncation_cutoff_geom): C0 + (M - m) + eps ln(eps/(nu_min tau |J|)), >= C0
 //   INT  (Eq. truncation_cutoff_int):  M + eps ln(eps D/(tau |J|)), >= C0
@@ -329,6 +363,166 @@ __global__ __launch_bounds__(256) void k_tile_ref(
     }
 }
 
+// ln nu + v / eps > th, decided exactly as written (the division rounded
+// once, then the sum) but with the division only where a product with 1/eps
+// lands within a rounding band of the threshold
+__device__ __forceinline__ bool bound_above(double lnnu, double v, double eps, double inv_eps,
+                                            double th) {
+    const double q = v * inv_eps;
+    const double a = lnnu + q;
+    const double band = 1e-12 * (fabs(q) + fabs(lnnu) + fabs(th) + 1.0);
+    if (a > th + band) return true;
+    if (a < th - band) return false;
+    return lnnu + v / eps > th;
+}
+
+// ln U_TG of a culling group (the same bound with the group's tables)
+template <int D>
+__device__ __forceinline__ double grp_lnU(const double *__restrict__ tile_lo,
+                                          const double *__restrict__ tile_hi,
+                                          const double *__restrict__ glo,
+                                          const double *__restrict__ ghi,
+                                          const double *__restrict__ glnnu,
+                                          const double *__restrict__ gpsi, int64_t t, int64_t G,
+                                          double cs, double eps) {
+    double dmin2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double g = box_gap(tile_lo[t * 3 + k], tile_hi[t * 3 + k], glo[G * 3 + k],
+                                 ghi[G * 3 + k]);
+        dmin2 += g * g;
+    }
+    return glnnu[G] + (gpsi[G] - cs * dmin2) / eps;
+}
+
+// The tile rule over groups of g targets instead of blocks: G* = argmax_G
+// ln U_TG (lowest index on ties), ln L_T over the targets of G*, threshold
+// ln L_T + ln(eta / n_groups). One wavefront per tile.
+template <int D>
+__global__ __launch_bounds__(256) void k_tile_ref_grp(
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi,
+    const double *__restrict__ blk_lnnu, const double *__restrict__ blk_stat,
+    const double *__restrict__ glo, const double *__restrict__ ghi,
+    const double *__restrict__ glnnu, const double *__restrict__ gpsi,
+    const double *__restrict__ ty, const double *__restrict__ tnu,
+    const double *__restrict__ tpsi, const int32_t *__restrict__ tperm, int64_t n_tiles,
+    int64_t n_groups, int g, double cs, double eps, double ln_eta_ng,
+    int32_t *__restrict__ gstar, double *__restrict__ thr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    // A group's bound is at most its block's (less mass, no larger psi, a
+    // box inside the block's), up to rounding: the block with the largest
+    // bound gives a first group value gv, and only blocks whose bound reaches
+    // gv (less a margin) can hold a group above it.
+    const int ng = 64 / g;
+    const int64_t n_blocks = n_groups / ng;
+    double bmax = -INFINITY;
+    int64_t bm = 0;
+    for (int64_t b = lane; b < n_blocks; b += 64) {
+        const double v = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
+                                     cs, eps);
+        if (v > bmax) {
+            bmax = v;
+            bm = b;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(bmax, o, 64);
+        const int64_t oi = __shfl_xor(bm, o, 64);
+        if (ob > bmax || (ob == bmax && oi < bm)) {
+            bmax = ob;
+            bm = oi;
+        }
+    }
+    double gv = -INFINITY;
+    if (lane < ng)
+        gv = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, bm * ng + lane, cs, eps);
+    gv = wave_max(gv);
+    const double floor_v = gv - 1e-9 * (fabs(gv) + 1.0);
+    double best = -INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int64_t b = lane; b < n_blocks; b += 64) {
+        const double v = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
+                                     cs, eps);
+        if (!(v >= floor_v)) continue;
+        for (int i = 0; i < ng; ++i) {
+            const int64_t G = b * ng + i;
+            const double lnU = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, G, cs, eps);
+            if (lnU > best) {
+                best = lnU;
+                bi = G;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int64_t oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    const bool found = bi != INT64_MAX;
+    double lb = -INFINITY;
+    if (found && lane < g) {
+        const int64_t j = bi * g + lane;
+        if (tperm[j] >= 0) {
+            double dmax2 = 0.0;
+            for (int k = 0; k < D; ++k) {
+                const double f = box_far_pt(tile_lo[t * 3 + k], tile_hi[t * 3 + k], ty[j * 3 + k]);
+                dmax2 += f * f;
+            }
+            lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) / eps;
+        }
+    }
+    const double th = wave_max(lb) + ln_eta_ng;
+    if (lane == 0) {
+        gstar[t] = found ? (int32_t)bi : -1;
+        thr[t] = found ? th : INFINITY;
+    }
+}
+
+// Chunk bits (bit c: targets 8c..8c+7 of block b) of the groups of g targets
+// of block b that the tile rule keeps for tile t.
+template <int D>
+__device__ __forceinline__ uint32_t group_chunks(int64_t t, int64_t b, int g,
+                                                 const double *__restrict__ tile_lo,
+                                                 const double *__restrict__ tile_hi,
+                                                 const double *__restrict__ glo,
+                                                 const double *__restrict__ ghi,
+                                                 const double *__restrict__ glnnu,
+                                                 const double *__restrict__ gpsi, int32_t gs,
+                                                 double th, double cs, double eps) {
+    const int ng = 64 / g, cpg = g / 8;
+    const double inv_eps = 1.0 / eps;
+    double tl[3], thb[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        tl[k] = tile_lo[t * 3 + k];
+        thb[k] = tile_hi[t * 3 + k];
+    }
+    uint32_t m = 0;
+    for (int i = 0; i < ng; ++i) {
+        const int64_t G = b * ng + i;
+        bool keep = G == gs;
+        if (!keep) {
+            double dmin2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double gp = box_gap(tl[k], thb[k], glo[G * 3 + k], ghi[G * 3 + k]);
+                dmin2 += gp * gp;
+            }
+            keep = bound_above(glnnu[G], gpsi[G] - cs * dmin2, eps, inv_eps, th);
+        }
+        if (keep) m |= ((1u << cpg) - 1u) << (i * cpg);
+    }
+    return m;
+}
+
 // Culling of the truncated rules straight into CSR lists. Rows are tiles
 // (ROWS) or target blocks; each row is cut into nseg segments of seg_len
 // columns so that short lists of long rows still fill the device, and one
@@ -340,8 +534,15 @@ __global__ __launch_bounds__(256) void k_tile_ref(
 // ptr[row] plus the counts of the row's earlier segments: the index (with
 // RSOT_PARTIAL_BIT when the pair needs the per-pair test) and, for such
 // entries of the rows, the chunk mask.
-// TILE: the tile rule (kept pairs are whole); otherwise the cost cutoff C of
-// the T1 rules.
+// TILE: the tile rule; with grp = 64 it decides per (tile, block) and kept
+// pairs are whole; with culling groups of grp < 64 targets it decides per
+// (tile, group): an entry keeps the chunks of its kept groups, and one that
+// drops some real chunk is marked partial and carries the chunk bits (rows:
+// 2-bit classes in cmask, FULL or SKIP; columns: one bit per chunk in ccm).
+// The block's own bound caps its groups' bounds (a group's mass, psi and
+// box distance are at most the block's), so the groups of a block whose
+// bound falls below the threshold by more than a rounding margin are not
+// tested. Otherwise: the cost cutoff C of the T1 rules.
 template <int D, bool TILE, bool ROWS, bool FILL>
 __global__ __launch_bounds__(256) void k_cull(
     const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
@@ -353,7 +554,10 @@ __global__ __launch_bounds__(256) void k_cull(
     const double *__restrict__ dscal, int32_t *__restrict__ scnt,
     uint64_t *__restrict__ kbits, uint64_t *__restrict__ pbits,
     const int64_t *__restrict__ ptr, uint32_t *__restrict__ idx,
-    uint16_t *__restrict__ cmask) {
+    uint16_t *__restrict__ cmask, int grp, const double *__restrict__ glo,
+    const double *__restrict__ ghi, const double *__restrict__ glnnu,
+    const double *__restrict__ gpsi, const int32_t *__restrict__ blk_cnt,
+    uint8_t *__restrict__ ccm, uint8_t *__restrict__ gm_out, const uint8_t *__restrict__ gm_in) {
     const int lane = threadIdx.x & 63;
     const int64_t rs = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nrows = ROWS ? n_tiles : n_blocks, ncols = ROWS ? n_blocks : n_tiles;
@@ -362,6 +566,7 @@ __global__ __launch_bounds__(256) void k_cull(
     const int sg = (int)(rs % nseg);
     const int64_t kb = sg * seg_len, ke = std::min<int64_t>(kb + seg_len, ncols);
     const double C = TILE ? 0.0 : dscal[SC_C];
+    const bool groups = TILE && grp < 64;
     int c = 0;
     int64_t base = 0;
     if (FILL) {
@@ -376,10 +581,30 @@ __global__ __launch_bounds__(256) void k_cull(
         uint32_t cls = PAIR_SKIP;
         if (FILL) {
             const uint64_t kw = kbits[wi];
-            const uint64_t pw = TILE ? 0 : pbits[wi];
+            const uint64_t pw = (TILE && !groups) ? 0 : pbits[wi];
             if ((kw >> lane) & 1) cls = ((pw >> lane) & 1) ? PAIR_PARTIAL : PAIR_FULL;
         } else if (k < ke) {
-            if (TILE) {
+            if (TILE && groups) {
+                uint32_t m = 0;
+                if (gm_in) {
+                    m = gm_in[r * ncols + k];          // the row pass's masks, transposed
+                } else {
+                    const int32_t gs = bstar[t];
+                    const double th = thr[t];
+                    const bool holds = gs >= 0 && gs / (64 / grp) == b;
+                    const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
+                                                   blk_stat, t, b, cs, eps);
+                    if (holds || lnU > th - 1e-9)
+                        m = group_chunks<D>(t, b, grp, tile_lo, tile_hi, glo, ghi, glnnu, gpsi, gs,
+                                            th, cs, eps);
+                    if (gm_out) gm_out[r * ncols + k] = (uint8_t)m;
+                }
+                if (m) {
+                    const int nr = blk_cnt[b];
+                    const uint32_t real = nr >= 64 ? 0xFFu : ((1u << ((nr + 7) / 8)) - 1u);
+                    cls = (m & real) == real ? PAIR_FULL : PAIR_PARTIAL;
+                }
+            } else if (TILE) {
                 const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
                                                blk_stat, t, b, cs, eps);
                 cls = (b == bstar[t] || lnU > thr[t]) ? PAIR_FULL : PAIR_SKIP;
@@ -394,7 +619,7 @@ __global__ __launch_bounds__(256) void k_cull(
             const uint64_t pw = __ballot(cls == PAIR_PARTIAL);
             if (lane == 0) {
                 kbits[wi] = kw;
-                if (!TILE) pbits[wi] = pw;
+                if (!TILE || groups) pbits[wi] = pw;
             }
         } else {
             const uint64_t mask = __ballot(cls != PAIR_SKIP);
@@ -405,6 +630,20 @@ __global__ __launch_bounds__(256) void k_cull(
                 if (!TILE && ROWS && cls == PAIR_PARTIAL)
                     cmask[base + below] = (uint16_t)chunk_mask<D>(t, b, tile_lo, tile_hi, tch_lo,
                                                                   tch_hi, cs, C);
+                if (TILE && groups && cls == PAIR_PARTIAL) {
+                    const uint32_t m =
+                        gm_in ? (uint32_t)gm_in[r * ncols + k]
+                              : group_chunks<D>(t, b, grp, tile_lo, tile_hi, glo, ghi, glnnu,
+                                                gpsi, bstar[t], thr[t], cs, eps);
+                    if (ROWS) {
+                        uint32_t cm2 = 0;
+                        for (int q = 0; q < 8; ++q)
+                            if ((m >> q) & 1u) cm2 |= (uint32_t)PAIR_FULL << (2 * q);
+                        cmask[base + below] = (uint16_t)cm2;
+                    } else {
+                        ccm[base + below] = (uint8_t)m;
+                    }
+                }
             }
             base += __popcll(mask);
         }
@@ -423,6 +662,25 @@ __global__ void k_seg_sum(const int32_t *__restrict__ scnt, int64_t nrows, int n
     int32_t c = 0;
     for (int i = 0; i < nseg; ++i) c += scnt[r * nseg + i];
     cnt[r] = c;
+}
+
+// out = in^T for a rows x cols byte matrix, through 64 x 64 tiles in LDS
+// (grid: x over column tiles, y over row tiles)
+__global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t *__restrict__ in,
+                                                      int64_t rows, int64_t cols,
+                                                      uint8_t *__restrict__ out) {
+    __shared__ uint8_t tb[64][65];
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        tb[i][tx] = (r < rows && c < cols) ? in[r * cols + c] : (uint8_t)0;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows) out[c * rows + r] = tb[tx][i];
+    }
 }
 
 // bounding boxes of consecutive groups of 8 elements (coordinates with the
@@ -541,9 +799,10 @@ __global__ void k_item_keys(const int64_t *__restrict__ wi_range, const uint32_t
 // power of two. Exact for any first value of m (m = -1e300: no reference yet).
 // MASK: only targets with t_j > G_j - A (c < C) enter, and are counted.
 template <int D, bool F64, bool MASK, typename RP, typename GP>
-__device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, double x2, double A,
-                                          double rq, double &m, double &s, double &kept) {
-    for (int k0 = 0; k0 < 64; k0 += CH) {
+__device__ __forceinline__ void lse_chunk(RP T, int k0, GP G, double x0, double x1, double x2,
+                                          double A, double rq, double &m, double &s,
+                                          double &kept) {
+    {
         double tv[CH];
         double cm = -INFINITY;
 #pragma unroll
@@ -574,6 +833,13 @@ __device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, doub
             s += (double)cs;
         }
     }
+}
+
+template <int D, bool F64, bool MASK, typename RP, typename GP>
+__device__ __forceinline__ void lse_block(RP T, GP G, double x0, double x1, double x2, double A,
+                                          double rq, double &m, double &s, double &kept) {
+    for (int k0 = 0; k0 < 64; k0 += CH)
+        lse_chunk<D, F64, MASK>(T, k0, G, x0, x1, x2, A, rq, m, s, kept);
 }
 
 // Mixed-precision fast path for a chunk of 8 targets whose pairs are all
@@ -699,12 +965,18 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
     double m = -1e300, s = 0.0, kept = 0.0;
     constexpr bool FAST = !F64;
     if (FAST && e1 > e0) {
-        // reference from the first target of the first block
+        // reference from the first target of the first block (under the tile
+        // rule with groups: of its first kept chunk), a kept target
         const uint32_t ent0 = MODE == MODE_DENSE ? (uint32_t)e0 : row_idx[e0];
         const int64_t b0 = (int64_t)(ent0 & ~RSOT_PARTIAL_BIT);
+        int k0 = 0;
+        if (MODE == MODE_LIST && (ent0 & RSOT_PARTIAL_BIT)) {
+            const uint32_t cm0 = row_cm[e0];
+            while (k0 < 56 && !((cm0 >> (k0 / 4)) & 2u)) k0 += 8;
+        }
         double4 r;
-        if constexpr (D == 3) r = trec_at<D>(trec + b0 * 64, 0);
-        else r = trec_at<D>(trec3 + b0 * 192, 0);
+        if constexpr (D == 3) r = trec_at<D>(trec + b0 * 64, k0);
+        else r = trec_at<D>(trec3 + b0 * 192, k0);
         m = ceil(pair_exp<D>(x0, x1, x2, r) - rq) + rq;
     }
     // the next list entry is read one block ahead, and the block's pair
@@ -716,7 +988,17 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
         else if (e + 1 < e1) ent_next = row_idx[e + 1];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
         auto block = [&](auto T) {
-            if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
+            if (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT)) {
+                // tile rule with groups: the kept 8-target chunks only
+                const uint32_t cm = row_cm[e];
+                const int cnt = blk_cnt[b];
+                for (int c = 0; c < 8; ++c) {
+                    if (!((cm >> (2 * c)) & 2u)) continue;
+                    if (FAST) lse_chunk_fast<D>(T, 8 * c, x0, x1, x2, m, s);
+                    else lse_chunk<D, F64, false>(T, 8 * c, tG, x0, x1, x2, A, rq, m, s, kept);
+                    kept += (double)std::min(8, std::max(0, cnt - 8 * c));
+                }
+            } else if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
                 if (!FAST) {
                     lse_block<D, F64, true>(T, tG + b * 64, x0, x1, x2, A, rq, m, s, kept);
                 } else {
@@ -972,10 +1254,14 @@ __device__ __forceinline__ double mass_tile(QP Q, double Y0, double Y1, double Y
 // Gradient pass, one work item = (target block, segment of its tile list).
 // Under the cutoff rules a tile that straddles the cutoff runs its 8-point
 // chunks by their class in the entry's chunk mask (FP64: every pair tested).
-template <int D, bool F64, int MODE, typename QP, typename AP, typename IP, typename RP>
+// Under the tile rule with culling groups, an entry that keeps only some of
+// the block's 8-target chunks carries their bits: the other lanes' terms
+// enter as 2^-inf = 0.
+template <int D, bool F64, int MODE, typename QP, typename AP, typename IP, typename RP,
+          typename CP>
 __device__ __forceinline__ void pass2_item(QP qp, AP qA, RP tref, const double4 *__restrict__ trec,
-                                           const double *__restrict__ tG, IP col_idx, int64_t b,
-                                           int64_t e0, int64_t e1, int64_t w, int lane,
+                                           const double *__restrict__ tG, IP col_idx, CP col_cm,
+                                           int64_t b, int64_t e0, int64_t e1, int64_t w, int lane,
                                            double *__restrict__ gpart) {
     const int64_t j = b * 64 + lane;
     const double4 rec = trec[j];
@@ -994,6 +1280,9 @@ __device__ __forceinline__ void pass2_item(QP qp, AP qA, RP tref, const double4 
             for (int i0 = 0; i0 < 64; i0 += CH)
                 a += mass_chunk<D, F64, true>(Q, i0, qA + t * 64, rec.x, rec.y, rec.z, rec.w, G);
             acc += a * scale;
+        } else if (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT)) {
+            const double Bl = ((col_cm[e] >> (lane >> 3)) & 1u) ? rec.w : -INFINITY;
+            acc += mass_tile<D, F64>(Q, rec.x, rec.y, rec.z, Bl) * scale;
         } else {
             acc += mass_tile<D, F64>(Q, rec.x, rec.y, rec.z, rec.w) * scale;
         }
@@ -1007,7 +1296,7 @@ __global__ __launch_bounds__(256) void k_pass2(
     const double2 *__restrict__ tref, const double4 *__restrict__ trec,
     const double *__restrict__ tG, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
-    const uint32_t *__restrict__ col_idx, int64_t n_tiles,
+    const uint32_t *__restrict__ col_idx, const uint8_t *__restrict__ col_cm, int64_t n_tiles,
     int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1037,7 +1326,7 @@ __global__ __launch_bounds__(256) void k_pass2(
         e0 = wi_range[2 * w];
         e1 = wi_range[2 * w + 1];
     }
-    pass2_item<D, F64, MODE>(qp, qA, tref, trec, tG, col_idx, b, e0, e1, w, lane, gpart);
+    pass2_item<D, F64, MODE>(qp, qA, tref, trec, tG, col_idx, col_cm, b, e0, e1, w, lane, gpart);
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,6 +1344,7 @@ struct BatchDesc {
     const double *tG;
     const int32_t *blk_cnt;
     const uint32_t *row_idx;
+    const uint16_t *row_cm;
     const int32_t *wi1_tile;
     const int64_t *wi1_range;
     const int32_t *wi1_perm;
@@ -1062,6 +1352,7 @@ struct BatchDesc {
     double kcs;
     double *part1, *part1k;
     const uint32_t *col_idx;
+    const uint8_t *col_cm;
     const int32_t *wi_block;
     const int64_t *wi_range;
     const int32_t *wi_perm;
@@ -1118,7 +1409,7 @@ __global__ __launch_bounds__(256) void k_pass1_batched(const BatchDesc *__restri
     }
     pass1_item<D, false, MODE>(d.qp, uniform_const(d.trec), uniform_const(d.trec3),
                                uniform_const(d.tG), uniform_const(d.blk_cnt),
-                               uniform_const(d.row_idx), (const uint16_t *)nullptr, t, e0, e1,
+                               uniform_const(d.row_idx), uniform_const(d.row_cm), t, e0, e1,
                                d.kcs, w, lane, d.part1, d.part1k, (uint64_t *)nullptr);
 }
 
@@ -1148,7 +1439,8 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
     }
     pass2_item<D, false, MODE>(uniform_const(d.qp), uniform_const(d.qA),
                                uniform_const(d.tile_ref), d.trec, d.tG,
-                               uniform_const(d.col_idx), b, e0, e1, w, lane, d.gpart);
+                               uniform_const(d.col_idx), uniform_const(d.col_cm), b, e0, e1, w,
+                               lane, d.gpart);
 }
 
 // per target: merge the work-item partials in order, un-permute, norms
@@ -1318,7 +1610,7 @@ static void launch_pass2(rsot_problem *p, int64_t n_wi, int64_t n_seg, int64_t s
         grid = xcd_run_grid(n_wi);
     hipLaunchKernelGGL((k_pass2<D, F64, MODE>), dim3(grid), dim3(256), 0, p->stream, p->qp, p->qA,
                        p->tile_ref, p->trec, p->tG, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,
-                       p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
+                       p->col_cm, p->n_tiles, p->n_blocks, n_wi, n_seg, seg, p->gpart);
 }
 
 template <int D, bool F64>
@@ -1346,9 +1638,14 @@ static void cull_segments(int64_t nrows, int64_t ncols, int *nseg, int64_t *seg_
     *nseg = (int)((ncols + len - 1) / len);
 }
 
+// Culling group of the tile rule: targets per group (64 = whole blocks)
+static int tile_group(const rsot_problem *p) {
+    return p->opt.tile_group > 0 ? (int)p->opt.tile_group : RSOT_TILE_GROUP_DEFAULT;
+}
+
 // Buffers of the culling step: list pointers and counts; for the tile rule
-// the per-tile B* and threshold; for the cutoff rules the boxes of 8-target
-// chunks (made once).
+// the per-tile B* and threshold, and with culling groups the group tables;
+// for the cutoff rules the boxes of 8-target chunks (made once).
 static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStream_t st) {
     if (!p->row_ptr) {
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
@@ -1368,7 +1665,8 @@ static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStrea
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_kbits, sizeof(uint64_t) * rw));
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_kbits, sizeof(uint64_t) * cw));
     }
-    if (!tile_rule && !p->row_pbits) {
+    const bool groups = tile_rule && tile_group(p) < 64;
+    if ((!tile_rule || groups) && !p->row_pbits) {
         const size_t rw = (size_t)p->n_tiles * (size_t)((p->n_blocks + 63) / 64);
         const size_t cw = (size_t)p->n_blocks * (size_t)((p->n_tiles + 63) / 64);
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_pbits, sizeof(uint64_t) * rw));
@@ -1377,6 +1675,28 @@ static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStrea
     if (tile_rule && !p->tile_bstar) {
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tile_bstar, sizeof(int32_t) * p->n_tiles));
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tile_thr, sizeof(double) * p->n_tiles));
+    }
+    // the group masks of every (tile, block) pair and their transpose, when
+    // both fit in 4 GiB (else every culling pass recomputes them)
+    if (groups && !p->gmask && !p->gmask_tried) {
+        p->gmask_tried = 1;
+        const size_t nf = (size_t)p->n_tiles * (size_t)p->n_blocks;
+        if (2 * nf <= ((size_t)1 << 32) &&
+            rsot_dev_alloc(p, (void **)&p->gmask, nf) == RSOT_OK) {
+            if (rsot_dev_alloc(p, (void **)&p->gmaskT, nf) == RSOT_OK) {
+                p->gmask_ok = 1;
+            } else {
+                rsot_dev_free(p, p->gmask);
+                p->gmask = nullptr;
+            }
+        }
+    }
+    if (groups && !p->grp_lo) {       // sized for the smallest group, 8 targets
+        const int64_t ng = p->n_pad / 8;
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->grp_lo, sizeof(double) * 3 * ng));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->grp_hi, sizeof(double) * 3 * ng));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->grp_lnnu, sizeof(double) * ng));
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->grp_psi, sizeof(double) * ng));
     }
     if (!tile_rule && !p->tch_lo) {
         const int64_t ntc = p->n_pad / 8;
@@ -1404,11 +1724,19 @@ static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, 
     uint16_t *cm = rows ? p->row_cm : nullptr;
     uint64_t *kb = rows ? p->row_kbits : p->col_kbits;
     uint64_t *pb = rows ? p->row_pbits : p->col_pbits;
+    const int grp = tile_rule ? tile_group(p) : 64;
+    // tile rule with groups and stored masks: the row count pass writes them,
+    // every other pass reads them (the column passes the transposed copy)
+    const bool masks = tile_rule && grp < 64 && p->gmask_ok;
+    uint8_t *gm_out = (masks && rows && !fill) ? p->gmask : nullptr;
+    const uint8_t *gm_in = !masks ? nullptr : (rows ? (fill ? p->gmask : nullptr) : p->gmaskT);
 #define RSOT_CULL(DD, TT, RR, FF)                                                              \
     hipLaunchKernelGGL((k_cull<DD, TT, RR, FF>), g, dim3(256), 0, st, p->tile_lo, p->tile_hi,    \
                        p->blk_lo, p->blk_hi, p->tch_lo, p->tch_hi,                               \
                        p->blk_lnnu, p->blk_stat, p->tile_bstar, p->tile_thr, p->n_tiles,         \
-                       p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, kb, pb, ptr, idx, cm)
+                       p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, kb, pb, ptr, idx, cm, \
+                       grp, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->blk_cnt,          \
+                       rows ? nullptr : p->col_cm, gm_out, gm_in)
 #define RSOT_CULL_F(DD, TT, RR)                                                                \
     do {                                                                                        \
         if (fill) RSOT_CULL(DD, TT, RR, true);                                                  \
@@ -1432,6 +1760,10 @@ static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, 
     if (!fill)
         hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st, cnt,
                            nrows, nseg, rows ? p->row_cnt : p->col_cnt);
+    if (gm_out)
+        hipLaunchKernelGGL(k_transpose_u8,
+                           dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
+                           dim3(256), 0, st, p->gmask, p->n_tiles, p->n_blocks, p->gmaskT);
 }
 
 // One evaluation in stages, so that a batch of problems can share host
@@ -1452,6 +1784,7 @@ struct EvalPlan {
     int64_t n_wi = 0, n_seg = 1, seg = 1;
     Pass1Work pw{0, 0, 1};
     int64_t seg1_cfg = RSOT_SEG1_DEFAULT;
+    int group = 64;                     // culling group of the tile rule
 };
 
 static rsot_status plan_begin(EvalPlan &e) {
@@ -1521,7 +1854,26 @@ static rsot_status plan_begin(EvalPlan &e) {
     RSOT_TRY(ensure_cull_buffers(p, tile_rule, st));
     e.culled = true;
     e.mode = tile_rule ? MODE_LIST : MODE_MASK;
-    if (tile_rule) {
+    const int grp = tile_rule ? tile_group(p) : 64;
+    e.group = grp;
+    if (tile_rule && grp < 64) {
+        const int64_t ng = p->n_pad / grp;
+        const double ln_eta_ng = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
+                                 std::log((double)ng);
+        hipLaunchKernelGGL(k_group_tables, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st,
+                           p->ty, p->tnu, p->tpsi, p->tperm, ng, grp, p->grp_lo, p->grp_hi,
+                           p->grp_lnnu, p->grp_psi);
+        if (D == 2)
+            hipLaunchKernelGGL(k_tile_ref_grp<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->ty, p->tnu,
+                               p->tpsi, p->tperm, p->n_tiles, ng, grp, cs, eps, ln_eta_ng,
+                               p->tile_bstar, p->tile_thr);
+        else
+            hipLaunchKernelGGL(k_tile_ref_grp<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
+                               p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->ty, p->tnu,
+                               p->tpsi, p->tperm, p->n_tiles, ng, grp, cs, eps, ln_eta_ng,
+                               p->tile_bstar, p->tile_thr);
+    } else if (tile_rule) {
         const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
                                  std::log((double)p->n_blocks);
         if (D == 2)
@@ -1597,6 +1949,7 @@ static rsot_status plan_lists(EvalPlan &e) {
         RSOT_TRY(grow(p, &p->col_idx, &cap_c, want));
         RSOT_TRY(grow(p, &p->row_cm, &cap_rm, want));
         p->list_cap = std::min(std::min(cap_r, cap_c), cap_rm);
+        if (e.group < 64) RSOT_TRY(grow(p, &p->col_cm, &p->col_cm_cap, want));
         size_t cap_b = p->wi_cap, cap_rg = p->wi_cap;
         RSOT_TRY(grow(p, &p->wi_block, &cap_b, (size_t)std::max<int64_t>(e.n_wi, 1)));
         RSOT_TRY(grow(p, &p->wi_range, &cap_rg, (size_t)std::max<int64_t>(2 * e.n_wi, 2)));
@@ -1694,6 +2047,7 @@ static rsot_status plan_result(EvalPlan &e, bool timed_passes, double *J_out,
     if (e.dense_fallback && p->absJ_ref <= 0.0) p->absJ_ref = std::fabs(h[SC_J]);
     p->last_eval_valid = 1;
     p->last_mode = e.mode;
+    p->last_group = e.group;
     p->last_n_wi = e.n_wi;
     p->last_n_seg = e.n_seg;
     p->last_seg = e.seg;
@@ -1852,6 +2206,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.tG = p->tG;
         d.blk_cnt = p->blk_cnt;
         d.row_idx = p->row_idx;
+        d.row_cm = p->row_cm;
         d.wi1_tile = p->wi1_tile;
         d.wi1_range = p->wi1_range;
         d.wi1_perm = p->wi1_perm;
@@ -1862,6 +2217,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
         d.part1 = p->part1;
         d.part1k = p->part1k;
         d.col_idx = p->col_idx;
+        d.col_cm = p->col_cm;
         d.wi_block = p->wi_block;
         d.wi_range = p->wi_range;
         d.wi_perm = p->wi_perm;
@@ -2042,6 +2398,61 @@ extern "C" rsot_status rsot_get_tile_keep(rsot_problem *p, uint8_t *keep_out) {
         hipLaunchKernelGGL(k_scatter_keep, dim3((unsigned)((p->n_tiles + 255) / 256)), dim3(256),
                            0, p->stream, p->row_ptr, p->row_idx, p->n_tiles, p->n_blocks,
                            keep_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    return RSOT_OK;
+}
+
+// one thread per tile row: per kept entry the bits of its 8-target chunks
+// whose pairs entered the sum (cutoff rules: every chunk not skipped; FP64
+// cutoff rules test every chunk of a straddling block)
+__global__ void k_scatter_chunks(const int64_t *__restrict__ row_ptr,
+                                 const uint32_t *__restrict__ row_idx,
+                                 const uint16_t *__restrict__ row_cm, int64_t n_tiles,
+                                 int64_t n_blocks, int all_tested, uint8_t *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    for (int64_t e = row_ptr[t]; e < row_ptr[t + 1]; ++e) {
+        const uint32_t ent = row_idx[e];
+        uint32_t m = 0xFFu;
+        if ((ent & RSOT_PARTIAL_BIT) && !all_tested) {
+            const uint32_t cm = row_cm[e];
+            m = 0;
+            for (int c = 0; c < 8; ++c)
+                if ((cm >> (2 * c)) & 3u) m |= 1u << c;
+        }
+        out[t * n_blocks + (ent & ~RSOT_PARTIAL_BIT)] = (uint8_t)m;
+    }
+}
+
+extern "C" rsot_status rsot_get_tile_chunk_keep(rsot_problem *p, uint8_t *mask_out) {
+    if (!p || !mask_out || !p->last_eval_valid) return RSOT_ERR_INVALID_ARG;
+    const int64_t nf = p->n_tiles * p->n_blocks;
+    const bool dense = p->last_mode == MODE_DENSE;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, p->stream,
+                       mask_out, nf, (uint8_t)(dense ? 0xFF : 0));
+    if (!dense)
+        hipLaunchKernelGGL(k_scatter_chunks, dim3((unsigned)((p->n_tiles + 255) / 256)), dim3(256),
+                           0, p->stream, p->row_ptr, p->row_idx, p->row_cm, p->n_tiles,
+                           p->n_blocks, (p->last_mode == MODE_MASK && rsot_pairs_fp64(p)) ? 1 : 0,
+                           mask_out);
+    RSOT_HIP(hipGetLastError());
+    RSOT_HIP(hipStreamSynchronize(p->stream));
+    return RSOT_OK;
+}
+
+__global__ void k_target_slots(const int32_t *__restrict__ tperm, int64_t n_pad,
+                               int32_t *__restrict__ slot) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    const int32_t src = tperm[i];
+    if (src >= 0) slot[src] = (int32_t)i;
+}
+
+extern "C" rsot_status rsot_get_target_slots(rsot_problem *p, int32_t *slot_out) {
+    if (!p || !slot_out) return RSOT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_target_slots, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0,
+                       p->stream, p->tperm, p->n_pad, slot_out);
     RSOT_HIP(hipGetLastError());
     RSOT_HIP(hipStreamSynchronize(p->stream));
     return RSOT_OK;
@@ -2365,9 +2776,10 @@ extern "C" rsot_status rsot_softmax_refine(rsot_problem *p, double eps, const do
 // timed as the best of `reps` evaluations with HIP events. The problem keeps
 // the fastest pair; the default configuration's time is reported beside it.
 static rsot_status time_config(rsot_problem *p, double eps, const double *psi, int sb, int stl,
-                               int reps, double *ms_out) {
+                               int grp, int reps, double *ms_out) {
     p->opt.seg_blocks = sb;
     p->opt.seg_tiles = stl;
+    p->opt.tile_group = grp;
     double best = INFINITY, J = 0.0;
     rsot_eval_info info{};
     for (int r = 0; r < reps; ++r) {
@@ -2379,9 +2791,11 @@ static rsot_status time_config(rsot_problem *p, double eps, const double *psi, i
 }
 
 extern "C" rsot_status rsot_autotune(rsot_problem *p, double eps, const double *psi, int reps,
-                                     int *seg_blocks_out, int *seg_tiles_out, double *best_ms_out,
+                                     int *seg_blocks_out, int *seg_tiles_out,
+                                     int *tile_group_out, double *best_ms_out,
                                      double *default_ms_out) {
     if (!p || !psi || !(eps > 0.0) || reps < 1) return RSOT_ERR_INVALID_ARG;
+    static const int GR[] = {64, 32, 16, 8};
     static const int SB[] = {64, 128, 256, 512, 1024};
     static const int ST[] = {16, 32, 64, 128, 256, 512, 1024, 4096};
     const rsot_options keep = p->opt;
@@ -2389,13 +2803,25 @@ extern "C" rsot_status rsot_autotune(rsot_problem *p, double eps, const double *
     rsot_eval_info info{};
     RSOT_TRY(rsot_eval_impl(p, eps, psi, &J, p->dgrad, &info));   // state (|J_ref|), warm-up
     double t_def = 0.0;
-    rsot_status s = time_config(p, eps, psi, 0, 0, reps, &t_def);
-    int best_sb = 0, best_st = 0;
+    rsot_status s = time_config(p, eps, psi, 0, 0, 0, reps, &t_def);
+    int best_sb = 0, best_st = 0, best_gr = 0;
     double best = t_def;
+    // culling group first (tile rule only): it sets the lists the segments cut
+    if (p->opt.truncation == RSOT_TRUNC_TILE) {
+        for (int gr : GR) {
+            if (s != RSOT_OK) break;
+            double t = 0.0;
+            s = time_config(p, eps, psi, 0, 0, gr, reps, &t);
+            if (s == RSOT_OK && t < best) {
+                best = t;
+                best_gr = gr;
+            }
+        }
+    }
     for (int sb : SB) {
         if (s != RSOT_OK) break;
         double t = 0.0;
-        s = time_config(p, eps, psi, sb, best_st, reps, &t);
+        s = time_config(p, eps, psi, sb, best_st, best_gr, reps, &t);
         if (s == RSOT_OK && t < best) {
             best = t;
             best_sb = sb;
@@ -2404,7 +2830,7 @@ extern "C" rsot_status rsot_autotune(rsot_problem *p, double eps, const double *
     for (int st : ST) {
         if (s != RSOT_OK) break;
         double t = 0.0;
-        s = time_config(p, eps, psi, best_sb, st, reps, &t);
+        s = time_config(p, eps, psi, best_sb, st, best_gr, reps, &t);
         if (s == RSOT_OK && t < best) {
             best = t;
             best_st = st;
@@ -2414,16 +2840,23 @@ extern "C" rsot_status rsot_autotune(rsot_problem *p, double eps, const double *
     if (s != RSOT_OK) return s;
     p->opt.seg_blocks = best_sb;
     p->opt.seg_tiles = best_st;
+    p->opt.tile_group = best_gr;
     if (seg_blocks_out) *seg_blocks_out = best_sb;
     if (seg_tiles_out) *seg_tiles_out = best_st;
+    if (tile_group_out) *tile_group_out = best_gr;
     if (best_ms_out) *best_ms_out = best;
     if (default_ms_out) *default_ms_out = t_def;
     return RSOT_OK;
 }
 
-extern "C" rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles) {
+extern "C" rsot_status rsot_set_tuning(rsot_problem *p, int seg_blocks, int seg_tiles,
+                                       int tile_group) {
     if (!p || seg_blocks < 0 || seg_tiles < 0) return RSOT_ERR_INVALID_ARG;
+    if (tile_group != 0 && tile_group != 8 && tile_group != 16 && tile_group != 32 &&
+        tile_group != 64)
+        return RSOT_ERR_INVALID_ARG;
     p->opt.seg_blocks = seg_blocks;
     p->opt.seg_tiles = seg_tiles;
+    p->opt.tile_group = tile_group;
     return RSOT_OK;
 }

@@ -31,6 +31,8 @@ enum : uint8_t { PAIR_SKIP = 0, PAIR_PARTIAL = 1, PAIR_FULL = 2 };
 // list entries: index, with the top bit set when the pair needs the per-pair
 // cutoff test
 #define RSOT_PARTIAL_BIT 0x80000000u
+// targets per culling group of the tile rule when opt.tile_group is 0
+#define RSOT_TILE_GROUP_DEFAULT 64
 
 struct rsot_problem {
     int dim = 0;
@@ -131,8 +133,20 @@ struct rsot_problem {
     uint64_t *col_kbits = nullptr, *col_pbits = nullptr;
     uint32_t *row_idx = nullptr; // kept entries per tile
     uint32_t *col_idx = nullptr; // kept entries per block
-    uint16_t *row_cm = nullptr;  // chunk masks of row entries that need the per-pair test
-    int32_t *tile_bstar = nullptr; // tile rule: B* of each tile
+    uint16_t *row_cm = nullptr;  // chunk classes of row entries that keep part of a block
+    int32_t *tile_bstar = nullptr; // tile rule: B* (or G*, with groups) of each tile
+    // tile rule with culling groups below 64 targets: per group of the last
+    // evaluation the box of its real targets, ln nu(G) and max psi; and the
+    // chunk bits of the column entries that keep only some of their chunks
+    double *grp_lo = nullptr, *grp_hi = nullptr, *grp_lnnu = nullptr, *grp_psi = nullptr;
+    uint8_t *col_cm = nullptr;
+    size_t col_cm_cap = 0;
+    // group masks (chunk bits) of every (tile, block) pair, row-major by tile,
+    // and their transpose, written by the row count pass and read by the
+    // other culling passes; only when both fit (gmask_ok)
+    uint8_t *gmask = nullptr, *gmaskT = nullptr;
+    int gmask_ok = 0, gmask_tried = 0;
+    int last_group = 64;         // culling group of the last evaluation (64: blocks)
     double *tile_thr = nullptr;  // tile rule: skip threshold of each tile
     double *tch_lo = nullptr, *tch_hi = nullptr;   // [n_pad/8*3] boxes of 8-target chunks
     size_t list_cap = 0;

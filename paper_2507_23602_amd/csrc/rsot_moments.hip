@@ -90,8 +90,9 @@ __global__ __launch_bounds__(256) void k_moments(
     const double2 *__restrict__ tref, const double4 *__restrict__ trec,
     const double *__restrict__ ty, const double *__restrict__ tG,
     const int32_t *__restrict__ wi_block, const int64_t *__restrict__ wi_range,
-    const int32_t *__restrict__ perm, const uint32_t *__restrict__ col_idx, int64_t n_tiles,
-    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, double *__restrict__ mpart) {
+    const int32_t *__restrict__ perm, const uint32_t *__restrict__ col_idx,
+    const uint8_t *__restrict__ col_cm, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
+    int64_t n_seg, int64_t seg, double *__restrict__ mpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t b, w, e0, e1;
@@ -122,10 +123,16 @@ __global__ __launch_bounds__(256) void k_moments(
         const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
         const int64_t t = ent & ~RSOT_PARTIAL_BIT;
         const double scale = tref[t].y;
-        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) {
             moment_tile<D, F64, true>(qp + t * 64, qA + t * 64, rec, G, yv, scale, a);
-        else
+        } else if (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT)) {
+            // tile rule with culling groups: this lane's chunk may be dropped
+            const bool on = (col_cm[e] >> (lane >> 3)) & 1u;
+            const double4 rl = make_double4(rec.x, rec.y, rec.z, on ? rec.w : -INFINITY);
+            moment_tile<D, F64, false>(qp + t * 64, qA, rl, G, yv, scale, a);
+        } else {
             moment_tile<D, F64, false>(qp + t * 64, qA, rec, G, yv, scale, a);
+        }
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) mpart[(w * 64 + lane) * D + d] = a[d];
@@ -232,9 +239,12 @@ __global__ __launch_bounds__(256) void k_maps(
     for (int64_t e = e0; e < e1; ++e) {
         const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
         const int64_t b = ent & ~RSOT_PARTIAL_BIT;
-        const uint32_t cm = (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT))
-                                ? (F64 ? 0x5555u : (uint32_t)row_cm[e])
-                                : 0xAAAAu;
+        // chunk classes: cutoff rules as the objective pass (FP64: every
+        // chunk of a straddling block tested); tile rule with groups: the
+        // kept chunks whole
+        uint32_t cm = 0xAAAAu;
+        if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) cm = F64 ? 0x5555u : (uint32_t)row_cm[e];
+        else if (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT)) cm = row_cm[e];
         auto block = [&](auto T) {
             for (int c = 0; c < 8; ++c) {
                 const int cls = (int)((cm >> (2 * c)) & 3u);
@@ -278,8 +288,8 @@ void launch_moments(rsot_problem *p, int mode) {
 #define RSOT_MOM(M)                                                                            \
     hipLaunchKernelGGL((k_moments<D, F64, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,      \
                        p->qA, p->tile_ref, p->trec, p->ty, p->tG, p->wi_block, p->wi_range,     \
-                       p->wi_perm, p->col_idx, p->n_tiles, p->n_blocks, n_wi, n_seg, seg,       \
-                       p->mpart)
+                       p->wi_perm, p->col_idx, p->col_cm, p->n_tiles, p->n_blocks, n_wi, n_seg,  \
+                       seg, p->mpart)
     if (mode == MODE_DENSE) RSOT_MOM(MODE_DENSE);
     else if (mode == MODE_LIST) RSOT_MOM(MODE_LIST);
     else RSOT_MOM(MODE_MASK);

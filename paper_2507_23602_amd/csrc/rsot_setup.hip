@@ -576,6 +576,7 @@ extern "C" void rsot_options_default(rsot_options *opt) {
     opt->tau = 1e-12;
     opt->delta_thr = 1e-12;
     opt->fp64_below_points = 16384;
+    opt->tile_group = 0;
 }
 
 extern "C" const char *rsot_status_string(rsot_status s) {
@@ -600,6 +601,9 @@ static bool options_valid(const rsot_options &o) {
     if (!(o.tau > 0.0) || !(o.delta_thr > 0.0)) return false;
     if (o.seg_tiles < 0 || o.seg_blocks < 0 || o.mem_limit_bytes < 0) return false;
     if (o.fp64_below_points < 0) return false;
+    if (o.tile_group != 0 && o.tile_group != 8 && o.tile_group != 16 && o.tile_group != 32 &&
+        o.tile_group != 64)
+        return false;
     return true;
 }
 

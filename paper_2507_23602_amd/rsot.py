@@ -58,7 +58,8 @@ class Options(ctypes.Structure):
                 ("truncation", ctypes.c_int), ("tau", ctypes.c_double),
                 ("delta_thr", ctypes.c_double), ("inputs_on_device", ctypes.c_int),
                 ("seg_tiles", ctypes.c_int), ("seg_blocks", ctypes.c_int),
-                ("mem_limit_bytes", ctypes.c_int64), ("fp64_below_points", ctypes.c_int64)]
+                ("mem_limit_bytes", ctypes.c_int64), ("fp64_below_points", ctypes.c_int64),
+                ("tile_group", ctypes.c_int64)]
 
 
 class EvalInfo(ctypes.Structure):
@@ -200,8 +201,10 @@ SIGNATURES = {
                                     ctypes.POINTER(_D), ctypes.POINTER(_P),
                                     ctypes.POINTER(EvalInfo), ctypes.POINTER(_D)]),
     "rsot_autotune": (_I, [_P, _D, _P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
-                           ctypes.POINTER(_D), ctypes.POINTER(_D)]),
-    "rsot_set_tuning": (_I, [_P, _I, _I]),
+                           ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "rsot_set_tuning": (_I, [_P, _I, _I, _I]),
+    "rsot_get_tile_chunk_keep": (_I, [_P, _P]),
+    "rsot_get_target_slots": (_I, [_P, _P]),
     "rsot_get_lse": (_I, [_P, _P]),
     "rsot_get_kept_counts": (_I, [_P, _P]),
     "rsot_get_tile_keep": (_I, [_P, _P]),
@@ -313,7 +316,7 @@ class Problem:
 
     def __init__(self, x, mu, y, nu, *, cost_scale=0.5, precision="mixed", truncation="dense",
                  tau=1e-12, delta_thr=1e-12, seg_tiles=0, seg_blocks=0, mem_limit_bytes=0,
-                 fp64_below_points=None, stream=None):
+                 fp64_below_points=None, tile_group=0, stream=None):
         torch = _torch()
         lib = load_library()
         on_dev = isinstance(x, torch.Tensor) and x.is_cuda
@@ -331,7 +334,7 @@ class Problem:
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
                               tau=tau, delta_thr=delta_thr, inputs_on_device=int(on_dev),
                               seg_tiles=seg_tiles, seg_blocks=seg_blocks,
-                              mem_limit_bytes=mem_limit_bytes, **extra)
+                              mem_limit_bytes=mem_limit_bytes, tile_group=tile_group, **extra)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -403,19 +406,21 @@ class Problem:
         return EvalResult(J.value, grad, info.as_dict())
 
     def autotune(self, psi, eps, reps=2):
-        """rsot_autotune: returns dict(seg_blocks, seg_tiles, best_ms, default_ms)."""
+        """rsot_autotune: returns dict(seg_blocks, seg_tiles, tile_group,
+        best_ms, default_ms)."""
         pt = _dev_f64(psi, self.n)
-        sb, st = _I(0), _I(0)
+        sb, st, gr = _I(0), _I(0), _I(0)
         best, dflt = _D(0), _D(0)
         _check(load_library().rsot_autotune(self._h, float(eps), pt.data_ptr(), int(reps),
-                                            ctypes.byref(sb), ctypes.byref(st), ctypes.byref(best),
-                                            ctypes.byref(dflt)), "rsot_autotune")
-        return {"seg_blocks": sb.value, "seg_tiles": st.value, "best_ms": best.value,
-                "default_ms": dflt.value}
+                                            ctypes.byref(sb), ctypes.byref(st), ctypes.byref(gr),
+                                            ctypes.byref(best), ctypes.byref(dflt)),
+               "rsot_autotune")
+        return {"seg_blocks": sb.value, "seg_tiles": st.value, "tile_group": gr.value,
+                "best_ms": best.value, "default_ms": dflt.value}
 
-    def set_tuning(self, seg_blocks, seg_tiles):
-        _check(load_library().rsot_set_tuning(self._h, int(seg_blocks), int(seg_tiles)),
-               "rsot_set_tuning")
+    def set_tuning(self, seg_blocks, seg_tiles, tile_group=0):
+        _check(load_library().rsot_set_tuning(self._h, int(seg_blocks), int(seg_tiles),
+                                              int(tile_group)), "rsot_set_tuning")
 
     def lse(self):
         torch = _torch()
@@ -440,6 +445,27 @@ class Problem:
                                                  ctypes.byref(nb)), "rsot_get_partition")
         out = torch.empty((nt.value, nb.value), dtype=torch.uint8, device="cuda")
         _check(load_library().rsot_get_tile_keep(self._h, out.data_ptr()), "rsot_get_tile_keep")
+        return out
+
+    def tile_chunk_keep(self):
+        """Per (tile, block) of the last evaluation the bits of the block's
+        8-target chunks whose pairs entered it: uint8 CUDA tensor
+        (n_tiles, n_blocks)."""
+        torch = _torch()
+        nt, nb = _I64(0), _I64(0)
+        _check(load_library().rsot_get_partition(self._h, None, None, ctypes.byref(nt),
+                                                 ctypes.byref(nb)), "rsot_get_partition")
+        out = torch.empty((nt.value, nb.value), dtype=torch.uint8, device="cuda")
+        _check(load_library().rsot_get_tile_chunk_keep(self._h, out.data_ptr()),
+               "rsot_get_tile_chunk_keep")
+        return out
+
+    def target_slots(self):
+        """Each target's position in the sorted, padded order (int32 CUDA)."""
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(load_library().rsot_get_target_slots(self._h, out.data_ptr()),
+               "rsot_get_target_slots")
         return out
 
     def softmax_refine(self, psi_coarse, eps, y_fine):
@@ -599,7 +625,7 @@ class Multilevel:
     """Combined source/target multilevel solver (Sec. 5.3)."""
 
     def __init__(self, sources, targets, *, cost_scale=0.5, precision="mixed",
-                 truncation="tile", tau=1e-12):
+                 truncation="tile", tau=1e-12, tile_group=0):
         torch = _torch()
         lib = load_library()
         self._src = [(_dev_f64(x).reshape(len(m) if not isinstance(m, torch.Tensor) else m.numel(), -1),
@@ -615,7 +641,7 @@ class Multilevel:
         yp = (_P * nt)(*[y.data_ptr() for y, _ in self._tgt])
         vp = (_P * nt)(*[v.data_ptr() for _, v in self._tgt])
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
-                              tau=tau, inputs_on_device=1)
+                              tau=tau, inputs_on_device=1, tile_group=tile_group)
         h = _P()
         _check(lib.rsot_multilevel_create(dim, ns, nq, xp, mp, nt, ntg, yp, vp, ctypes.byref(opt),
                                           _P(torch.cuda.current_stream().cuda_stream),
@@ -706,7 +732,8 @@ def tuned(problem, psi, eps, truncation, cache_path, reps=2):
         with open(cache_path) as f:
             cache = json.load(f)
     if key in cache:
-        problem.set_tuning(cache[key]["seg_blocks"], cache[key]["seg_tiles"])
+        problem.set_tuning(cache[key]["seg_blocks"], cache[key]["seg_tiles"],
+                           cache[key].get("tile_group", 0))
         return dict(cache[key], cached=True)
     res = problem.autotune(psi, eps, reps=reps)
     cache[key] = res

@@ -71,10 +71,11 @@ def test_autotune_cache_by_shape_class(tmp_path):
 
         def autotune(self, psi, eps, reps=2):
             self.autotuned += 1
-            return {"seg_blocks": 128, "seg_tiles": 32, "best_ms": 1.0, "default_ms": 2.0}
+            return {"seg_blocks": 128, "seg_tiles": 32, "tile_group": 8, "best_ms": 1.0,
+                    "default_ms": 2.0}
 
-        def set_tuning(self, sb, st):
-            self.tuned_with = (sb, st)
+        def set_tuning(self, sb, st, gr=0):
+            self.tuned_with = (sb, st, gr)
 
     cache = str(tmp_path / "tune.json")
     a = FakeProblem(3, 1_000_000, 65536)
@@ -82,7 +83,7 @@ def test_autotune_cache_by_shape_class(tmp_path):
     assert a.autotuned == 1 and r["cached"] is False
     b = FakeProblem(3, 1_040_000, 66000)          # same log2 sizes and eps decade
     r = rsot.tuned(b, None, 2e-3, "tile", cache)
-    assert b.autotuned == 0 and r["cached"] is True and b.tuned_with == (128, 32)
+    assert b.autotuned == 0 and r["cached"] is True and b.tuned_with == (128, 32, 8)
     c = FakeProblem(3, 1_000_000, 65536)
     rsot.tuned(c, None, 1e-3, "dense", cache)     # another rule: its own class
     assert c.autotuned == 1
@@ -114,7 +115,8 @@ def test_arguments_are_checked_before_any_device_work():
 
     for kw in ({"dim": 4}, {"dim": 1}, {"nq": 0}, {"n": 0}, {"nq": -5}, {"xp": None},
                {"opt": {"cost_scale": 0.0}}, {"opt": {"tau": 0.0}}, {"opt": {"truncation": 9}},
-               {"opt": {"precision": 7}}, {"opt": {"mem_limit_bytes": -1}}):
+               {"opt": {"precision": 7}}, {"opt": {"mem_limit_bytes": -1}},
+               {"opt": {"tile_group": 12}}, {"opt": {"tile_group": 128}}):
         out.value = 123
         assert create(**kw) == rsot.ERR_INVALID_ARG, kw
         assert out.value is None            # *out cleared on failure

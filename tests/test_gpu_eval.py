@@ -264,42 +264,90 @@ def test_cutoff_rules_parity(rule, prec):
         assert -1e-13 * absJ <= dense.J - ref.J <= tau * absJ
 
 
+def _chunk_keep_from_groups(keep_g, slots, n_blocks, g, n):
+    """The oracle's (tile, group) keep matrix as the library's per (tile,
+    block) chunk bits, and the mask of chunks that hold a real target."""
+    nt = keep_g.shape[0]
+    bits = np.zeros((nt, n_blocks), dtype=np.uint8)
+    real = np.zeros(n_blocks * 8, dtype=bool)
+    real[slots // 8] = True
+    for c in range(8):
+        grp = (np.arange(n_blocks) * 64 + 8 * c) // g            # group of chunk c of each block
+        ok = grp < keep_g.shape[1]
+        col = np.zeros((nt, n_blocks), dtype=bool)
+        col[:, ok] = keep_g[:, grp[ok]] > 0
+        bits |= (col.astype(np.uint8) << c)
+    return bits, real.reshape(n_blocks, 8)
+
+
 @pytest.mark.parametrize("prec", PREC)
 @pytest.mark.parametrize("d", [2, 3])
-def test_tile_rule_parity(prec, d):
-    """Tile-local rule: GPU kept set, J and grad equal the oracle's rule
-    applied to the GPU's own tile/block partition; error bound holds."""
+@pytest.mark.parametrize("group", [64, 32, 16, 8])
+def test_tile_rule_parity(prec, d, group):
+    """Tile-local rule at every culling granularity (targets per group): the
+    GPU's kept set, chunk by chunk, equals the oracle's rule applied to the
+    GPU's own tiles and groups (the library's sorted target order cut into
+    groups of g); per-point |I_q|, J and grad equal the oracle's; the
+    truncation bound holds."""
     import torch
-    _say(f"tile rule d={d} prec={prec}")
+    _say(f"tile rule d={d} prec={prec} group={group}")
     if d == 3:
         p = W.cube_mixture(10, 3000, 1e-3)
     else:
         p = W.square_uniform(48, 4000, seed=6, eps=1e-3)
     tau = 1e-8
-    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec, truncation="tile", tau=tau)
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision=prec, truncation="tile", tau=tau,
+                    tile_group=group)
     psi = W.random_psi(8, p.n, p.eps)
     dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
     prob.set_reference(abs(dense.J))
     r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
     tile_of, block_of, nt, nb = prob.partition()
-    ref = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of.cpu().numpy(), nt,
-                                block_of.cpu().numpy(), nb, tau, abs(dense.J), want_L=True)
+    tile_of = tile_of.cpu().numpy()
+    slots = prob.target_slots().cpu().numpy()
+    assert np.array_equal(slots // 64, block_of.cpu().numpy())
+    group_of = (slots // group).astype(np.int32)
+    ng = nb * 64 // group
+    ref = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, group_of, ng, tau,
+                                abs(dense.J), want_L=True, want_keep=True)
     _say(f"  kept gpu={r.info['kept_pairs']} oracle={ref.kept} of {p.nq * p.n}")
     assert r.info["kept_pairs"] == ref.kept
     assert ref.kept < p.nq * p.n
-    # the kept (tile, block) set, byte for byte, and |I_q| point by point
-    tile_of, block_of = tile_of.cpu().numpy(), block_of.cpu().numpy()
+    # the kept (tile, chunk) set, bit for bit on the chunks holding targets
+    bits = prob.tile_chunk_keep().cpu().numpy()
+    ref_bits, real = _chunk_keep_from_groups(ref.keep, slots, nb, group, p.n)
+    realbits = np.packbits(real[:, ::-1], axis=1, bitorder="big").reshape(-1)
+    assert np.array_equal(bits & realbits[None, :], ref_bits & realbits[None, :])
     keep = prob.tile_keep().cpu().numpy()
-    assert set(np.unique(keep)) <= {0, 2}
-    refk = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, block_of, nb,
-                                 tau, abs(dense.J), want_keep=True).keep
-    _say(f"  kept (tile, block) pairs: gpu {int((keep > 0).sum())}, oracle {int(refk.sum())}")
-    assert np.array_equal(keep > 0, refk > 0)
+    if group == 64:
+        assert set(np.unique(keep)) <= {0, 2}
+    assert np.array_equal(keep > 0, (ref_bits & realbits[None, :]) > 0)
+    _say(f"  kept (tile, chunk) pairs: {int(np.unpackbits(bits & realbits[None, :]).sum())}")
     cnt = prob.kept_counts().cpu().numpy()
-    ref_cnt = (refk[tile_of] > 0).astype(np.int64) @ np.bincount(block_of, minlength=nb)
+    ref_cnt = (ref.keep[tile_of] > 0).astype(np.int64) @ np.bincount(group_of, minlength=ng)
     assert np.array_equal(cnt, ref_cnt)
     _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, prec, ref=ref, r=r)
     assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
+
+
+def test_tile_rule_groups_keep_fewer_pairs():
+    """Finer culling groups give a tighter rule: on the same problem groups
+    of 8 targets keep fewer pairs than whole blocks, and every granularity
+    stays within the tau |J| bound of the dense objective."""
+    import torch
+    p = W.cube_mixture(12, 6000, 1e-3)
+    psi = W.random_psi(9, p.n, p.eps)
+    dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    kept = []
+    for g in (64, 32, 16, 8):
+        prob = _problem(p.x, p.mu, p.y, p.nu, precision="fp64", truncation="tile", tau=1e-8,
+                        tile_group=g)
+        prob.set_reference(abs(dense.J))
+        r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+        kept.append(r.info["kept_pairs"])
+        assert -1e-13 * abs(dense.J) <= dense.J - r.J <= 1e-8 * abs(dense.J)
+    _say(f"  kept pairs by group 64/32/16/8: {kept}")
+    assert kept[-1] < kept[0]
 
 
 def test_full_size_sampled_points():

@@ -39,9 +39,12 @@ def _problem(p, prec, rule, tau=1e-8):
 def _keep_for(prob, p, rule, psi, r):
     """The oracle's restriction for the GPU evaluation that produced r."""
     if rule == "tile":
+        # the kept (tile, 8-target chunk) set, whatever the culling group
         tile_of, block_of, nt, nb = prob.partition()
-        keep = prob.tile_keep().cpu().numpy()
-        return dict(keep=(tile_of.cpu().numpy(), block_of.cpu().numpy(), keep > 0))
+        bits = prob.tile_chunk_keep().cpu().numpy()
+        chunk_of = (prob.target_slots().cpu().numpy() // 8).astype(np.int32)
+        keep_c = np.unpackbits(bits[:, :, None], axis=2, bitorder="little").reshape(nt, nb * 8)
+        return dict(keep=(tile_of.cpu().numpy(), chunk_of, keep_c > 0))
     if rule in ("geom", "pw"):
         return dict(cutoff=r.info["cutoff"])
     return {}
