@@ -50,7 +50,18 @@ def log(*a):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dense_eval_cube64_n65536_hbm_traffic.md")
-EVAL_SOURCE = os.path.join(ROOT, "paper_2507_23602_amd", "csrc", "rsot_eval.hip")
+# the evaluation passes' source: the kernels and the pair helpers they include
+EVAL_SOURCES = [os.path.join(ROOT, "paper_2507_23602_amd", "csrc", f)
+                for f in ("rsot_eval.hip", "rsot_pairs.h", "rsot_device.h")]
+
+
+def eval_source_sha():
+    """sha256 of the evaluation sources, concatenated in order"""
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def counter_traffic(kernel: str):
@@ -61,8 +72,7 @@ def counter_traffic(kernel: str):
         return None
     txt = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel source sha256: ([0-9a-f]{64})", txt)
-    sha = hashlib.sha256(open(EVAL_SOURCE, "rb").read()).hexdigest()
-    if not m or m.group(1) != sha:
+    if not m or m.group(1) != eval_source_sha():
         return None
     m = re.search(re.escape(kernel) + r" HBM bytes per launch: ([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
@@ -80,6 +90,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
+    ap.add_argument("--main-extras", type=int, default=1,
+                    help="0: skip the extras on the benchmark workload itself (rules, FP64, "
+                         "moments, solves) and run only the legs")
     ap.add_argument("--quick", action="store_true",
                     help="skip the disk multilevel, batched and learned legs")
     ap.add_argument("--ml-spread", action="store_true",
@@ -93,6 +106,15 @@ def main():
     ap.add_argument("--mlp", type=str, default="65536,20",
                     help="time the warm-start network kernels: 'ROWS,STEPS' training steps "
                          "and forward passes on synthetic rows ('' to skip)")
+    ap.add_argument("--tile-group", type=int, default=0,
+                    help="targets per culling group of the tile rule in the multilevel leg "
+                         "(0: library default)")
+    ap.add_argument("--trunc-study", type=int, default=1,
+                    help="truncation-strategy study on both densities (0: skip)")
+    ap.add_argument("--trunc-tol", type=str, default="1e-3",
+                    help="stopping tolerances of the truncation study, comma separated")
+    ap.add_argument("--gpu-size", type=str, default="2-5x1-3",
+                    help="App. C sizes 'R0-R1xG0-G1' (refinements x Gauss orders; '' to skip)")
     ap.add_argument("--learned", type=str, default="448,64,30",
                     help="learned warm start on the blob family: 'TRAIN,TEST,EPOCHS': dataset "
                          "from the solver, training, comparison ('' to skip)")
@@ -178,7 +200,8 @@ def main():
            "setup_s": setup_s,
            "J": r.J, "grad_l1": r.info["grad_l1"]}
 
-    if not args.no_extras:
+    psi1 = None
+    if not args.no_extras and args.main_extras:
         extras = {}
         absJ = abs(r.J)
         for rule in ["geom", "tile"]:
@@ -201,6 +224,45 @@ def main():
                             "pass1_ms": rr.info["pass1_ms"], "pass2_ms": rr.info["pass2_ms"]}
             log(f"[bench] {rule}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
                 f"effective {pairs/tt:.3e} pairs/s, kept {kept/tt:.3e} pairs/s")
+        # the tile rule at each culling granularity (targets per group)
+        extras["tile_groups"] = {}
+        prob.set_truncation("tile", tau=1e-12)
+        for g in (64, 32, 16, 8):
+            prob.set_tuning(0, 0, g)
+            rr = prob.dual_eval(psi, p.eps, out=grad)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            k = max(2, args.steps)
+            for _ in range(k):
+                rr = prob.dual_eval(psi, p.eps, out=grad)
+            torch.cuda.synchronize()
+            tt = (time.perf_counter() - ts) / k
+            kept = rr.info["kept_pairs"]
+            extras["tile_groups"][str(g)] = {
+                "ms_per_eval": tt * 1e3, "kept_frac": kept / pairs, "kept_pairs_s": kept / tt,
+                "setup_ms": rr.info["setup_ms"], "pass1_ms": rr.info["pass1_ms"],
+                "pass2_ms": rr.info["pass2_ms"], "J_minus_dense_rel": (r.J - rr.J) / absJ}
+            log(f"[bench] tile rule, groups of {g}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
+                f"culling {rr.info['setup_ms']:.2f} ms, pass1 {rr.info['pass1_ms']:.2f} ms, "
+                f"pass2 {rr.info['pass2_ms']:.2f} ms")
+        # the autotuner's choice for this problem (culling group, then the
+        # work segments of both passes), timed like the rows above
+        prob.set_tuning(0, 0, 0)
+        tune = prob.autotune(psi, p.eps, reps=2)
+        rr = prob.dual_eval(psi, p.eps, out=grad)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        k = max(2, args.steps)
+        for _ in range(k):
+            rr = prob.dual_eval(psi, p.eps, out=grad)
+        torch.cuda.synchronize()
+        tt = (time.perf_counter() - ts) / k
+        extras["tile_tuned"] = dict(tune, ms_per_eval=tt * 1e3,
+                                    kept_frac=rr.info["kept_pairs"] / pairs,
+                                    J_minus_dense_rel=(r.J - rr.J) / absJ)
+        log(f"[bench] tile rule, autotuned {tune}: {tt*1e3:.2f} ms/eval, "
+            f"kept {rr.info['kept_pairs']/pairs:.4f}")
+        prob.set_tuning(0, 0, 0)
         prob.set_truncation("dense")
         prob.set_precision("fp64")
         rr = prob.dual_eval(psi, p.eps, out=grad)
@@ -297,9 +359,19 @@ def main():
     legs = []
     if not args.no_extras:
         if not (args.quick or args.no_multilevel):
-            legs.append(("multilevel", lambda: multilevel_leg(spread=args.ml_spread)))
+            legs.append(("multilevel", lambda: multilevel_leg(spread=args.ml_spread,
+                                                              tile_group=args.tile_group)))
         if args.batched and not args.quick:
             legs.append(("batched", lambda: batched_leg(args.batched)))
+        if args.trunc_study and not args.quick:
+            tols = tuple(float(v) for v in args.trunc_tol.split(","))
+            legs.append(("trunc_study", lambda: trunc_study_leg(tols=tols)))
+        if args.gpu_size and not args.quick:
+            rr, gg = args.gpu_size.split("x")
+            r0, r1 = (int(v) for v in rr.split("-"))
+            g0, g1 = (int(v) for v in gg.split("-"))
+            spec = [(r, g) for r in range(r0, r1 + 1) for g in range(g0, g1 + 1)]
+            legs.append(("gpu_size", lambda: {"rows": gpu_size_leg(spec)}))
         if args.mlp:
             rows, steps = (int(v) for v in args.mlp.split(","))
             legs.append(("mlp", lambda: mlp_leg(rows, steps)))
@@ -317,8 +389,7 @@ def main():
         out.setdefault("extras", {})[name] = res
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(),
-                                           psi1 if not args.no_extras else None)
+        out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(), psi1)
     print(json.dumps(out), flush=True)
 
 
@@ -490,8 +561,9 @@ def batched_leg(k):
                       "kept_pairs": kept, "kept_pairs_s_batched": kept / tb,
                       "kept_pairs_s_singles": kept / ts}
     t0 = time.perf_counter()
+    groups = []
     for pr, ps, e in zip(probs, psis, eps):
-        pr.autotune(ps, e, reps=1)
+        groups.append(pr.autotune(ps, e, reps=1)["tile_group"] or 64)
     t_tune = time.perf_counter() - t0
     singles()
     ts, kept = singles()
@@ -499,25 +571,28 @@ def batched_leg(k):
     res["tuned"] = {"singles_s": ts, "batched_s": tb, "batched_device_ms": ms,
                     "kept_pairs_s_batched": kept / tb, "kept_pairs_s_singles": kept / ts,
                     "tune_seconds": t_tune}
+    res["tuned"]["tile_groups"] = {str(g): groups.count(g) for g in sorted(set(groups))}
     res.update(instances=k, dense_pairs=dense_pairs, kept_frac=kept / dense_pairs,
                effective_pairs_s_batched=dense_pairs / tb)
     # the oracle on the four smallest members, against the batched call's
     # results (tile rule: the oracle applies the same rule to the same
-    # partition and |J_ref|)
+    # partition, cut into the member's tuned culling groups, and |J_ref|)
     import oracle
     J, grads, infos, _ = rsot.dual_eval_batched(probs, eps, psis)
     order = sorted(range(k), key=lambda i: insts[i].nq * insts[i].n)[:4]
     checks = []
     for i in order:
         q = insts[i]
-        tile_of, block_of, nt, nb = probs[i].partition()
+        tile_of, _, nt, nb = probs[i].partition()
+        g = groups[i]
+        group_of = (probs[i].target_slots().cpu().numpy() // g).astype(np.int32)
         ref = oracle.dual_eval_tile(q.x, q.mu, q.y, q.nu, psis[i].cpu().numpy(), q.eps,
-                                    tile_of.cpu().numpy(), nt, block_of.cpu().numpy(), nb,
+                                    tile_of.cpu().numpy(), nt, group_of, nb * 64 // g,
                                     1e-12, infos[i]["absJ_ref"],
                                     threads=int(os.environ.get("OMP_NUM_THREADS",
                                                                os.cpu_count() or 1)))
         g = grads[i].cpu().numpy()
-        checks.append({"instance": i, "nq": q.nq, "n": q.n,
+        checks.append({"instance": i, "nq": q.nq, "n": q.n, "tile_group": g,
                        "J_rel_err": abs(J[i] - ref.J) / abs(ref.J),
                        "grad_err": float(np.max(np.abs(g - ref.grad) / (q.nu + ref.grad + q.nu))),
                        "kept_equal": infos[i]["kept_pairs"] == ref.kept})
@@ -531,10 +606,60 @@ def batched_leg(k):
         f"tuned singles {ts*1e3:.1f} ms, batched {tb*1e3:.1f} ms (tuning {t_tune:.1f}s)")
     for pr in probs:
         pr.close()
+    res["small"] = small_batch(256)
+    res["small_fp32"] = small_batch(256, fp64_below_points=0)
     return res
 
 
-def multilevel_leg(spread=False):
+def small_batch(k, fp64_below_points=None):
+    """k uneven small 2D instances (6,144 to 98,304 points, 256 to 65,536
+    targets), dense, mixed precision: one batched call against k single calls,
+    wall clock on the host (where per-call launch and synchronisation costs
+    show), and the device time of the batch. With the library's routing the
+    members with few effective points run the FP64 pair loop, one problem at a
+    time inside the batched call too; fp64_below_points=0 keeps every member
+    on the batched FP32 loop."""
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+    insts = [W.small_square_instance(i) for i in range(k)]
+    probs = [rsot.Problem(p.x, p.mu, p.y, p.nu, fp64_below_points=fp64_below_points)
+             for p in insts]
+    psis = [torch.as_tensor(W.random_psi(500 + i, p.n, p.eps), device="cuda")
+            for i, p in enumerate(insts)]
+    eps = [p.eps for p in insts]
+    pairs = sum(p.nq * p.n for p in insts)
+
+    def singles():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for pr, ps, e in zip(probs, psis, eps):
+            pr.dual_eval(ps, e)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def batch():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, _, ms = rsot.dual_eval_batched(probs, eps, psis)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, ms
+
+    singles()
+    batch()
+    ts = min(singles() for _ in range(3))
+    tb, ms = min(batch() for _ in range(3))
+    for pr in probs:
+        pr.close()
+    log(f"[bench] small batch {k} (fp64_below_points {fp64_below_points}): {pairs:.3e} pairs; "
+        f"singles {ts*1e3:.1f} ms, batched {tb*1e3:.1f} ms (device {ms:.1f} ms): {ts/tb:.2f}x")
+    return {"instances": k, "pairs": pairs, "singles_s": ts, "batched_s": tb,
+            "fp64_below_points": fp64_below_points,
+            "batched_device_ms": ms, "speedup": ts / tb,
+            "points": [min(p.nq for p in insts), max(p.nq for p in insts)],
+            "targets": [min(p.n for p in insts), max(p.n for p in insts)]}
+
+
+def multilevel_leg(spread=False, tile_group=0):
     """Time to ||grad||_1 < 1e-6 of the combined multilevel solve (Sec. 5.3)
     with the eps schedule, on the 2D disk workload; per-level breakdown.
     Default: the schedule on the two coarsest levels and the final eps on the
@@ -549,7 +674,8 @@ def multilevel_leg(spread=False):
                                    c3["target_levels"], lloyd_iters=20, seed=6)
     torch.cuda.synchronize()
     t_h = time.perf_counter() - t0
-    ml = rsot.Multilevel(c3["sources"], levels, precision="mixed", truncation="tile", tau=1e-12)
+    ml = rsot.Multilevel(c3["sources"], levels, precision="mixed", truncation="tile", tau=1e-12,
+                         tile_group=tile_group)
     t0 = time.perf_counter()
     def progress(it):
         if it.iteration % 25 == 0:
@@ -573,9 +699,120 @@ def multilevel_leg(spread=False):
         f"seconds {[round(v, 3) for v in info['seconds']]}, "
         f"refine {[round(v, 3) for v in info['refine_seconds']]}")
     return {"workload": c3["name"], "schedule": "spread" if spread else "coarse",
+            "tile_group": tile_group,
             "hierarchy_seconds": t_h, "solve_seconds": t_s,
             "time_to_tol_seconds": t_h + t_s, "recheck": recheck,
             "target_sizes": [int(l[1].numel()) for l in levels], **info}
+
+
+TRUNC_STUDY = [("dense", None), ("pw", 1e-12), ("pw", 1e-10), ("pw", 1e-7),
+               ("int", 1e-6), ("int", 1e-5), ("int", 1e-4),
+               ("geom", 1e-6), ("geom", 1e-5), ("geom", 1e-4),
+               ("tile", 1e-6), ("tile", 1e-5), ("tile", 1e-4)]
+
+
+def trunc_study_leg(densities=("custom", "uniform"), tols=(1e-3,), max_iter=2000):
+    """The truncation-strategy study (Sec. 6.1, Table of strategies) on the
+    synthetic stand-in of its inputs (375,000 points x 14,761 targets, eps
+    1e-2): one solve from psi = 0 per (density, rule, parameter) to
+    ||grad||_1 <= tol (the study's 1e-3 by default), mixed precision;
+    iterations, seconds, converged (status OK) and E_rel = |J_trunc -
+    J_dense| / |J_dense| of the final values (Eq. relative_error_definition).
+    With a loose tol that figure also holds the two solves' different
+    stopping points, so E_rel_same_psi adds |J_trunc(psi) - J_dense(psi)| /
+    |J_dense(psi)| at the truncated solve's own potential (the truncation's
+    share alone). Each returned potential is re-evaluated without truncation
+    (FP64) for its true ||grad||_1; the baseline's potential is re-checked by
+    the oracle's dense pass."""
+    import torch
+    import oracle
+    from paper_2507_23602_amd import rsot, workloads as W
+    res = {}
+    for dens, tol in ((d, t) for d in densities for t in tols):
+        p = W.trunc_study(dens)
+        dev = [torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)]
+        chk = rsot.Problem(*dev, precision="fp64")
+        rows = []
+        base_J = None
+        for rule, par in TRUNC_STUDY:
+            kw = {} if rule == "dense" else (
+                {"truncation": rule, "delta_thr": par} if rule == "pw" else
+                {"truncation": rule, "tau": par})
+            pr = rsot.Problem(*dev, precision="mixed", **kw)
+            try:                                             # kernels loaded, lists sized
+                pr.solve([p.eps], tol=tol, max_iter=2)
+            except rsot.RsotError:
+                pass
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            try:
+                psi, info = pr.solve([p.eps], tol=tol, max_iter=max_iter)
+                status = info["status"]
+            except rsot.RsotError as e:
+                psi, info, status = e.psi, e.info, e.code
+            sec = time.perf_counter() - ts
+            pr.close()
+            rd = chk.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+            if rule == "dense":
+                base_J = info["J"]
+                ref = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+                orc = {"oracle_grad_l1": float(np.abs(ref.grad).sum()),
+                       "oracle_J_rel": abs(ref.J - info["J"]) / abs(ref.J)}
+            row = {"rule": rule, "param": par, "iterations": info["iterations"],
+                   "evaluations": info["evaluations"], "seconds": sec, "status": status,
+                   "converged": status == rsot.OK, "J": info["J"],
+                   "E_rel": abs(info["J"] - base_J) / abs(base_J),
+                   "E_rel_same_psi": abs(info["J"] - rd.J) / abs(rd.J),
+                   "kept_frac": info["kept_frac"], "grad_l1": info["grad_l1"],
+                   "dense_grad_l1": rd.info["grad_l1"]}
+            if rule == "dense":
+                row.update(orc)
+            rows.append(row)
+            log(f"[bench] trunc study {dens} tol {tol:g}: {rule:5s} {str(par):6s} "
+                f"{info['iterations']:4d} it {sec:6.2f} s  status {status}  E_rel "
+                f"{row['E_rel']:.1e} (same psi {row['E_rel_same_psi']:.1e})  kept "
+                f"{info['kept_frac']:.3f}  dense |g|_1 {rd.info['grad_l1']:.2e}")
+        chk.close()
+        res[f"{dens}_tol{tol:g}"] = {"workload": p.name, "tol": tol, "rows": rows}
+    return res
+
+
+def gpu_size_leg(spec, tol=1e-3, solve_below=2.5e11, solve_also=((5, 3),)):
+    """The workload at the problem sizes of App. C (uniform [-1, 1]^3 hex
+    meshes, Gauss 1-3, targets uniform in the unit ball, eps 1e-2, no
+    truncation): per (refinement, order) the device time of one dense mixed
+    evaluation at psi = 0 and, where N_q N <= solve_below or for the cases in
+    solve_also (default: the finest, 7,077,888 x 232,609), a dense solve from
+    psi = 0 to ||grad||_1 <= 1e-3 (seconds, iterations, mean seconds per
+    iteration), its potential re-checked (FP64 ||grad||_1 and oracle L_q)."""
+    import torch
+    from paper_2507_23602_amd import rsot, workloads as W
+    out = []
+    for r, order in spec:
+        p = W.gpu_size(r, order)
+        dev = [torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)]
+        pr = rsot.Problem(*dev, precision="mixed")
+        z = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        pr.dual_eval(z, p.eps)
+        ms = min(pr.dual_eval(z, p.eps).info["kernel_ms"] for _ in range(3))
+        row = {"workload": p.name, "refinement": r, "gauss": order, "n_quad": p.nq,
+               "n_target": p.n, "eval_ms": ms, "pairs_s": p.nq * p.n / (ms * 1e-3)}
+        if p.nq * p.n <= solve_below or (r, order) in solve_also:
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            psi, info = pr.solve([p.eps], tol=tol)
+            sec = time.perf_counter() - ts
+            row.update(solve_seconds=sec, iterations=info["iterations"],
+                       evaluations=info["evaluations"], status=info["status"],
+                       seconds_per_iteration=sec / max(1, info["iterations"]),
+                       recheck=fp64_recheck(p, psi, n_sample=64))
+            log(f"[bench] gpu-size {p.name}: eval {ms:.2f} ms, solve {sec:.2f} s, "
+                f"{info['iterations']} it, status {info['status']}")
+        else:
+            log(f"[bench] gpu-size {p.name}: eval {ms:.2f} ms")
+        pr.close()
+        out.append(row)
+    return out
 
 
 def cpu_model():

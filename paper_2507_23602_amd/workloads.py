@@ -378,6 +378,98 @@ def blob_targets_disk(n: int, seed: int = 5, k: int = 5, sigma: float = 0.08,
     return mixture_samples(rng, means, sigma, n)
 
 
+def trunc_study(density: str = "custom", n_cells: int = 25, n_targets: int = 14761,
+                eps: float = 1e-2) -> Problem:
+    """Inputs of the truncation-strategy study (Sec. 6.1 and its Table of
+    strategies), on the benchmark's synthetic stand-ins: the unit cube in
+    25^3 cells x 6 Kuhn tets = 93,750 tets x 4 points = 375,000 points (17,576
+    P1 nodes, against the study's 98,304 cells and 17,969 nodes), N = 14,761
+    targets from the benchmark's target mixture (means seed 3, samples seed 4,
+    sigma 0.1), nu = 1/N, eps = 1e-2. density "custom": the benchmark's
+    3-Gaussian source mixture (seed 2), P1-interpolated; "uniform": rho = 1."""
+    if density == "custom":
+        p = cube_mixture(n_cells, n_targets, eps)
+    elif density == "uniform":
+        x, mu = quadrature(cube_mesh(n_cells))
+        tgt_means = mixture_means(np.random.default_rng(3), 3, 3)
+        y = mixture_samples(np.random.default_rng(4), tgt_means, 0.1, n_targets)
+        p = Problem(x, mu, y, np.full(n_targets, 1.0 / n_targets), eps)
+    else:
+        raise ValueError(density)
+    p.name = f"cube{n_cells}_tet4_{density}_n{n_targets}_eps{eps:g}"
+    return p
+
+
+def gauss_legendre(order: int):
+    """Nodes and weights of the order-point Gauss-Legendre rule on [-1, 1]."""
+    return np.polynomial.legendre.leggauss(order)
+
+
+def hex_gauss(n_cells: int, order: int, lo: float = -1.0, hi: float = 1.0):
+    """Uniform hexahedral mesh of [lo, hi]^3 with n_cells^3 cubes and the
+    tensor Gauss-Legendre rule of ``order`` points per direction in each
+    (order^3 points per cube); uniform density: mu_q = w_q / |Omega|. Points
+    are ordered cube by cube."""
+    t, w = gauss_legendre(order)
+    h = (hi - lo) / n_cells
+    loc = (t + 1.0) * 0.5 * h                              # nodes inside one cube
+    wl = w * 0.5 * h
+    c = lo + h * np.arange(n_cells)
+    cx, cy, cz = np.meshgrid(c, c, c, indexing="ij")
+    corner = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)     # (nc, 3)
+    a, b, g = np.meshgrid(np.arange(order), np.arange(order), np.arange(order), indexing="ij")
+    a, b, g = a.ravel(), b.ravel(), g.ravel()
+    off = np.stack([loc[a], loc[b], loc[g]], axis=1)                     # (order^3, 3)
+    wq = wl[a] * wl[b] * wl[g]
+    x = (corner[:, None, :] + off[None]).reshape(-1, 3)
+    mu = np.tile(wq, corner.shape[0])
+    return np.ascontiguousarray(x), np.ascontiguousarray(mu / mu.sum())
+
+
+def ball_uniform(seed: int, n: int, d: int = 3) -> np.ndarray:
+    """n points uniform in the unit ball: a normal direction, radius U^(1/d)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, d))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v * rng.uniform(0.0, 1.0, size=(n, 1)) ** (1.0 / d)
+
+
+# target counts of the GPU-size workload at refinement 2..5 (App. C, Table of
+# problem sizes): the vertex counts of the refined ball meshes
+GPU_SIZE_TARGETS = {2: 507, 3: 3817, 4: 29521, 5: 232609}
+
+
+def gpu_size(refinement: int, order: int, eps: float = 1e-2, seed: int = 21) -> Problem:
+    """Workload at the sizes of App. C: source uniform on [-1, 1]^3, a hex mesh
+    of (2^(refinement+1))^3 cubes with order^3 Gauss-Legendre points each
+    (refinement 2, order 1: 512 cubes and points; refinement 5, order 3:
+    262,144 cubes, 7,077,888 points); targets uniform
+    in the unit ball (standing in for the ball mesh's vertices) in the counts
+    of the refined ball meshes (507, 3,817, 29,521, 232,609), nu = 1/N;
+    eps = 1e-2."""
+    cells = 2 << refinement
+    x, mu = hex_gauss(cells, order)
+    n = GPU_SIZE_TARGETS[refinement]
+    y = ball_uniform(seed + refinement, n)
+    return Problem(x, mu, y, np.full(n, 1.0 / n), eps,
+                   name=f"hex{cells}_gauss{order}_ball{n}_eps{eps:g}")
+
+
+def small_square_instance(i: int) -> Problem:
+    """Uneven small 2D instance (seed 4000 + i), between the sizes of the
+    small 2D workload and the learned-start family: unit square in n x n
+    cells x 2 triangles x 3 points, n = round(logU[32, 128]) (6,144 to 98,304
+    points), uniform density; N ~ logU[256, 65,536] uniform targets, nu = 1/N;
+    eps ~ logU[1e-3, 1e-1]."""
+    rng = np.random.default_rng(4000 + i)
+    n_cells = int(round(math.exp(rng.uniform(math.log(32), math.log(128)))))
+    n = int(round(math.exp(rng.uniform(math.log(256), math.log(65536)))))
+    eps = math.exp(rng.uniform(math.log(1e-3), math.log(1e-1)))
+    x, mu = quadrature(square_mesh(n_cells))
+    y = rng.uniform(0.0, 1.0, size=(n, 2))
+    return Problem(x, mu, y, np.full(n, 1.0 / n), eps, name=f"square{n_cells}_n{n}_small{i}")
+
+
 def random_psi(seed: int, n: int, scale: float) -> np.ndarray:
     return scale * np.random.default_rng(seed).standard_normal(n)
 

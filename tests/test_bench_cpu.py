@@ -26,7 +26,7 @@ def test_counter_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     summary.write_text(f"kernel source sha256: {sha}\n\n"
                        "k_pass1 HBM bytes per launch: 3.357301e+08\n"
                        "k_pass2 HBM bytes per launch: 7.373038e+08\n")
-    monkeypatch.setattr(bench, "EVAL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "EVAL_SOURCES", [str(src)])
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
     assert bench.counter_traffic("k_pass1") == 3.357301e+08
     assert bench.counter_traffic("k_pass2") == 7.373038e+08

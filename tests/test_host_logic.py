@@ -1,9 +1,11 @@
-"""Host-side schedules that the solves are driven by (no GPU): the eps
-schedule of Sec. 4.2 and the stage-to-level lists of the multilevel starts
-(Sec. 5.3, with the reading that runs the schedule on the coarsest level)."""
+"""Host-side logic (no GPU): the eps schedule of Sec. 4.2, the stage-to-level
+lists of the multilevel starts (Sec. 5.3, with the reading that runs the
+schedule on the coarsest level), the 64-bit widening of wave-uniform halves,
+and the shapes of the seeded workloads."""
 import math
 import os
 
+import numpy as np
 import pytest
 
 from paper_2507_23602_amd import warmstart
@@ -86,3 +88,36 @@ int main() {
                     str(exe)], check=True, capture_output=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
+
+
+@pytest.mark.parametrize("refinement,order", [(2, 1), (2, 2), (2, 3), (3, 3)])
+def test_gpu_size_workload_shapes_and_rule(refinement, order):
+    """The App. C workload: (2^(r+1))^3 cubes of [-1, 1]^3 with order^3 points
+    each and the ball target counts of its Table of problem sizes; the tensor
+    Gauss rule integrates x^(2 order - 1) and lower exactly (moments of the
+    uniform density on [-1, 1]: 1/3 for x^2, 1/5 for x^4), and the targets lie
+    in the unit ball."""
+    p = W.gpu_size(refinement, order)
+    table = {(2, 1): 512, (2, 2): 4096, (2, 3): 13824, (3, 3): 110592}
+    assert p.nq == table[(refinement, order)]
+    assert p.n == {2: 507, 3: 3817}[refinement]
+    assert abs(p.mu.sum() - 1.0) < 1e-14
+    assert np.all(np.abs(p.x) < 1.0)
+    assert np.all(np.linalg.norm(p.y, axis=1) <= 1.0)
+    for k in range(3):
+        assert abs((p.mu * p.x[:, k]).sum()) < 1e-14
+        if 2 * order - 1 >= 2:
+            assert abs((p.mu * p.x[:, k] ** 2).sum() - 1.0 / 3.0) < 1e-14
+        if 2 * order - 1 >= 4:
+            assert abs((p.mu * p.x[:, k] ** 4).sum() - 1.0 / 5.0) < 1e-14
+
+
+def test_truncation_study_inputs():
+    """The two densities of the truncation study share mesh, points and
+    targets; only the source masses differ (uniform: equal cell volumes, so
+    equal masses)."""
+    c, u = W.trunc_study("custom"), W.trunc_study("uniform")
+    assert c.nq == u.nq == 375000 and c.n == u.n == 14761
+    assert np.array_equal(c.x, u.x) and np.array_equal(c.y, u.y)
+    assert np.allclose(u.mu, 1.0 / u.nq, rtol=1e-12)
+    assert not np.allclose(c.mu, u.mu)
