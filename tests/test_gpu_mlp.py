@@ -55,6 +55,24 @@ def _model(seed=0, f=None):
     return m, th.astype(np.float64), norm
 
 
+def _abs_backward(cache, dout):
+    """The backward recursion of oracle.mlp with every factor replaced by its
+    magnitude: for each gradient element the sum of the magnitudes of the
+    terms it adds up, the scale of the rounding error it can carry."""
+    W, hs, zs = cache["W"], cache["h"], cache["z"]
+    NH = M.N_HIDDEN
+    d = np.abs(np.asarray(dout, dtype=np.float64))
+    G = {f"W{NH}": np.abs(hs[-1]).T @ d, f"b{NH}": np.array([d.sum()])}
+    dz = np.outer(d, np.abs(W[NH])) * np.abs(M.gelu_prime(zs[-1]))
+    for l in range(NH - 1, 0, -1):
+        G[f"W{l}"] = np.abs(hs[l - 1]).T @ dz
+        G[f"b{l}"] = dz.sum(axis=0)
+        dz = (dz @ np.abs(W[l]).T) * np.abs(M.gelu_prime(zs[l - 1]))
+    G["W0"] = np.abs(cache["F"]).T @ dz
+    G["b0"] = dz.sum(axis=0)
+    return M.pack(G)
+
+
 def _blocks():
     off, out = 0, {}
     for name, shape in M.layout():
@@ -106,12 +124,18 @@ def test_backward_matches_reference(R):
     ref = M.backward(th, c, dout.astype(np.float64) * norm[3])
     _, cf = M.forward(th, f.astype(np.float64), norm)
     ref64 = M.backward(th, cf, dout.astype(np.float64) * norm[3])
+    # element by element: each gradient entry within 5e-4 of the magnitude
+    # sum of its terms (FP32 sums: ~1e-6 of it; an activation whose bf16
+    # rounding flips moves its terms by 2^-8; measured worst 5e-5)
+    S = _abs_backward(c, dout.astype(np.float64) * norm[3])
     for name, sl in _blocks().items():
         e = np.linalg.norm(g[sl] - ref[sl]) / np.linalg.norm(ref[sl])
         e64 = np.linalg.norm(g[sl] - ref64[sl]) / np.linalg.norm(ref64[sl])
-        _say(f"  {name}: {e:.2e} (fp64 {e64:.2e})")
+        ratio = float(np.max(np.abs(g[sl] - ref[sl]) / (S[sl] + 1e-30)))
+        _say(f"  {name}: {e:.2e} (fp64 {e64:.2e}), worst element {ratio:.2e} of its term sum")
         assert e <= 2e-3, name
         assert e64 <= 2e-2, name
+        assert ratio <= 5e-4, name
 
 
 def test_adam_matches_reference_and_remakes_copies():
@@ -233,6 +257,39 @@ def test_invalid_arguments_are_rejected():
 
 def _small_instance(i):
     return W.config4_instance(i, n_cells=16, n_targets=512)
+
+
+def test_learned_start_on_held_out_instances():
+    """The learned warm start generalises: trained on the solutions of 128
+    blob instances (16 x 16 mesh, 512 targets), it starts 8 other instances
+    with fewer L-BFGS iterations to ||grad||_1 < 1e-6 than the zero start with
+    the eps schedule and than the combined multilevel start (Sec. 5.3), on
+    average, and its solutions pass the oracle's gradient check."""
+    import torch
+    from paper_2507_23602_amd import rsot, warmstart
+    train_ids, test_ids = list(range(3000, 3128)), list(range(3200, 3208))
+    feats, target, recs = warmstart.build_dataset(train_ids, n_cells=16, n_targets=512,
+                                                  every=64)
+    assert all(r["status"] == rsot.OK for r in recs)
+    m, log = warmstart.train(feats, target, epochs=60, batch=4096, lr=2e-3)
+    _say(f"  trained: final batch loss {log[-1]['train_batch_loss']:.3e}")
+    res = warmstart.compare(m, test_ids, n_cells=16, n_targets=512, coarse_cells=(4, 8),
+                            target_levels=(32, 128), keep_psi=len(test_ids))
+    s = warmstart.summarize(res)
+    _say(f"  {s}")
+    it = {k: s[k]["mean_iterations"] for k in ("zero_sched", "learned", "multilevel")}
+    assert s["learned_used"] >= 6
+    assert it["learned"] < it["zero_sched"] and it["learned"] < it["multilevel"]
+    for r in res:
+        assert r["learned"]["status"] == rsot.OK
+        p = W.config4_instance(r["id"], n_cells=16, n_targets=512)
+        g = oracle_grad_l1(p, r["learned"]["psi"])
+        assert g <= 1.5e-6, (r["id"], g)
+
+
+def oracle_grad_l1(p, psi):
+    import oracle
+    return float(np.abs(oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps).grad).sum())
 
 
 def test_solve_learned_uses_a_good_start_and_falls_back_on_a_bad_one():
