@@ -545,7 +545,9 @@ typedef struct {
  * stage of step l-1 (Eq. softmax_refinement_formula_combined), otherwise it is
  * kept. psi_out: HOST pointer, n_target of the finest level, centred.
  * mp->base must carry no checkpoint and no resume (INVALID_ARG): the levels
- * differ in size.
+ * differ in size. Problems other than the finest (source, target) pair run
+ * the FP32 pair loop whatever their size (fp64_below_points applies to the
+ * finest only): they warm-start the next level and stop at its tolerance.
  */
 rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_params *mp, double *psi_out,
                                   rsot_ml_info *info);

@@ -43,6 +43,11 @@ struct rsot_multilevel {
         }
         rsot_options o = opt;
         o.inputs_on_device = 1;
+        // a coarser (source, target) pair only warm-starts the next level and
+        // stops at the level tolerance: it keeps the FP32 pair loop whatever
+        // its size (the FP64 loop for small problems measured a third slower
+        // on the blob family's coarsest level, with the same iterations)
+        if (is != (int)nq.size() - 1 || it != (int)nt.size() - 1) o.fp64_below_points = 0;
         rsot_problem *p = nullptr;
         RSOT_TRY(rsot_problem_create(dim, nq[is], x[is], mu[is], nt[it], y[it], nu[it], &o,
                                      stream, &p));

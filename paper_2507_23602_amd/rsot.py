@@ -625,7 +625,7 @@ class Multilevel:
     """Combined source/target multilevel solver (Sec. 5.3)."""
 
     def __init__(self, sources, targets, *, cost_scale=0.5, precision="mixed",
-                 truncation="tile", tau=1e-12, tile_group=0):
+                 truncation="tile", tau=1e-12, tile_group=0, fp64_below_points=None):
         torch = _torch()
         lib = load_library()
         self._src = [(_dev_f64(x).reshape(len(m) if not isinstance(m, torch.Tensor) else m.numel(), -1),
@@ -640,8 +640,9 @@ class Multilevel:
         mp = (_P * ns)(*[m.data_ptr() for _, m in self._src])
         yp = (_P * nt)(*[y.data_ptr() for y, _ in self._tgt])
         vp = (_P * nt)(*[v.data_ptr() for _, v in self._tgt])
+        extra = {} if fp64_below_points is None else {"fp64_below_points": fp64_below_points}
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
-                              tau=tau, inputs_on_device=1, tile_group=tile_group)
+                              tau=tau, inputs_on_device=1, tile_group=tile_group, **extra)
         h = _P()
         _check(lib.rsot_multilevel_create(dim, ns, nq, xp, mp, nt, ntg, yp, vp, ctypes.byref(opt),
                                           _P(torch.cuda.current_stream().cuda_stream),
