@@ -29,9 +29,15 @@ Functions and the passage each follows:
   laguerre_areas_2d -- exact Laguerre-cell areas in the unit square by
                        half-plane clipping (no quadrature)
   two_target_mass   -- closed form of int_0^1 sigma((a - b x)/eps) dx
+  dual_eval_sphere, dual_eval_tile_sphere
+                    -- the same with the squared geodesic cost on the unit
+                       sphere, c = cost_scale d_g^2 (Sec. 6.4)
+  sphere_karcher_step -- one Riemannian-barycentre step per target with the
+                       plan's conditional measures held fixed (Alg. 5)
 
 Parity pins for every function are in tests/test_oracle_pins.py and
-tests/test_oracle_pins_cutoffs.py (two-sided cutoff windows, D).
+tests/test_oracle_pins_cutoffs.py (two-sided cutoff windows, D); the sphere
+functions in tests/test_oracle_pins_sphere.py.
 """
 from __future__ import annotations
 
@@ -91,6 +97,16 @@ def _load():
         lib.oracle_transport_maps.restype = _I
         lib.oracle_transport_maps.argtypes = [_I, _I64, _P, _I64, _P, _P, _P, _D, _D, _P, _P,
                                               _I64, _P, _D, _I, _P, _P, _P]
+        lib.oracle_dual_eval_sphere.restype = _I
+        lib.oracle_dual_eval_sphere.argtypes = [_I64, _P, _P, _I64, _P, _P, _P, _D, _D, _I,
+                                                _P, _P, _P]
+        lib.oracle_dual_eval_tile_sphere.restype = _I
+        lib.oracle_dual_eval_tile_sphere.argtypes = [_I64, _P, _P, _I64, _P, _P, _P, _D, _D,
+                                                     _P, _I64, _P, _I64, _D, _D, _I,
+                                                     _P, _P, _P, _P, _P]
+        lib.oracle_sphere_karcher_step.restype = _I
+        lib.oracle_sphere_karcher_step.argtypes = [_I64, _P, _P, _I64, _P, _P, _P, _D, _D, _P,
+                                                   _D, _I, _P, _P, _P]
         lib.oracle_dual_eval_tile.restype = _I
         lib.oracle_dual_eval_tile.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _D, _D,
                                               _P, _I64, _P, _I64, _D, _D, _I,
@@ -507,3 +523,72 @@ def _softplus(t):
 def two_target_mass(a, b, eps):
     """int_0^1 sigma((a - b s)/eps) ds = (eps/b)[softplus(a/eps) - softplus((a-b)/eps)]."""
     return (eps / b) * (_softplus(a / eps) - _softplus((a - b) / eps))
+
+
+# --------------------------------------------------------------------------
+# squared geodesic cost on the unit sphere (Sec. 6.4, Algs. 4-5)
+# --------------------------------------------------------------------------
+def dual_eval_sphere(x, mu, y, nu, psi, eps, cost_scale=1.0, want_grad=True, want_L=False,
+                     threads=0) -> EvalResult:
+    """J^h and grad J^h with c(x, y) = cost_scale arccos(x . y)^2 for unit
+    vectors x (nq x 3) and y (n x 3), dense."""
+    lib = _load()
+    x, mu, y, nu, psi = _c(x), _c(mu), _c(y), _c(nu), _c(psi)
+    nq, n = x.shape[0], y.shape[0]
+    J = ctypes.c_double(0.0)
+    grad = np.empty(n) if want_grad else None
+    L = np.empty(nq) if want_L else None
+    rc = lib.oracle_dual_eval_sphere(nq, _ptr(x), _ptr(mu), n, _ptr(y), _ptr(nu), _ptr(psi),
+                                     float(eps), float(cost_scale), int(threads),
+                                     ctypes.byref(J), _ptr(grad), _ptr(L))
+    if rc != 0:
+        raise ValueError("oracle_dual_eval_sphere: invalid arguments")
+    return EvalResult(J.value, grad, L, nq * n, 0)
+
+
+def dual_eval_tile_sphere(x, mu, y, nu, psi, eps, tile_of, n_tiles, block_of, n_blocks, tau,
+                          absJ_ref, cost_scale=1.0, want_L=False, want_keep=False,
+                          threads=0) -> EvalResult:
+    """The tile rule with the squared geodesic cost (geodesic bounds from the
+    chord bounds of the boxes; rule stated in rsot_oracle.c)."""
+    lib = _load()
+    x, mu, y, nu, psi = _c(x), _c(mu), _c(y), _c(nu), _c(psi)
+    tile_of = _c(tile_of, np.int32)
+    block_of = _c(block_of, np.int32)
+    nq, n = x.shape[0], y.shape[0]
+    J = ctypes.c_double(0.0)
+    kept = ctypes.c_int64(0)
+    grad = np.empty(n)
+    L = np.empty(nq) if want_L else None
+    keep = np.empty((n_tiles, n_blocks), dtype=np.uint8) if want_keep else None
+    rc = lib.oracle_dual_eval_tile_sphere(nq, _ptr(x), _ptr(mu), n, _ptr(y), _ptr(nu),
+                                          _ptr(psi), float(eps), float(cost_scale),
+                                          _ptr(tile_of), int(n_tiles), _ptr(block_of),
+                                          int(n_blocks), float(tau), float(absJ_ref),
+                                          int(threads), ctypes.byref(J), _ptr(grad), _ptr(L),
+                                          ctypes.byref(kept), _ptr(keep))
+    if rc != 0:
+        raise ValueError("oracle_dual_eval_tile_sphere: invalid arguments")
+    r = EvalResult(J.value, grad, L, kept.value, 0)
+    r.keep = keep
+    return r
+
+
+def sphere_karcher_step(x, mu, y_plan, nu, psi, eps, y_cur, alpha=0.5, cost_scale=1.0,
+                        threads=0):
+    """Alg. 5, one step for every target: returns (y_next, step_norm, mass)
+    with the conditional measures of the plan at (psi, y_plan) fixed and the
+    log/exp maps taken at y_cur."""
+    lib = _load()
+    x, mu, y_plan, nu, psi, y_cur = (_c(a) for a in (x, mu, y_plan, nu, psi, y_cur))
+    nq, n = x.shape[0], y_plan.shape[0]
+    y_next = np.empty((n, 3))
+    step = np.empty(n)
+    mass = np.empty(n)
+    rc = lib.oracle_sphere_karcher_step(nq, _ptr(x), _ptr(mu), n, _ptr(y_plan), _ptr(nu),
+                                        _ptr(psi), float(eps), float(cost_scale), _ptr(y_cur),
+                                        float(alpha), int(threads), _ptr(y_next), _ptr(step),
+                                        _ptr(mass))
+    if rc != 0:
+        raise ValueError("oracle_sphere_karcher_step: invalid arguments")
+    return y_next, step, mass

@@ -587,3 +587,311 @@ int oracle_transport_maps(int d, int64_t nq, const double *x, int64_t n, const d
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Squared geodesic cost on the unit sphere (Sec. 6.4, Algs. 4-5)           */
+/* ------------------------------------------------------------------------ */
+
+/* c(x, y) = cost_scale * d_g(x, y)^2, d_g = arccos(x . y) for unit vectors
+ * (the great-circle distance; Sec. 6.4 uses c = d_g^2) */
+static double sphere_angle(const double *x, const double *y)
+{
+    double t = x[0] * y[0] + x[1] * y[1] + x[2] * y[2];
+    if (t > 1.0) t = 1.0;
+    if (t < -1.0) t = -1.0;
+    return acos(t);
+}
+
+static double sphere_cost(const double *x, const double *y, double cost_scale)
+{
+    double a = sphere_angle(x, y);
+    return cost_scale * a * a;
+}
+
+/*
+ * Dual objective and gradient with the squared geodesic cost on the unit
+ * sphere, dense (Eqs. discretized_functional, discretized_gradient with
+ * c = cost_scale d_g^2). x: nq x 3 unit vectors, y: n x 3 unit vectors; the
+ * rest as oracle_dual_eval.
+ */
+int oracle_dual_eval_sphere(int64_t nq, const double *x, const double *mu, int64_t n,
+                            const double *y, const double *nu, const double *psi,
+                            double eps, double cost_scale, int nthreads, double *J_out,
+                            double *grad_out, double *L_out)
+{
+    if (nq < 0 || n < 1 || !(eps > 0.0)) return -1;
+    const int T = oracle_threads(nthreads);
+    double *gpart = (double *)calloc((size_t)T * (size_t)n, sizeof(double));
+    double *Jpart = (double *)calloc((size_t)T, sizeof(double));
+    if (!gpart || !Jpart) { free(gpart); free(Jpart); return -1; }
+#pragma omp parallel num_threads(T)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+        double *g = gpart + (size_t)tid * (size_t)n;
+        double Jt = 0.0;
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < nq; ++q) {
+            double zmax = -INFINITY;
+            for (int64_t j = 0; j < n; ++j) {
+                z[j] = (psi[j] - sphere_cost(x + q * 3, y + j * 3, cost_scale)) / eps + log(nu[j]);
+                if (z[j] > zmax) zmax = z[j];
+            }
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += exp(z[j] - zmax);
+            double L = zmax + log(s);
+            if (L_out) L_out[q] = L;
+            Jt += eps * L * mu[q];
+            if (grad_out)
+                for (int64_t j = 0; j < n; ++j) g[j] += mu[q] * exp(z[j] - L);
+        }
+        Jpart[tid] = Jt;
+        free(z);
+    }
+    double J = 0.0;
+    for (int t = 0; t < T; ++t) J += Jpart[t];
+    for (int64_t j = 0; j < n; ++j) J -= psi[j] * nu[j];
+    if (grad_out)
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int t = 0; t < T; ++t) s += gpart[(size_t)t * (size_t)n + j];
+            grad_out[j] = s - nu[j];
+        }
+    *J_out = J;
+    free(gpart); free(Jpart);
+    return 0;
+}
+
+/* geodesic length of a chord of Euclidean length d on the unit sphere */
+static double chord_to_angle(double d)
+{
+    double h = 0.5 * d;
+    if (h > 1.0) h = 1.0;
+    return 2.0 * asin(h);
+}
+
+/*
+ * The tile rule of oracle_dual_eval_tile with the squared geodesic cost. The
+ * boxes are axis-aligned boxes of the unit vectors in R^3; the geodesic
+ * distance increases with the chord, so the least chord between two boxes
+ * gives a lower bound of the cost, cost_scale (2 asin(dmin / 2))^2, and the
+ * largest chord from a target to a tile box an upper bound. Everything else
+ * (U_TB, B*, L_T, the threshold ln L_T + ln(eta / n_blocks)) as there.
+ */
+int oracle_dual_eval_tile_sphere(int64_t nq, const double *x, const double *mu, int64_t n,
+                                 const double *y, const double *nu, const double *psi,
+                                 double eps, double cost_scale, const int32_t *tile_of,
+                                 int64_t n_tiles, const int32_t *block_of, int64_t n_blocks,
+                                 double tau, double absJ_ref, int nthreads, double *J_out,
+                                 double *grad_out, double *L_out, int64_t *kept_out,
+                                 uint8_t *keep_out)
+{
+    if (n_tiles < 1 || n_blocks < 1 || n < 1 || !(eps > 0.0)) return -1;
+    double *tlo = (double *)malloc(sizeof(double) * (size_t)n_tiles * 3);
+    double *thi = (double *)malloc(sizeof(double) * (size_t)n_tiles * 3);
+    double *blo = (double *)malloc(sizeof(double) * (size_t)n_blocks * 3);
+    double *bhi = (double *)malloc(sizeof(double) * (size_t)n_blocks * 3);
+    double *bpsi = (double *)malloc(sizeof(double) * (size_t)n_blocks);
+    double *bnu = (double *)malloc(sizeof(double) * (size_t)n_blocks);
+    uint8_t *keep = (uint8_t *)calloc((size_t)n_tiles * (size_t)n_blocks, 1);
+    if (!tlo || !thi || !blo || !bhi || !bpsi || !bnu || !keep) return -1;
+    double summu = 0.0;
+    for (int64_t q = 0; q < nq; ++q) summu += mu[q];
+    for (int64_t t = 0; t < n_tiles * 3; ++t) { tlo[t] = INFINITY; thi[t] = -INFINITY; }
+    for (int64_t b = 0; b < n_blocks * 3; ++b) { blo[b] = INFINITY; bhi[b] = -INFINITY; }
+    for (int64_t b = 0; b < n_blocks; ++b) { bpsi[b] = -INFINITY; bnu[b] = 0.0; }
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t t = tile_of[q];
+        for (int k = 0; k < 3; ++k) {
+            double v = x[q * 3 + k];
+            if (v < tlo[t * 3 + k]) tlo[t * 3 + k] = v;
+            if (v > thi[t * 3 + k]) thi[t * 3 + k] = v;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t b = block_of[j];
+        for (int k = 0; k < 3; ++k) {
+            double v = y[j * 3 + k];
+            if (v < blo[b * 3 + k]) blo[b * 3 + k] = v;
+            if (v > bhi[b * 3 + k]) bhi[b * 3 + k] = v;
+        }
+        if (psi[j] > bpsi[b]) bpsi[b] = psi[j];
+        bnu[b] += nu[j];
+    }
+    const double ln_eta_over_nb = log(tau * absJ_ref / (eps * summu)) - log((double)n_blocks);
+    const int T = oracle_threads(nthreads);
+#pragma omp parallel for num_threads(T) schedule(static)
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        if (!(tlo[t * 3] <= thi[t * 3])) continue;
+        int64_t bstar = -1;
+        double ubest = -INFINITY;
+        double *lnU = (double *)malloc(sizeof(double) * (size_t)n_blocks);
+        for (int64_t b = 0; b < n_blocks; ++b) {
+            lnU[b] = -INFINITY;
+            if (!(bnu[b] > 0.0)) continue;
+            double dmin2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double gap = 0.0;
+                if (blo[b * 3 + k] > thi[t * 3 + k]) gap = blo[b * 3 + k] - thi[t * 3 + k];
+                else if (tlo[t * 3 + k] > bhi[b * 3 + k]) gap = tlo[t * 3 + k] - bhi[b * 3 + k];
+                dmin2 += gap * gap;
+            }
+            double a = chord_to_angle(sqrt(dmin2));
+            lnU[b] = log(bnu[b]) + (bpsi[b] - cost_scale * a * a) / eps;
+            if (lnU[b] > ubest) { ubest = lnU[b]; bstar = b; }
+        }
+        double lnL = -INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            if (block_of[j] != bstar) continue;
+            double dmax2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double a = fabs(y[j * 3 + k] - tlo[t * 3 + k]);
+                double c = fabs(y[j * 3 + k] - thi[t * 3 + k]);
+                double m = a > c ? a : c;
+                dmax2 += m * m;
+            }
+            double a = chord_to_angle(sqrt(dmax2));
+            double lb = log(nu[j]) + (psi[j] - cost_scale * a * a) / eps;
+            if (lb > lnL) lnL = lb;
+        }
+        for (int64_t b = 0; b < n_blocks; ++b) {
+            if (!(bnu[b] > 0.0)) continue;
+            int skip = (b != bstar) && (lnU[b] <= lnL + ln_eta_over_nb);
+            keep[t * n_blocks + b] = (uint8_t)!skip;
+        }
+        free(lnU);
+    }
+    double *gpart = (double *)calloc((size_t)T * (size_t)n, sizeof(double));
+    double *Jpart = (double *)calloc((size_t)T, sizeof(double));
+    int64_t *kpart = (int64_t *)calloc((size_t)T, sizeof(int64_t));
+#pragma omp parallel num_threads(T)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+        char *in = (char *)malloc((size_t)n);
+        double *g = gpart + (size_t)tid * (size_t)n;
+        double Jt = 0.0;
+        int64_t kt = 0;
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < nq; ++q) {
+            const uint8_t *row = keep + (size_t)tile_of[q] * (size_t)n_blocks;
+            double zmax = -INFINITY;
+            for (int64_t j = 0; j < n; ++j) {
+                in[j] = row[block_of[j]];
+                if (!in[j]) continue;
+                z[j] = (psi[j] - sphere_cost(x + q * 3, y + j * 3, cost_scale)) / eps + log(nu[j]);
+                if (z[j] > zmax) zmax = z[j];
+                ++kt;
+            }
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                if (in[j]) s += exp(z[j] - zmax);
+            double L = zmax + log(s);
+            if (L_out) L_out[q] = L;
+            Jt += eps * L * mu[q];
+            if (grad_out)
+                for (int64_t j = 0; j < n; ++j)
+                    if (in[j]) g[j] += mu[q] * exp(z[j] - L);
+        }
+        Jpart[tid] = Jt;
+        kpart[tid] = kt;
+        free(z);
+        free(in);
+    }
+    double J = 0.0;
+    int64_t kept = 0;
+    for (int t = 0; t < T; ++t) { J += Jpart[t]; kept += kpart[t]; }
+    for (int64_t j = 0; j < n; ++j) J -= psi[j] * nu[j];
+    if (grad_out)
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int t = 0; t < T; ++t) s += gpart[(size_t)t * (size_t)n + j];
+            grad_out[j] = s - nu[j];
+        }
+    *J_out = J;
+    if (kept_out) *kept_out = kept;
+    if (keep_out) memcpy(keep_out, keep, (size_t)n_tiles * (size_t)n_blocks);
+    free(tlo); free(thi); free(blo); free(bhi); free(bpsi); free(bnu); free(keep);
+    free(gpart); free(Jpart); free(kpart);
+    return 0;
+}
+
+/*
+ * One step of the Riemannian barycentre iteration (Alg. 5) for every target,
+ * with the conditional measures mu_j(x | psi) of the plan at (psi, y_plan)
+ * held fixed (Alg. 4 computes them once per Lloyd iteration):
+ *   w_qj   = mu_q p_qj(psi, y_plan)                 (the plan, Eq. final_plan_density)
+ *   log_y(x) = theta / sin(theta) (x - cos(theta) y),  theta = d_g(x, y)
+ *   delta_j = -2 sum_q w_qj log_{y_j}(x_q) / sum_q w_qj     (gradient of the
+ *             expected squared distance on the tangent space at y_j)
+ *   y_next_j = exp_{y_j}(-alpha delta_j),  exp_y(v) = cos|v| y + sin|v| v / |v|
+ * at the current points y_cur. Outputs y_next (n x 3), step_norm[j] = |delta_j|,
+ * mass_out[j] = sum_q w_qj (may be NULL). A target with no mass keeps its point.
+ */
+int oracle_sphere_karcher_step(int64_t nq, const double *x, const double *mu, int64_t n,
+                               const double *y_plan, const double *nu, const double *psi,
+                               double eps, double cost_scale, const double *y_cur,
+                               double alpha, int nthreads, double *y_next,
+                               double *step_norm, double *mass_out)
+{
+    if (nq < 0 || n < 1 || !(eps > 0.0)) return -1;
+    const int T = oracle_threads(nthreads);
+    double *acc = (double *)calloc((size_t)T * (size_t)n * 4, sizeof(double));
+    if (!acc) return -1;
+#pragma omp parallel num_threads(T)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *z = (double *)malloc(sizeof(double) * (size_t)n);
+        double *a = acc + (size_t)tid * (size_t)n * 4;
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < nq; ++q) {
+            const double *xq = x + q * 3;
+            double zmax = -INFINITY;
+            for (int64_t j = 0; j < n; ++j) {
+                z[j] = (psi[j] - sphere_cost(xq, y_plan + j * 3, cost_scale)) / eps + log(nu[j]);
+                if (z[j] > zmax) zmax = z[j];
+            }
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j) s += exp(z[j] - zmax);
+            const double L = zmax + log(s);
+            for (int64_t j = 0; j < n; ++j) {
+                const double w = mu[q] * exp(z[j] - L);
+                const double *yc = y_cur + j * 3;
+                const double th = sphere_angle(xq, yc);
+                const double ct = cos(th);
+                const double f = th > 0.0 ? th / sin(th) : 1.0;
+                for (int k = 0; k < 3; ++k) a[j * 4 + k] += w * f * (xq[k] - ct * yc[k]);
+                a[j * 4 + 3] += w;
+            }
+        }
+        free(z);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double lg[3] = {0.0, 0.0, 0.0}, m = 0.0;
+        for (int t = 0; t < T; ++t) {
+            const double *a = acc + ((size_t)t * (size_t)n + (size_t)j) * 4;
+            for (int k = 0; k < 3; ++k) lg[k] += a[k];
+            m += a[3];
+        }
+        const double *yc = y_cur + j * 3;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (m > 0.0)
+            for (int k = 0; k < 3; ++k) v[k] = -alpha * (-2.0 * lg[k] / m);
+        const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        for (int k = 0; k < 3; ++k)
+            y_next[j * 3 + k] = nv > 0.0 ? cos(nv) * yc[k] + sin(nv) * v[k] / nv : yc[k];
+        step_norm[j] = alpha > 0.0 ? nv / alpha : 0.0;
+        if (mass_out) mass_out[j] = m;
+    }
+    free(acc);
+    return 0;
+}

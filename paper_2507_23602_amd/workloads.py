@@ -470,6 +470,75 @@ def small_square_instance(i: int) -> Problem:
     return Problem(x, mu, y, np.full(n, 1.0 / n), eps, name=f"square{n_cells}_n{n}_small{i}")
 
 
+def icosphere(k: int) -> Mesh:
+    """Unit sphere: the icosahedron with every triangle split into four at its
+    edge midpoints k times, every vertex pushed onto the sphere (20 * 4^k
+    triangles)."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t),
+                  (0, -1, -t), (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)],
+                 dtype=np.float64)
+    f = np.array([(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9),
+                  (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2),
+                  (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+                  (8, 6, 7), (9, 8, 1)], dtype=np.int64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    for _ in range(k):
+        e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
+        e.sort(axis=1)
+        uniq, inv = np.unique(e, axis=0, return_inverse=True)
+        mid = 0.5 * (v[uniq[:, 0]] + v[uniq[:, 1]])
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        m = inv.reshape(3, -1).T + v.shape[0]           # midpoints of (01, 12, 20)
+        v = np.concatenate([v, mid])
+        a, b, c = f[:, 0], f[:, 1], f[:, 2]
+        ab, bc, ca = m[:, 0], m[:, 1], m[:, 2]
+        f = np.concatenate([np.stack([a, ab, ca], 1), np.stack([ab, b, bc], 1),
+                            np.stack([ca, bc, c], 1), np.stack([ab, bc, ca], 1)])
+    return Mesh(v, f)
+
+
+def sphere_quadrature(k: int, density: str = "harmonic"):
+    """Quadrature points and masses on the unit sphere: the degree-2 triangle
+    rule on each flat triangle of icosphere(k), the points pushed radially onto
+    the sphere, masses rho(x_q) |K| / 3 normalised to sum 1. density
+    "harmonic": rho = 1 + 0.9 P2(x_2), P2(z) = (3 z^2 - 1) / 2, the zonal
+    eigenfunction of the Laplace-Beltrami operator of degree 2 (the fifth
+    eigenvalue counted with multiplicity), shifted to stay positive;
+    "uniform": rho = 1."""
+    mesh = icosphere(k)
+    cv = mesh.verts[mesh.cells]                                   # (nc, 3, 3)
+    x = np.einsum("pk,ckd->cpd", TRI3_BARY, cv).reshape(-1, 3)
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    area = 0.5 * np.linalg.norm(np.cross(cv[:, 1] - cv[:, 0], cv[:, 2] - cv[:, 0]), axis=1)
+    w = np.repeat(area / 3.0, 3)
+    if density == "harmonic":
+        rho = 1.0 + 0.9 * 0.5 * (3.0 * x[:, 2] ** 2 - 1.0)
+    elif density == "uniform":
+        rho = np.ones_like(w)
+    else:
+        raise ValueError(density)
+    mu = rho * w
+    return np.ascontiguousarray(x), np.ascontiguousarray(mu / mu.sum())
+
+
+def sphere_points(seed: int, n: int) -> np.ndarray:
+    """n points uniform on the unit sphere (normalised Gaussian vectors)."""
+    v = np.random.default_rng(seed).standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def sphere_problem(k: int, n_targets: int, eps: float, density: str = "harmonic",
+                   seed: int = 40) -> Problem:
+    """Blue-noise / quantization workload on the unit sphere (Sec. 6.4):
+    icosphere(k) quadrature with the given density, n_targets points uniform on
+    the sphere (seed), nu = 1/N; squared geodesic cost."""
+    x, mu = sphere_quadrature(k, density)
+    y = sphere_points(seed, n_targets)
+    return Problem(x, mu, y, np.full(n_targets, 1.0 / n_targets), eps,
+                   name=f"sphere{k}_{density}_n{n_targets}_eps{eps:g}")
+
+
 def random_psi(seed: int, n: int, scale: float) -> np.ndarray:
     return scale * np.random.default_rng(seed).standard_normal(n)
 

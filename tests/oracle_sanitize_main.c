@@ -134,7 +134,62 @@ static void run(int d, int64_t nq, int64_t n, double eps) {
     free(tof); free(bof); free(keep); free(yf); free(pf);
 }
 
+int oracle_dual_eval_sphere(int64_t nq, const double *x, const double *mu, int64_t n,
+                            const double *y, const double *nu, const double *psi, double eps,
+                            double cost_scale, int nthreads, double *J_out, double *grad_out,
+                            double *L_out);
+int oracle_dual_eval_tile_sphere(int64_t nq, const double *x, const double *mu, int64_t n,
+                                 const double *y, const double *nu, const double *psi,
+                                 double eps, double cost_scale, const int32_t *tile_of,
+                                 int64_t n_tiles, const int32_t *block_of, int64_t n_blocks,
+                                 double tau, double absJ_ref, int nthreads, double *J_out,
+                                 double *grad_out, double *L_out, int64_t *kept_out,
+                                 uint8_t *keep_out);
+int oracle_sphere_karcher_step(int64_t nq, const double *x, const double *mu, int64_t n,
+                               const double *y_plan, const double *nu, const double *psi,
+                               double eps, double cost_scale, const double *y_cur,
+                               double alpha, int nthreads, double *y_next, double *step_norm,
+                               double *mass_out);
+
+/* unit vectors for the sphere functions */
+static void normalise_rows(double *v, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = sqrt(v[i * 3] * v[i * 3] + v[i * 3 + 1] * v[i * 3 + 1] + v[i * 3 + 2] * v[i * 3 + 2]);
+        for (int k = 0; k < 3; ++k) v[i * 3 + k] /= s;
+    }
+}
+
+static void run_sphere(int64_t nq, int64_t n, double eps)
+{
+    double *x = alloc_fill(nq * 3, -1.0, 1.0), *y = alloc_fill(n * 3, -1.0, 1.0);
+    normalise_rows(x, nq);
+    normalise_rows(y, n);
+    double *mu = alloc_fill(nq, 0.5, 1.5), *nu = alloc_fill(n, 0.5, 1.5);
+    double *psi = alloc_fill(n, -eps, eps), *g = alloc_fill(n, 0, 0), *L = alloc_fill(nq, 0, 0);
+    double J = 0.0;
+    int rc = oracle_dual_eval_sphere(nq, x, mu, n, y, nu, psi, eps, 1.0, 2, &J, g, L);
+    printf("sphere rc=%d J=%.15e\n", rc, J);
+    int64_t nt = (nq + 7) / 8, nb = (n + 3) / 4, kept = 0;
+    int32_t *tof = (int32_t *)malloc(sizeof(int32_t) * (size_t)nq);
+    int32_t *bof = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int64_t q = 0; q < nq; ++q) tof[q] = (int32_t)(q / 8);
+    for (int64_t j = 0; j < n; ++j) bof[j] = (int32_t)(j / 4);
+    uint8_t *keep = (uint8_t *)malloc((size_t)(nt * nb));
+    double Jt = 0.0;
+    rc = oracle_dual_eval_tile_sphere(nq, x, mu, n, y, nu, psi, eps, 1.0, tof, nt, bof, nb, 1e-8,
+                                      fabs(J), 2, &Jt, g, L, &kept, keep);
+    printf("sphere tile rc=%d J=%.15e kept=%ld\n", rc, Jt, (long)kept);
+    double *yn = alloc_fill(n * 3, 0, 0), *st = alloc_fill(n, 0, 0), *ms = alloc_fill(n, 0, 0);
+    rc = oracle_sphere_karcher_step(nq, x, mu, n, y, nu, psi, eps, 1.0, y, 0.5, 2, yn, st, ms);
+    printf("karcher rc=%d y0=%.15e step0=%.15e\n", rc, yn[0], st[0]);
+    free(x); free(y); free(mu); free(nu); free(psi); free(g); free(L); free(tof); free(bof);
+    free(keep); free(yn); free(st); free(ms);
+}
+
 int main(void) {
+    run_sphere(37, 11, 0.05);
+    run_sphere(1, 1, 0.1);
     run(2, 37, 11, 0.03);
     run(3, 29, 17, 0.05);
     run(2, 1, 1, 0.1);
