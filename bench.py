@@ -111,6 +111,8 @@ def main():
                          "(0: library default)")
     ap.add_argument("--trunc-study", type=int, default=1,
                     help="truncation-strategy study on both densities (0: skip)")
+    ap.add_argument("--sphere", type=int, default=1,
+                    help="blue-noise sampling and evaluation rate on the sphere (0: skip)")
     ap.add_argument("--trunc-tol", type=str, default="1e-3",
                     help="stopping tolerances of the truncation study, comma separated")
     ap.add_argument("--gpu-size", type=str, default="2-5x1-3",
@@ -366,6 +368,8 @@ def main():
         if args.trunc_study and not args.quick:
             tols = tuple(float(v) for v in args.trunc_tol.split(","))
             legs.append(("trunc_study", lambda: trunc_study_leg(tols=tols)))
+        if args.sphere and not args.quick:
+            legs.append(("sphere", sphere_leg))
         if args.gpu_size and not args.quick:
             rr, gg = args.gpu_size.split("x")
             r0, r1 = (int(v) for v in rr.split("-"))
@@ -813,6 +817,47 @@ def gpu_size_leg(spec, tol=1e-3, solve_below=2.5e11, solve_also=((5, 3),)):
         pr.close()
         out.append(row)
     return out
+
+
+def sphere_leg(eval_k=7, eval_n=65536):
+    """Sec. 6.4 on the unit sphere (squared geodesic cost, density 1 + 0.9 P2):
+    blue-noise sampling by Lloyd's algorithm with Riemannian barycentres
+    (Algs. 4-5) for N = 4..9 at eps = 1e-2 and tol 1e-3, as in the paper's
+    figure; then the evaluation rate of the sphere pair loop on icosphere(7)
+    (983,040 points) against 65,536 targets, dense, mixed and FP64, the
+    mixed gradient re-checked against the FP64 one."""
+    import torch
+    from paper_2507_23602_amd import rsot, sphere, workloads as W
+    x, mu = W.sphere_quadrature(4, "harmonic")
+    runs = []
+    for n in range(4, 10):
+        y0 = W.sphere_points(200 + n, n)
+        y, lg = sphere.lloyd(x, mu, y0, 1e-2, tol=1e-3)
+        runs.append({"n": n, "iterations": len(lg), "seconds": lg[-1]["seconds"],
+                     "W_start": -lg[0]["J"], "W_end": -lg[-1]["J"],
+                     "min_angle": float(sphere.pairwise_angles(y)[0])})
+        log(f"[bench] sphere blue noise N={n}: {len(lg)} Lloyd iterations, "
+            f"{lg[-1]['seconds']:.2f} s, W {-lg[0]['J']:.5f} -> {-lg[-1]['J']:.5f}")
+    p = W.sphere_problem(eval_k, eval_n, 1e-2, seed=40)
+    dev = [torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)]
+    psi = torch.as_tensor(W.random_psi(48, p.n, p.eps), device="cuda")
+    rates = {}
+    grads = {}
+    for prec in ("mixed", "fp64"):
+        pr = rsot.Problem(*dev, cost="sphere", cost_scale=1.0, precision=prec)
+        pr.dual_eval(psi, p.eps)
+        best = min(pr.dual_eval(psi, p.eps).info["kernel_ms"] for _ in range(3))
+        grads[prec] = pr.dual_eval(psi, p.eps).grad.clone()
+        rates[prec] = {"ms": best, "pairs_s": p.nq * p.n / (best * 1e-3)}
+        pr.close()
+    nu_t = torch.as_tensor(p.nu, device="cuda")
+    eg = torch.max(torch.abs(grads["mixed"] - grads["fp64"]) /
+                   (nu_t + grads["fp64"] + nu_t)).item()
+    log(f"[bench] sphere evaluation {p.name}: mixed {rates['mixed']['ms']:.1f} ms "
+        f"({rates['mixed']['pairs_s']:.3e} pairs/s), fp64 {rates['fp64']['ms']:.1f} ms; "
+        f"mixed vs fp64 e_g {eg:.1e}")
+    return {"blue_noise": runs, "eval_workload": p.name, "eval": rates,
+            "grad_err_mixed_vs_fp64": eg}
 
 
 def cpu_model():

@@ -77,6 +77,20 @@ typedef enum {
     RSOT_TRUNC_TILE = 4
 } rsot_truncation;
 
+/* The cost c(x, y).
+ * SQEUCLID: cost_scale |x - y|^2 (Sec. 2; cost_scale 1/2 is the paper's).
+ * SPHERE  : cost_scale d_g(x, y)^2 with d_g the great-circle distance on the
+ *           unit sphere, computed as 2 asin(|x - y| / 2) (Sec. 6.4 uses
+ *           c = d_g^2: cost_scale 1). Requires dim 3 and points and targets
+ *           of unit norm (| |v|^2 - 1 | <= 1e-9, else INVALID_ARG), and the
+ *           DENSE or TILE rule; the tile rule's box bounds pass through the
+ *           chord (the geodesic increases with it) and it culls whole blocks
+ *           (tile_group is ignored). Batched calls run such members one by
+ *           one; the moments, maps, refinement, multilevel and allocation-free
+ *           calls return INVALID_ARG for them (rsot_sphere_karcher_step is
+ *           the sphere's own moment call). */
+typedef enum { RSOT_COST_SQEUCLID = 0, RSOT_COST_SPHERE = 1 } rsot_cost;
+
 typedef struct {
     double cost_scale;        /* c(x,y) = cost_scale |x-y|^2; default 0.5         */
     int precision;            /* rsot_precision; default MIXED                     */
@@ -102,6 +116,7 @@ typedef struct {
                                  gets a smaller share of the budget tau |J|, so
                                  which keeps fewer pairs depends on the problem:
                                  rsot_autotune picks it                             */
+    int cost_kind;            /* rsot_cost; default SQEUCLID                        */
 } rsot_options;
 
 typedef struct rsot_problem rsot_problem;
@@ -363,6 +378,33 @@ rsot_status rsot_plan_moments(rsot_problem *p, double eps, const double *psi, do
  */
 rsot_status rsot_transport_maps(rsot_problem *p, double eps, const double *psi, double *bary_out,
                                 int32_t *modal_out, rsot_eval_info *info, double *kernel_ms);
+
+/*
+ * One step of the Riemannian barycentre iteration (Alg. 5) for every target,
+ * for a problem with the squared geodesic cost on the sphere (opt.cost_kind
+ * SPHERE). The conditional measures mu_j(x | psi) of the plan at (psi, the
+ * problem's targets) are held fixed (Alg. 4 computes them once per Lloyd
+ * iteration); the log and exp maps are taken at the current points y_cur:
+ *   delta_j  = -2 sum_q w_qj log_{y_cur_j}(x_q) / sum_q w_qj,  w_qj = mu_q p_qj
+ *   y_next_j = exp_{y_cur_j}(-alpha delta_j)
+ * with log_y(x) = theta / sin(theta) (x - cos(theta) y), theta = d_g(x, y),
+ * and exp_y(v) = cos|v| y + sin|v| v / |v|. alpha = 1/2 moves a point to the
+ * barycentre of the measure it sees when that measure is a single point.
+ *   psi        DEVICE, n_target doubles (caller order)
+ *   y_cur      DEVICE, n_target x 3 doubles (unit vectors, caller order)
+ *   y_next     DEVICE, n_target x 3 doubles (out; may alias nothing else)
+ *   step_norm  DEVICE, n_target doubles |delta_j| (out), or NULL
+ *   mass_out   DEVICE, n_target doubles sum_q w_qj = nu~_j (out), or NULL
+ *   info, kernel_ms  as for rsot_plan_moments
+ * The call evaluates J at psi first, under the problem's rule. A target with
+ * no mass keeps its point.
+ * Errors: INVALID_ARG (NULL, another cost, eps <= 0, alpha < 0), NONFINITE,
+ * DEVICE, OOM.
+ */
+rsot_status rsot_sphere_karcher_step(rsot_problem *p, double eps, const double *psi,
+                                     const double *y_cur, double alpha, double *y_next,
+                                     double *step_norm, double *mass_out, rsot_eval_info *info,
+                                     double *kernel_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Solver (Alg. 1): L-BFGS on J with an eps schedule (Sec. 4.2).            */

@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "librsot.so")
 ARCH = os.environ.get("RSOT_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["rsot_setup.hip", "rsot_eval.hip", "rsot_noalloc.hip", "rsot_moments.hip",
+           "rsot_sphere.hip",
            "rsot_solve.cpp", "rsot_multilevel.cpp", "rsot_hierarchy.hip", "rsot_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -293,6 +293,14 @@ __device__ __forceinline__ uint32_t chunk_mask(int64_t t, int64_t b,
 //   ln L_T = max_{j in B*} ln nu_j + (psi_j - cs dmax^2(T, y_j)) / eps (lower bound of S)
 //   keep (T,B) iff B = B* or ln U_TB > ln L_T + ln(eta / n_blocks),
 //   eta = tau |J_ref| / (eps sum mu): then J_dense - J_trunc <= tau |J_ref|.
+// With the squared geodesic cost on the unit sphere the boxes bound the
+// chord d; the geodesic 2 asin(d / 2) increases with it, so d^2 becomes
+// (2 asin(min(1, d / 2)))^2 in every bound.
+__device__ __forceinline__ double geo_of_chord2(double d2) {
+    const double a = 2.0 * asin(fmin(1.0, 0.5 * sqrt(d2)));
+    return a * a;
+}
+
 template <int D>
 __device__ __forceinline__ double tile_lnU(const double *__restrict__ tile_lo,
                                            const double *__restrict__ tile_hi,
@@ -300,7 +308,7 @@ __device__ __forceinline__ double tile_lnU(const double *__restrict__ tile_lo,
                                            const double *__restrict__ blk_hi,
                                            const double *__restrict__ blk_lnnu,
                                            const double *__restrict__ blk_stat, int64_t t,
-                                           int64_t b, double cs, double eps) {
+                                           int64_t b, double cs, double eps, bool sphere = false) {
     double dmin2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -308,6 +316,7 @@ __device__ __forceinline__ double tile_lnU(const double *__restrict__ tile_lo,
                                  blk_hi[b * 3 + k]);
         dmin2 += g * g;
     }
+    if (sphere) dmin2 = geo_of_chord2(dmin2);
     return blk_lnnu[b] + (blk_stat[b * 4 + 0] - cs * dmin2) / eps;
 }
 
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(256) void k_tile_ref(
     const int32_t *__restrict__ blk_cnt, const double *__restrict__ ty,
     const double *__restrict__ tnu, const double *__restrict__ tpsi, int64_t n_tiles,
     int64_t n_blocks, double cs, double eps, double ln_eta_nb, int32_t *__restrict__ bstar,
-    double *__restrict__ thr) {
+    double *__restrict__ thr, int sphere) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(256) void k_tile_ref(
     int64_t bi = INT64_MAX;
     for (int64_t b = lane; b < n_blocks; b += 64) {
         const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
-                                       cs, eps);
+                                       cs, eps, sphere != 0);
         if (lnU > best) {
             best = lnU;
             bi = b;
@@ -354,6 +363,7 @@ __global__ __launch_bounds__(256) void k_tile_ref(
             const double f = box_far_pt(tile_lo[t * 3 + k], tile_hi[t * 3 + k], ty[j * 3 + k]);
             dmax2 += f * f;
         }
+        if (sphere) dmax2 = geo_of_chord2(dmax2);
         lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) / eps;
     }
     const double th = wave_max(lb) + ln_eta_nb;
@@ -557,7 +567,8 @@ __global__ __launch_bounds__(256) void k_cull(
     uint16_t *__restrict__ cmask, int grp, const double *__restrict__ glo,
     const double *__restrict__ ghi, const double *__restrict__ glnnu,
     const double *__restrict__ gpsi, const int32_t *__restrict__ blk_cnt,
-    uint8_t *__restrict__ ccm, uint8_t *__restrict__ gm_out, const uint8_t *__restrict__ gm_in) {
+    uint8_t *__restrict__ ccm, uint8_t *__restrict__ gm_out, const uint8_t *__restrict__ gm_in,
+    int sphere) {
     const int lane = threadIdx.x & 63;
     const int64_t rs = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nrows = ROWS ? n_tiles : n_blocks, ncols = ROWS ? n_blocks : n_tiles;
@@ -606,7 +617,7 @@ __global__ __launch_bounds__(256) void k_cull(
                 }
             } else if (TILE) {
                 const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
-                                               blk_stat, t, b, cs, eps);
+                                               blk_stat, t, b, cs, eps, sphere != 0);
                 cls = (b == bstar[t] || lnU > thr[t]) ? PAIR_FULL : PAIR_SKIP;
             } else {
                 cls = cls_cutoff<D>(tile_lo + t * 3, tile_hi + t * 3, blk_lo + b * 3,
@@ -1626,6 +1637,20 @@ static void launch_passes(rsot_problem *p, int mode, bool grad, double kcs, int6
     else launch_pass2<D, F64, MODE_MASK>(p, n_wi, n_seg, seg);
 }
 
+// The squared geodesic cost on the sphere: its own pair kernels, the shared
+// merge (with no point term: the cost has no |x|^2 part) and reductions.
+static void launch_passes_sphere(rsot_problem *p, bool f64, int mode, bool grad, double kcs,
+                                 int64_t n_wi, int64_t n_seg, int64_t seg, const Pass1Work &pw) {
+    rsot_sphere_pass1(p, f64, mode, kcs, pw.n_items, pw.seg1, pw.n_seg1);
+    hipLaunchKernelGGL(k_pass1_combine, dim3((unsigned)((p->n_tiles + 3) / 4)), dim3(256), 0,
+                       p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
+                       mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
+                       p->n_tiles, 0.0, 0, pass_lcorr(p, f64), pass_corr(p, f64), p->qA,
+                       p->qlse, p->qkept, p->tile_ref, p->tile_part);
+    (void)hipEventRecord(p->ev_mid, p->stream);
+    if (grad) rsot_sphere_pass2(p, f64, mode, kcs, n_wi, n_seg, seg);
+}
+
 // Segments per row: enough (row, segment) wavefronts to fill the device
 // (16,384), each segment at least 64 columns.
 static void cull_segments(int64_t nrows, int64_t ncols, int *nseg, int64_t *seg_len) {
@@ -1640,6 +1665,7 @@ static void cull_segments(int64_t nrows, int64_t ncols, int *nseg, int64_t *seg_
 
 // Culling group of the tile rule: targets per group (64 = whole blocks)
 static int tile_group(const rsot_problem *p) {
+    if (p->opt.cost_kind == RSOT_COST_SPHERE) return 64;      // whole blocks only
     return p->opt.tile_group > 0 ? (int)p->opt.tile_group : RSOT_TILE_GROUP_DEFAULT;
 }
 
@@ -1736,7 +1762,8 @@ static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, 
                        p->blk_lnnu, p->blk_stat, p->tile_bstar, p->tile_thr, p->n_tiles,         \
                        p->n_blocks, nseg, seg_len, cs, eps, p->dscal, cnt, kb, pb, ptr, idx, cm, \
                        grp, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->blk_cnt,          \
-                       rows ? nullptr : p->col_cm, gm_out, gm_in)
+                       rows ? nullptr : p->col_cm, gm_out, gm_in,                                \
+                       p->opt.cost_kind == RSOT_COST_SPHERE ? 1 : 0)
 #define RSOT_CULL_F(DD, TT, RR)                                                                \
     do {                                                                                        \
         if (fill) RSOT_CULL(DD, TT, RR, true);                                                  \
@@ -1822,6 +1849,7 @@ static rsot_status plan_begin(EvalPlan &e) {
         hipLaunchKernelGGL(k_prep_targets<3>, gblk, dim3(256), 0, st, e.psi, p->tperm, p->ty,
                            p->tnu, p->tlog2nu, p->n_blocks, e.kappa, cs, p->trec, p->trec3,
                            p->tpsi, p->blk_stat);
+    if (p->opt.cost_kind == RSOT_COST_SPHERE) rsot_sphere_records(p, st, e.kappa);
     hipLaunchKernelGGL(k_pre_scalars, dim3(1), dim3(256), 0, st, p->blk_stat, p->n_blocks, e.rule,
                        eps, p->C0 < 0 ? 0.0 : p->C0, p->nu_min, p->nu_max, p->opt.tau,
                        p->absJ_ref, p->log_D_prev, p->opt.delta_thr, p->dscal);
@@ -1880,12 +1908,13 @@ static rsot_status plan_begin(EvalPlan &e) {
             hipLaunchKernelGGL(k_tile_ref<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
                                p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
-                               p->tile_bstar, p->tile_thr);
+                               p->tile_bstar, p->tile_thr, 0);
         else
             hipLaunchKernelGGL(k_tile_ref<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->blk_cnt, p->ty,
                                p->tnu, p->tpsi, p->n_tiles, p->n_blocks, cs, eps, ln_eta_nb,
-                               p->tile_bstar, p->tile_thr);
+                               p->tile_bstar, p->tile_thr,
+                               p->opt.cost_kind == RSOT_COST_SPHERE ? 1 : 0);
     } else {
         hipLaunchKernelGGL(k_target_G, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0, st,
                            p->tpsi, p->tlog2nu, p->tperm, p->n_pad, e.kappa, p->dscal, p->tG);
@@ -1994,7 +2023,9 @@ static void plan_passes(EvalPlan &e) {
     const bool f64 = rsot_pairs_fp64(p);
     const bool grad = e.grad != nullptr;
     (void)hipEventRecord(p->ev_p1, e.st);
-    if (p->dim == 2) {
+    if (p->opt.cost_kind == RSOT_COST_SPHERE) {
+        launch_passes_sphere(p, f64, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
+    } else if (p->dim == 2) {
         if (f64) launch_passes<2, true>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
         else launch_passes<2, false>(p, e.mode, grad, e.kcs, e.n_wi, e.n_seg, e.seg, e.pw);
     } else {
@@ -2187,7 +2218,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
     for (int i = 0; i < n; ++i) {
         EvalPlan &e = plans[(size_t)i];
         rsot_problem *p = e.p;
-        const bool batchable = !rsot_pairs_fp64(p) &&
+        const bool batchable = !rsot_pairs_fp64(p) && p->opt.cost_kind == RSOT_COST_SQEUCLID &&
                                (e.mode == MODE_DENSE || e.mode == MODE_LIST);
         if (!batchable) {
             plan_passes(e);
@@ -2669,6 +2700,7 @@ __global__ __launch_bounds__(256) void k_refine_reduce(const double *__restrict_
 
 rsot_status rsot_refine_impl(rsot_problem *p, double eps, const double *psi_coarse,
                              int64_t nf, const double *yf, double eta, double *psi_out) {
+    if (p->opt.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;
     // 1. coarse log-sum-exp L_q at the current points (objective pass only)
     double J = 0.0;
     rsot_eval_info info{};

@@ -201,6 +201,14 @@ rsot_status rsot_eval_impl(rsot_problem *p, double eps, const double *psi_dev, d
 // problem whose effective number of points is below opt.fp64_below_points
 bool rsot_pairs_fp64(const rsot_problem *p);
 
+// the squared geodesic cost on the sphere (rsot_sphere.hip): target records,
+// objective-pass and gradient-pass pair kernels on the evaluation's items
+void rsot_sphere_records(rsot_problem *p, hipStream_t st, double kappa);
+void rsot_sphere_pass1(rsot_problem *p, bool f64, int mode, double kcs, int64_t n_items,
+                       int64_t seg1, int64_t n_seg1);
+void rsot_sphere_pass2(rsot_problem *p, bool f64, int mode, double kcs, int64_t n_wi,
+                       int64_t n_seg, int64_t seg);
+
 // 1 / (1 + mean relative error of the FP32 exponential instruction) on the
 // current device, measured once per device (rsot_eval.hip)
 rsot_status rsot_device_exp_corr(hipStream_t st, double *corr);

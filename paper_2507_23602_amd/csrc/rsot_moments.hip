@@ -316,6 +316,7 @@ extern "C" rsot_status rsot_plan_moments(rsot_problem *p, double eps, const doub
                                          double *mass_out, double *first_out,
                                          rsot_eval_info *info, double *kernel_ms) {
     if (!p || !psi || (!mass_out && !first_out)) return RSOT_ERR_INVALID_ARG;
+    if (p->opt.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
     double J = 0.0;
     RSOT_TRY(rsot_eval_impl(p, eps, psi, &J, p->dgrad, info));
@@ -356,6 +357,7 @@ extern "C" rsot_status rsot_transport_maps(rsot_problem *p, double eps, const do
                                            double *bary_out, int32_t *modal_out,
                                            rsot_eval_info *info, double *kernel_ms) {
     if (!p || !psi || (!bary_out && !modal_out)) return RSOT_ERR_INVALID_ARG;
+    if (p->opt.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
     if (!p->tyf) {
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tyf, sizeof(float) * 4 * (size_t)p->n_pad));

@@ -83,6 +83,7 @@ extern "C" rsot_status rsot_multilevel_create(int dim, int n_source_levels, cons
     rsot_options o;
     rsot_options_default(&o);
     if (opt) o = *opt;
+    if (o.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;   // refinement is Euclidean
     auto *ml = new (std::nothrow) rsot_multilevel();
     if (!ml) return RSOT_ERR_OOM;
     ml->dim = dim;

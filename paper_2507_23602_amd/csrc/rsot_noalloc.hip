@@ -41,6 +41,7 @@ extern "C" rsot_status rsot_dual_eval_noalloc(rsot_problem *p, double eps, const
                                               double *J_out, double *grad_out,
                                               rsot_eval_info *info) {
     if (!p || !psi || !J_out) return RSOT_ERR_INVALID_ARG;
+    if (p->opt.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;
     if (!(eps > 0.0) || !std::isfinite(eps)) return RSOT_ERR_INVALID_ARG;
     if (p->opt.truncation != RSOT_TRUNC_DENSE) return RSOT_ERR_INVALID_ARG;
     double *s = nullptr;

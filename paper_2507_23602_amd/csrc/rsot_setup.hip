@@ -60,6 +60,7 @@ struct PointStats {
     double lo[3], hi[3];
     double wsum, wmin, wmax, w2sum;
     double nonfinite, badmass;
+    double unitdev;             // max | |v|^2 - 1 | (3D rows)
 };
 
 __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ x,
@@ -78,8 +79,14 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
     s.wmax = -INFINITY;
     s.nonfinite = 0;
     s.badmass = 0;
+    s.unitdev = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        if (dim == 3) {
+            const double r2 = x[i * 3] * x[i * 3] + x[i * 3 + 1] * x[i * 3 + 1] +
+                              x[i * 3 + 2] * x[i * 3 + 2];
+            s.unitdev = fmax(s.unitdev, fabs(r2 - 1.0));
+        }
         for (int k = 0; k < dim; ++k) {
             double v = x[i * dim + k];
             if (!isfinite(v)) {
@@ -110,6 +117,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
     s.wmax = wave_max(s.wmax);
     s.nonfinite = wave_sum(s.nonfinite);
     s.badmass = wave_sum(s.badmass);
+    s.unitdev = wave_max(s.unitdev);
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) red[wv] = s;
     __syncthreads();
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(256) void k_point_stats(const double *__restrict__ 
             r.wmax = fmax(r.wmax, red[i].wmax);
             r.nonfinite += red[i].nonfinite;
             r.badmass += red[i].badmass;
+            r.unitdev = fmax(r.unitdev, red[i].unitdev);
         }
         part[blockIdx.x] = r;
     }
@@ -147,6 +156,7 @@ __global__ __launch_bounds__(64) void k_point_stats_final(const PointStats *__re
         r.wmax = fmax(r.wmax, part[i].wmax);
         r.nonfinite += part[i].nonfinite;
         r.badmass += part[i].badmass;
+        r.unitdev = fmax(r.unitdev, part[i].unitdev);
     }
     *out = r;
 }
@@ -439,7 +449,13 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_TRY(rsot_device_exp_corr(p->stream, &p->exp_corr));
     p->nu_min = st.wmin;
     p->nu_max = st.wmax;
-    for (int k = 0; k < 3; ++k) p->shift[k] = k < p->dim ? 0.5 * (st.lo[k] + st.hi[k]) : 0.0;
+    // the sphere cost needs unit vectors (and keeps them unshifted)
+    if (p->opt.cost_kind == RSOT_COST_SPHERE && (sq.unitdev > 1e-9 || st.unitdev > 1e-9))
+        return RSOT_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        p->shift[k] = (k < p->dim && p->opt.cost_kind == RSOT_COST_SQEUCLID)
+                          ? 0.5 * (st.lo[k] + st.hi[k])
+                          : 0.0;
 
     int32_t *qorder = nullptr, *torder = nullptr;
     RSOT_TRY(sort_points(p, dx, nq, sq, &qorder));
@@ -604,6 +620,10 @@ static bool options_valid(const rsot_options &o) {
     if (o.tile_group != 0 && o.tile_group != 8 && o.tile_group != 16 && o.tile_group != 32 &&
         o.tile_group != 64)
         return false;
+    if (o.cost_kind != RSOT_COST_SQEUCLID && o.cost_kind != RSOT_COST_SPHERE) return false;
+    if (o.cost_kind == RSOT_COST_SPHERE && o.truncation != RSOT_TRUNC_DENSE &&
+        o.truncation != RSOT_TRUNC_TILE)
+        return false;
     return true;
 }
 
@@ -621,6 +641,7 @@ extern "C" rsot_status rsot_problem_create(int dim, int64_t n_quad, const double
     rsot_options_default(&o);
     if (opt) o = *opt;
     if (!options_valid(o)) return RSOT_ERR_INVALID_ARG;
+    if (o.cost_kind == RSOT_COST_SPHERE && dim != 3) return RSOT_ERR_INVALID_ARG;
     rsot_problem *p = new (std::nothrow) rsot_problem();
     if (!p) return RSOT_ERR_OOM;
     p->dim = dim;
@@ -703,6 +724,7 @@ extern "C" rsot_status rsot_set_reference(rsot_problem *p, double absJ_ref) {
 
 extern "C" rsot_status rsot_covering_cost(rsot_problem *p, double *C0_out) {
     if (!p || !C0_out) return RSOT_ERR_INVALID_ARG;
+    if (p->opt.cost_kind != RSOT_COST_SQEUCLID) return RSOT_ERR_INVALID_ARG;
     RSOT_TRY(rsot_compute_covering_cost(p));
     *C0_out = p->C0;
     return RSOT_OK;

@@ -39,6 +39,8 @@ TRUNC_TILE = 4
 _TRUNC_NAMES = {"dense": TRUNC_DENSE, "geom": TRUNC_GEOM, "int": TRUNC_INT, "pw": TRUNC_PW,
                 "tile": TRUNC_TILE}
 _PREC_NAMES = {"mixed": PREC_MIXED, "fp64": PREC_FP64}
+COST_SQEUCLID, COST_SPHERE = 0, 1
+_COST_NAMES = {"sqeuclid": COST_SQEUCLID, "sphere": COST_SPHERE}
 
 
 class RsotError(RuntimeError):
@@ -59,7 +61,7 @@ class Options(ctypes.Structure):
                 ("delta_thr", ctypes.c_double), ("inputs_on_device", ctypes.c_int),
                 ("seg_tiles", ctypes.c_int), ("seg_blocks", ctypes.c_int),
                 ("mem_limit_bytes", ctypes.c_int64), ("fp64_below_points", ctypes.c_int64),
-                ("tile_group", ctypes.c_int64)]
+                ("tile_group", ctypes.c_int64), ("cost_kind", ctypes.c_int)]
 
 
 class EvalInfo(ctypes.Structure):
@@ -204,6 +206,8 @@ SIGNATURES = {
                            ctypes.POINTER(_I), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "rsot_set_tuning": (_I, [_P, _I, _I, _I]),
     "rsot_get_tile_chunk_keep": (_I, [_P, _P]),
+    "rsot_sphere_karcher_step": (_I, [_P, _D, _P, _P, _D, _P, _P, _P, ctypes.POINTER(EvalInfo),
+                                      ctypes.POINTER(_D)]),
     "rsot_get_target_slots": (_I, [_P, _P]),
     "rsot_get_lse": (_I, [_P, _P]),
     "rsot_get_kept_counts": (_I, [_P, _P]),
@@ -316,7 +320,7 @@ class Problem:
 
     def __init__(self, x, mu, y, nu, *, cost_scale=0.5, precision="mixed", truncation="dense",
                  tau=1e-12, delta_thr=1e-12, seg_tiles=0, seg_blocks=0, mem_limit_bytes=0,
-                 fp64_below_points=None, tile_group=0, stream=None):
+                 fp64_below_points=None, tile_group=0, cost="sqeuclid", stream=None):
         torch = _torch()
         lib = load_library()
         on_dev = isinstance(x, torch.Tensor) and x.is_cuda
@@ -334,7 +338,8 @@ class Problem:
         opt = default_options(cost_scale=cost_scale, precision=precision, truncation=truncation,
                               tau=tau, delta_thr=delta_thr, inputs_on_device=int(on_dev),
                               seg_tiles=seg_tiles, seg_blocks=seg_blocks,
-                              mem_limit_bytes=mem_limit_bytes, tile_group=tile_group, **extra)
+                              mem_limit_bytes=mem_limit_bytes, tile_group=tile_group,
+                              cost_kind=_COST_NAMES[cost], **extra)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -446,6 +451,27 @@ class Problem:
         out = torch.empty((nt.value, nb.value), dtype=torch.uint8, device="cuda")
         _check(load_library().rsot_get_tile_keep(self._h, out.data_ptr()), "rsot_get_tile_keep")
         return out
+
+    def sphere_karcher_step(self, psi, eps, y_cur, alpha=0.5):
+        """Alg. 5, one step for every target (squared geodesic cost on the
+        sphere): the plan's conditional measures at (psi, the problem's
+        targets) with the log and exp maps at y_cur (n x 3 unit vectors).
+        Returns (y_next CUDA tensor n x 3, step norms |delta_j|, masses
+        nu~_j, kernel ms)."""
+        torch = _torch()
+        psi_t = _dev_f64(psi, self.n)
+        yc = _dev_f64(y_cur).reshape(self.n, 3).contiguous()
+        yn = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        st = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        ms = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info, kms = EvalInfo(), _D(0.0)
+        _check(load_library().rsot_sphere_karcher_step(self._h, float(eps), psi_t.data_ptr(),
+                                                       yc.data_ptr(), float(alpha),
+                                                       yn.data_ptr(), st.data_ptr(),
+                                                       ms.data_ptr(), ctypes.byref(info),
+                                                       ctypes.byref(kms)),
+               "rsot_sphere_karcher_step")
+        return yn, st, ms, kms.value
 
     def tile_chunk_keep(self):
         """Per (tile, block) of the last evaluation the bits of the block's

@@ -1,0 +1,209 @@
+"""GPU tests of the squared geodesic cost on the unit sphere (Sec. 6.4,
+Algs. 4-5) through the C ABI, against the oracle: dense and tile-rule
+evaluations (values, gradients, kept sets), the Riemannian barycentre step,
+and Lloyd's algorithm on the uniform sphere, whose 4- and 6-point optima are
+the regular tetrahedron and octahedron."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_23602_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# pair loop of each precision label: mixed (FP64 routing of small problems
+# left on), mixed_fp32 (the FP32 loop forced), fp64
+PREC = ["mixed", "mixed_fp32", "fp64"]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(p, prec, **kw):
+    from paper_2507_23602_amd import rsot
+    extra = {"fp64_below_points": 0} if prec == "mixed_fp32" else {}
+    return rsot.Problem(p.x, p.mu, p.y, p.nu, cost="sphere", cost_scale=1.0,
+                        precision="fp64" if prec == "fp64" else "mixed", **extra, **kw)
+
+
+def _grad_err(g, gref, nu):
+    return float(np.max(np.abs(g - gref) / (nu + (gref + nu))))
+
+
+def _check(r, ref, p, prec):
+    g = r.grad.cpu().numpy()
+    eg = _grad_err(g, ref.grad, p.nu)
+    dJ = abs(r.J - ref.J)
+    _say(f"  J {r.J:.15e} ref {ref.J:.15e} dJ {dJ:.1e} e_g {eg:.1e}")
+    if prec == "fp64" or r.info["fp64_pairs"]:
+        assert eg <= 1e-11 and dJ <= 1e-12 * abs(ref.J)
+    else:
+        assert eg <= 1e-6 and dJ <= 1.5e-7 * p.eps * p.mu.sum()
+
+
+@pytest.mark.parametrize("prec", PREC)
+def test_sphere_dense_parity(prec):
+    import torch
+    p = W.sphere_problem(4, 700, 2e-2, seed=41)
+    _say(f"sphere dense {p.name} {prec}")
+    prob = _problem(p, prec)
+    psi = W.random_psi(42, p.n, p.eps)
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    assert r.info["fp64_pairs"] == int(prec != "mixed_fp32")
+    ref = oracle.dual_eval_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps, want_L=True)
+    _check(r, ref, p, prec)
+    L = prob.lse().cpu().numpy()
+    el = float(np.max(np.abs(L - ref.L) / np.maximum(1.0, np.abs(ref.L))))
+    assert el <= (1e-12 if prec != "mixed_fp32" else 1e-6), el
+    # mass conservation: exact to rounding on the FP64 loop; the FP32
+    # exponential's residual bias on the FP32 loop (1e-9 of sum mu)
+    tol_sum = 1e-12 if r.info["fp64_pairs"] else 1e-9
+    assert abs(float(r.grad.sum().item()) - (p.mu.sum() - p.nu.sum())) < tol_sum
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
+def test_sphere_dense_probed_items(prec):
+    """Dense items of 32 blocks (one per tile): the objective pass seeds its
+    running maximum with probe pairs and skips pairs whose exponential
+    underflows; values and gradient as the oracle's, at eps = 2e-3 where
+    most pairs are skipped."""
+    import torch
+    p = W.sphere_problem(4, 2048, 2e-3, seed=49)
+    _say(f"sphere dense probed {p.name} {prec}")
+    prob = _problem(p, prec, seg_blocks=32)
+    psi = W.random_psi(50, p.n, p.eps)
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    ref = oracle.dual_eval_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps, want_L=True)
+    _check(r, ref, p, prec)
+    L = prob.lse().cpu().numpy()
+    el = float(np.max(np.abs(L - ref.L) / np.maximum(1.0, np.abs(ref.L))))
+    assert el <= (1e-12 if prec == "fp64" else 1e-6), el
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
+def test_sphere_tile_rule_parity(prec):
+    """The geodesic tile rule: the kept (tile, block) set byte for byte and
+    J, grad against the oracle's rule on the GPU's partition; App. B's bound
+    against the dense objective."""
+    import torch
+    p = W.sphere_problem(5, 2000, 5e-3, seed=43)
+    _say(f"sphere tile {p.name} {prec}")
+    tau = 1e-8
+    prob = _problem(p, prec, truncation="tile", tau=tau)
+    psi = W.random_psi(44, p.n, p.eps)
+    dense = oracle.dual_eval_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    prob.set_reference(abs(dense.J))
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    tile_of, block_of, nt, nb = prob.partition()
+    tile_of, block_of = tile_of.cpu().numpy(), block_of.cpu().numpy()
+    ref = oracle.dual_eval_tile_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, block_of,
+                                       nb, tau, abs(dense.J), want_keep=True)
+    keep = prob.tile_keep().cpu().numpy()
+    _say(f"  kept gpu {r.info['kept_pairs']} oracle {ref.kept} of {p.nq * p.n}")
+    assert 0 < ref.kept < p.nq * p.n
+    assert r.info["kept_pairs"] == ref.kept
+    assert np.array_equal(keep > 0, ref.keep > 0)
+    _check(r, ref, p, prec)
+    assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
+def test_sphere_karcher_step_parity(prec):
+    """One Alg. 5 step from points near the targets: new points, step norms
+    and masses against the oracle."""
+    import torch
+    p = W.sphere_problem(4, 300, 2e-2, seed=45)
+    prob = _problem(p, prec)
+    psi = W.random_psi(46, p.n, p.eps)
+    yc = p.y + 0.02 * np.random.default_rng(47).standard_normal(p.y.shape)
+    yc /= np.linalg.norm(yc, axis=1, keepdims=True)
+    yn, step, mass, ms = prob.sphere_karcher_step(psi, p.eps, torch.as_tensor(yc, device="cuda"),
+                                                  alpha=0.5)
+    ry, rs, rm = oracle.sphere_karcher_step(p.x, p.mu, p.y, p.nu, psi, p.eps, yc, alpha=0.5)
+    ey = float(np.max(np.abs(yn.cpu().numpy() - ry)))
+    es = float(np.max(np.abs(step.cpu().numpy() - rs) / np.maximum(rs, 1e-3)))
+    em = float(np.max(np.abs(mass.cpu().numpy() - rm) / (p.nu + rm)))
+    _say(f"  {prec}: y {ey:.1e}, step {es:.1e}, mass {em:.1e}, {ms:.3f} ms")
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert ey <= tol and es <= tol and em <= tol
+    assert np.allclose(np.linalg.norm(yn.cpu().numpy(), axis=1), 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,angles", [
+    (4, [math.acos(-1.0 / 3.0)] * 6),
+    (6, [math.pi / 2] * 12 + [math.pi] * 3)])
+def test_lloyd_on_the_uniform_sphere_finds_the_platonic_optimum(n, angles):
+    """Alg. 4 with Alg. 5 (eps = 1e-2 as in Sec. 6.4, tighter stopping) on the
+    uniform sphere from random points: 4 points end on a regular
+    tetrahedron and 6 on a regular octahedron (their pairwise great-circle
+    distances), and the final points are a fixed point of the oracle's step
+    under the oracle-checked potential."""
+    from paper_2507_23602_amd import rsot, sphere
+    x, mu = W.sphere_quadrature(4, "uniform")
+    y0 = W.sphere_points(100 + n, n)
+    # the icosphere quadrature keeps only a discrete symmetry group, so the
+    # last iterations drift slowly along an almost flat rotation direction:
+    # stop at 1e-5 relative motion (Sec. 6.4 stops at 1e-3)
+    y, log = sphere.lloyd(x, mu, y0, 1e-2, tol=1e-5, max_outer=400)
+    ang = sphere.pairwise_angles(y)
+    err = float(np.max(np.abs(ang - np.sort(angles))))
+    _say(f"  n={n}: {len(log)} Lloyd iterations, {log[-1]['seconds']:.2f} s, angle error {err:.1e}"
+         f", last rel_dy {log[-1]['rel_dy']:.1e}")
+    assert err < 2e-3
+    assert log[-1]["rel_dy"] <= 1e-5
+    prob = rsot.Problem(x, mu, y, np.full(n, 1.0 / n), cost="sphere", cost_scale=1.0,
+                        precision="fp64")
+    psi, info = prob.solve([1e-2], tol=1e-10)
+    r = oracle.dual_eval_sphere(x, mu, y, np.full(n, 1.0 / n), psi, 1e-2)
+    assert np.abs(r.grad).sum() < 1e-9
+    _, step, _ = oracle.sphere_karcher_step(x, mu, y, np.full(n, 1.0 / n), psi, 1e-2, y)
+    _say(f"  oracle barycentre step at the final points {float(step.max()):.1e}")
+    assert float(step.max()) < 1e-4
+
+
+def test_blue_noise_on_the_harmonic_density():
+    """The Sec. 6.4 setting (density 1 + 0.9 P2, eps = 1e-2, tol 1e-3) for
+    N = 4..9: Lloyd converges, and the quantization objective F(Y) =
+    W_eps(mu, nu(Y)) = J at the optimal potential ends below its value at
+    the random start."""
+    from paper_2507_23602_amd import sphere
+    x, mu = W.sphere_quadrature(4, "harmonic")
+    for n in range(4, 10):
+        y0 = W.sphere_points(200 + n, n)
+        y, log = sphere.lloyd(x, mu, y0, 1e-2, tol=1e-3)
+        _say(f"  N={n}: {len(log)} iterations, {log[-1]['seconds']:.2f} s, "
+             f"W_eps {-log[0]['J']:.6f} -> {-log[-1]['J']:.6f}")
+        assert log[-1]["rel_dy"] <= 1e-3
+        assert -log[-1]["J"] < -log[0]["J"]     # J = -W: the cost went down
+        assert np.allclose(np.linalg.norm(y, axis=1), 1.0, atol=1e-12)
+
+
+def test_sphere_rejections():
+    from paper_2507_23602_amd import rsot
+    p = W.sphere_problem(2, 20, 2e-2)
+    bad = p.x * 1.001
+    with pytest.raises(rsot.RsotError) as e:
+        rsot.Problem(bad, p.mu, p.y, p.nu, cost="sphere")
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    with pytest.raises(rsot.RsotError) as e:
+        rsot.Problem(p.x, p.mu, p.y, p.nu, cost="sphere", truncation="geom")
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    with pytest.raises(rsot.RsotError) as e:
+        rsot.Problem(p.x[:, :2], p.mu, p.y[:, :2], p.nu, cost="sphere")
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    prob = rsot.Problem(p.x, p.mu, p.y, p.nu, cost="sphere")
+    with pytest.raises(rsot.RsotError) as e:
+        prob.plan_moments(np.zeros(p.n), p.eps)
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    with pytest.raises(rsot.RsotError) as e:
+        prob.set_truncation("pw")
+    assert e.value.code == rsot.ERR_INVALID_ARG
+    eu = rsot.Problem(p.x, p.mu, p.y, p.nu)
+    with pytest.raises(rsot.RsotError) as e:
+        eu.sphere_karcher_step(np.zeros(p.n), p.eps, p.y)
+    assert e.value.code == rsot.ERR_INVALID_ARG
