@@ -480,6 +480,11 @@ typedef struct {
     double pass2_ms;            /* of which: gradient passes                       */
     double kept_frac;           /* mean fraction of pairs summed per evaluation    */
     int status;                 /* rsot_status of the solve                         */
+    int stalled_stages;         /* non-final eps stages that ended on a line-search
+                                   failure before stage_tol (no step improved J at
+                                   the pair loop's precision); the next stage
+                                   continues from the best iterate. A failure in
+                                   the final stage is the solve's status.        */
 } rsot_solve_info;
 
 void rsot_solve_params_default(rsot_solve_params *sp);
@@ -488,8 +493,10 @@ void rsot_solve_params_default(rsot_solve_params *sp);
  * Minimises J with L-BFGS (Alg. 1, Sec. 3.4) through the eps schedule
  * (Sec. 4.2), warm-starting each stage from the previous one.
  *   psi_inout HOST pointer, n_target doubles: warm start in (zeros allowed),
- *             solution out, centred so that sum_j nu_j psi_j = 0
- *             (App. A: the minimiser is unique up to a constant).
+ *             solution out, centred on success so that sum_j nu_j psi_j = 0
+ *             (App. A: the minimiser is unique up to a constant). On any
+ *             other status it is the last accepted iterate unshifted, so
+ *             that a resume continues from exactly that point.
  * With sp->checkpoint the solver state is written on every exit; with
  * sp->resume the solve continues from it (its stage, its L-BFGS pairs, its
  * |J| reference, its iteration count against max_iter) at psi_inout, which
@@ -578,6 +585,10 @@ typedef struct {
     double total_seconds;
     double grad_l1;
     int status;
+    int stalled_levels;       /* non-final steps whose solve ended on a line-search
+                                 failure before level_tol; the next step continues
+                                 from their best iterate, as after the iteration
+                                 cap. A failure in the final step is the status. */
 } rsot_ml_info;
 
 /*
@@ -585,7 +596,8 @@ typedef struct {
  * l = 0..Lmax solves on (T_is(l), nu^(it(l))); when it(l) = it(l-1)+1 the
  * potential is transferred by softmax refinement at the eps of the last
  * stage of step l-1 (Eq. softmax_refinement_formula_combined), otherwise it is
- * kept. psi_out: HOST pointer, n_target of the finest level, centred.
+ * kept. psi_out: HOST pointer, n_target of the finest level, centred when the
+ * final step succeeds.
  * mp->base must carry no checkpoint and no resume (INVALID_ARG): the levels
  * differ in size. Problems other than the finest (source, target) pair run
  * the FP32 pair loop whatever their size (fp64_below_points applies to the

@@ -121,7 +121,7 @@ typedef struct {
  * (2D problems only) is evaluated at the last eps of sp's schedule next to
  * psi = 0. If it is finite and gives the lower J, the solve runs at that eps
  * alone from the prediction; otherwise it runs sp's whole schedule from
- * zero. psi_out HOST n doubles (centred solution); info and linfo may be
+ * zero. psi_out HOST n doubles (centred on success); info and linfo may be
  * NULL. sp->checkpoint is written as in rsot_solve; sp->resume is rejected
  * (INVALID_ARG): the start is the prediction. Errors as rsot_solve.
  */

@@ -1455,19 +1455,36 @@ __global__ __launch_bounds__(256) void k_pass2_batched(const BatchDesc *__restri
 }
 
 // per target: merge the work-item partials in order, un-permute, norms
+// One workgroup per target block: wave v sums the block's item partials
+// v, v + 4, v + 8, ... in four interleaved accumulators (so that many loads
+// are in flight however many items a block has), the four wave sums are
+// added in a fixed order, and wave 0 writes the gradient and the block's
+// norm partials.
 __global__ __launch_bounds__(256) void k_grad_reduce(
     const double *__restrict__ gpart, const int64_t *__restrict__ wi_ptr, int64_t n_seg,
     const double *__restrict__ tnu, const int32_t *__restrict__ tperm, int64_t n_blocks,
     const double *__restrict__ dscal, double *__restrict__ grad_out,
     double *__restrict__ blk_gpart) {
+    __shared__ double red[4][64];
     const int lane = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x;
     if (b >= n_blocks) return;
     const int64_t j = b * 64 + lane;
     const int64_t w0 = wi_ptr ? wi_ptr[b] : b * n_seg;
     const int64_t w1 = wi_ptr ? wi_ptr[b + 1] : w0 + n_seg;
-    double nut = 0.0;
-    for (int64_t w = w0; w < w1; ++w) nut += gpart[w * 64 + lane];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t w = w0 + wv;
+    for (; w + 12 < w1; w += 16)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += gpart[(w + 4 * k) * 64 + lane];
+    if (w < w1) acc[0] += gpart[w * 64 + lane];
+    if (w + 4 < w1) acc[1] += gpart[(w + 4) * 64 + lane];
+    if (w + 8 < w1) acc[2] += gpart[(w + 8) * 64 + lane];
+    red[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (wv != 0) return;
+    const double nut = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     const double g = nut - tnu[j];
     const int32_t dst = tperm[j];
     const bool ok = dscal[SC_NONFINITE] == 0.0;
@@ -2040,9 +2057,8 @@ static rsot_status plan_finish(EvalPlan &e) {
     rsot_problem *p = e.p;
     const hipStream_t st = e.st;
     const bool grad = e.grad != nullptr;
-    const dim3 gblk((unsigned)((p->n_blocks + 3) / 4));
     if (grad)
-        hipLaunchKernelGGL(k_grad_reduce, gblk, dim3(256), 0, st, p->gpart,
+        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)p->n_blocks), dim3(256), 0, st, p->gpart,
                            e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi_ptr, e.n_seg,
                            p->tnu, p->tperm, p->n_blocks, p->dscal, e.grad, p->blk_gpart);
     hipLaunchKernelGGL(k_objective, dim3(1), dim3(256), 0, st, p->tile_part, p->n_tiles, e.eps,

@@ -213,7 +213,11 @@ extern "C" rsot_status rsot_solve_multilevel(rsot_multilevel *ml, const rsot_ml_
             inf.kept_frac[l] = si.kept_frac;
             inf.grad_l1 = si.grad_l1;
             absJ_prev = std::isfinite(si.J) ? std::fabs(si.J) : 0.0;   // 0: next level starts dense
-            if (s != RSOT_OK && !(s == RSOT_ERR_NOT_CONVERGED && !last)) status = s;
+            // a non-final step that stops short of level_tol (iteration cap or
+            // a line search that cannot improve its iterate) still warm-starts
+            // the next one; the final step's status is the solve's
+            if (s == RSOT_ERR_LINESEARCH && !last) ++inf.stalled_levels;
+            else if (s != RSOT_OK && !(s == RSOT_ERR_NOT_CONVERGED && !last)) status = s;
             eps_prev = eps_l.back();
         }
         inf.seconds[l] = secs(ts0, now());

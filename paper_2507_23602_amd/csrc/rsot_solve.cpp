@@ -460,7 +460,10 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
                 ls = line_search(ev, psi, J, g, dir, 1.0, sp.c1, sp.c2, sp.max_ls, np);
             }
             if (ls != RSOT_OK) {
-                st = ls;
+                // a non-final stage that cannot improve its iterate hands it
+                // to the next eps; the final stage reports the failure
+                if (ls == RSOT_ERR_LINESEARCH && !final_stage) ++inf.stalled_stages;
+                else st = ls;
                 break;
             }
             // history pair (sv, yv persist across iterations; the pair that
@@ -531,8 +534,10 @@ extern "C" rsot_status rsot_solve(rsot_problem *p, const rsot_solve_params *sp_i
             break;
         }
     }
-    // centre the potential: sum_j nu_j psi_j = 0
-    {
+    // centre the potential on success: sum_j nu_j psi_j = 0. Any other exit
+    // returns the last accepted iterate as the solver holds it, so that a
+    // resumed solve continues from exactly that point.
+    if (status == RSOT_OK) {
         std::vector<double> nu(n);
         std::vector<int32_t> perm((size_t)p->n_pad);
         std::vector<double> tnu((size_t)p->n_pad);

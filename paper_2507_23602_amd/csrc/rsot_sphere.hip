@@ -313,25 +313,45 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
     for (int k = 0; k < 4; ++k) kpart[(it.w * 64 + lane) * 4 + k] = a[k];
 }
 
-// per target: the items' sums in order, then delta = -2 sum w log / sum w and
+// One workgroup per target block: wave v sums the items v, v + 4, ... of
+// the block's four-component partials, the wave sums are added in a fixed
+// order; then per target delta = -2 sum w log / sum w and
 // y_next = exp_{y_cur}(-alpha delta), exp_y(v) = cos|v| y + sin|v| v / |v|
 __global__ __launch_bounds__(256) void k_sphere_karcher_update(
     const double *__restrict__ kpart, const int64_t *__restrict__ wi_ptr, int64_t n_seg,
     const int32_t *__restrict__ tperm, const double *__restrict__ y_cur, int64_t n_blocks,
     double alpha, double *__restrict__ y_next, double *__restrict__ step_norm,
     double *__restrict__ mass_out) {
+    __shared__ double4 red[4][64];
     const int lane = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x;
     if (b >= n_blocks) return;
     const int64_t j = b * 64 + lane;
-    const int32_t dst = tperm[j];
-    if (dst < 0) return;
     const int64_t w0 = wi_ptr ? wi_ptr[b] : b * n_seg;
     const int64_t w1 = wi_ptr ? wi_ptr[b + 1] : w0 + n_seg;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t w = w0; w < w1; ++w)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] += kpart[(w * 64 + lane) * 4 + k];
+    const double4 *kp = reinterpret_cast<const double4 *>(kpart);
+    double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int64_t w = w0 + wv; w < w1; w += 4) {
+        const double4 v = kp[w * 64 + lane];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+    }
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv != 0) return;
+    const int32_t dst = tperm[j];
+    if (dst < 0) return;
+    double a[4];
+    {
+        const double4 r0 = red[0][lane], r1 = red[1][lane], r2 = red[2][lane], r3 = red[3][lane];
+        a[0] = (r0.x + r1.x) + (r2.x + r3.x);
+        a[1] = (r0.y + r1.y) + (r2.y + r3.y);
+        a[2] = (r0.z + r1.z) + (r2.z + r3.z);
+        a[3] = (r0.w + r1.w) + (r2.w + r3.w);
+    }
     const double *yc = y_cur + (int64_t)dst * 3;
     double v[3] = {0.0, 0.0, 0.0};
     if (a[3] > 0.0)
@@ -435,7 +455,7 @@ extern "C" rsot_status rsot_sphere_karcher_step(rsot_problem *p, double eps, con
         else RSOT_SK(false, MODE_LIST);
     }
 #undef RSOT_SK
-    hipLaunchKernelGGL(k_sphere_karcher_update, dim3((unsigned)((p->n_blocks + 3) / 4)), dim3(256),
+    hipLaunchKernelGGL(k_sphere_karcher_update, dim3((unsigned)p->n_blocks), dim3(256),
                        0, p->stream, p->mpart,
                        mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi_ptr, n_seg, p->tperm,
                        y_cur, p->n_blocks, alpha, y_next, step_norm, mass_out);

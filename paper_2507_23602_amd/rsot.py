@@ -134,7 +134,8 @@ class SolveInfo(ctypes.Structure):
                 ("grad_linf", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("eval_ms", ctypes.c_double), ("cull_ms", ctypes.c_double),
                 ("pass1_ms", ctypes.c_double), ("pass2_ms", ctypes.c_double),
-                ("kept_frac", ctypes.c_double), ("status", ctypes.c_int)]
+                ("kept_frac", ctypes.c_double), ("status", ctypes.c_int),
+                ("stalled_stages", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -156,7 +157,8 @@ class MLInfo(ctypes.Structure):
                 ("refine_seconds", ctypes.c_double * ML_MAX),
                 ("refine_pairs", ctypes.c_int64 * ML_MAX), ("eval_ms", ctypes.c_double * ML_MAX),
                 ("kept_frac", ctypes.c_double * ML_MAX), ("total_seconds", ctypes.c_double),
-                ("grad_l1", ctypes.c_double), ("status", ctypes.c_int)]
+                ("grad_l1", ctypes.c_double), ("status", ctypes.c_int),
+                ("stalled_levels", ctypes.c_int)]
 
     def as_dict(self):
         n = self.n_steps
@@ -164,7 +166,7 @@ class MLInfo(ctypes.Structure):
                                                      "evaluations", "seconds", "refine_seconds",
                                                      "refine_pairs", "eval_ms", "kept_frac"]}
         d.update(n_steps=n, total_seconds=self.total_seconds, grad_l1=self.grad_l1,
-                 status=self.status)
+                 status=self.status, stalled_levels=self.stalled_levels)
         return d
 
 

@@ -252,6 +252,16 @@ def test_flipped_gradient_ends_with_line_search_error():
     assert err.code == rsot.ERR_LINESEARCH
     assert err.info["iterations"] == 0
     assert err.info["evaluations"] <= 2 + 8
+    assert err.info["stalled_stages"] == 0
+    assert np.all(err.psi == 0.0)
+    # two eps stages: the first stalls and hands its (unchanged) iterate on,
+    # the final one reports the failure
+    with pytest.raises(rsot.RsotError) as e:
+        prob.solve([2 * p.eps, p.eps], tol=1e-9, max_ls=8, test_flip_gradient=True)
+    err = e.value
+    assert err.code == rsot.ERR_LINESEARCH
+    assert err.info["stalled_stages"] == 1 and err.info["stages"] == 2
+    assert err.info["iterations"] == 0
     assert np.all(err.psi == 0.0)
 
 
