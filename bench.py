@@ -394,7 +394,16 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, psi.cpu().numpy(), psi1)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=json_value), flush=True)
+
+
+def json_value(v):
+    """numpy scalars and arrays in the result line as plain numbers and lists"""
+    if isinstance(v, np.ndarray):
+        return v.tolist()
+    if isinstance(v, np.generic):
+        return v.item()
+    raise TypeError(f"{type(v).__name__} in the result line")
 
 
 def fp64_recheck(p, psi, n_sample=256, seed=0):
@@ -595,10 +604,10 @@ def batched_leg(k):
                                     1e-12, infos[i]["absJ_ref"],
                                     threads=int(os.environ.get("OMP_NUM_THREADS",
                                                                os.cpu_count() or 1)))
-        g = grads[i].cpu().numpy()
+        gi = grads[i].cpu().numpy()
         checks.append({"instance": i, "nq": q.nq, "n": q.n, "tile_group": g,
                        "J_rel_err": abs(J[i] - ref.J) / abs(ref.J),
-                       "grad_err": float(np.max(np.abs(g - ref.grad) / (q.nu + ref.grad + q.nu))),
+                       "grad_err": float(np.max(np.abs(gi - ref.grad) / (q.nu + ref.grad + q.nu))),
                        "kept_equal": infos[i]["kept_pairs"] == ref.kept})
     res["oracle_check"] = checks
     worst_j = max(c["J_rel_err"] for c in checks)

@@ -43,3 +43,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout == ""                                       # no JSON line
+
+
+def test_result_line_takes_numpy_values():
+    """The one JSON line is printed whatever numpy scalars or arrays a leg
+    leaves in its results; anything else still fails loudly."""
+    import json
+
+    import numpy as np
+    import pytest
+    import bench
+    out = {"a": np.float64(1.5), "b": np.int32(3), "c": np.arange(3), "d": [np.float32(0.25)]}
+    assert json.loads(json.dumps(out, default=bench.json_value)) == \
+        {"a": 1.5, "b": 3, "c": [0, 1, 2], "d": [0.25]}
+    with pytest.raises(TypeError):
+        json.dumps({"x": object()}, default=bench.json_value)
