@@ -74,6 +74,38 @@ __device__ __forceinline__ double sphere_z(const GeoPoly &P, double s, double B)
     return fma(-P.kcs * t, t, B);
 }
 
+// H(v) = theta / sin(theta) of the logarithmic map (degree 20 for the FP64
+// loop, 16 for the FP32-exponential loop), unscaled
+struct LogPoly {
+    double c[RSOT_LOGMAP_DEG20 + 1];
+};
+
+// theta / sin(theta) for the squared chord s of x and y: the polynomial on
+// the near hemisphere; on the far one theta = pi - d' (d' from the antipode's
+// chord u = 4 - s) over sin(theta) = sqrt(s u) / 2, and 0 at the antipode
+// itself, where the logarithmic map is undefined
+template <bool F64>
+__device__ __forceinline__ double theta_over_sin(const GeoPoly &P, const LogPoly &H, double s) {
+    if (s <= 2.0) {
+        constexpr int N = F64 ? RSOT_LOGMAP_DEG20 : RSOT_LOGMAP_DEG16;
+        double f = H.c[N];
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) f = fma(f, s, H.c[i]);
+        return f;
+    }
+    const double u = fmax(4.0 - s, 0.0);
+    if (!(u > 1e-300)) return 0.0;
+    const double th = M_PI - sqrt(u * geo_F<F64>(P, u) * P.neg_inv_kcs);
+    return 2.0 * th / sqrt(s * u);
+}
+
+LogPoly log_poly(bool f64) {
+    LogPoly H{};
+    const int n = f64 ? RSOT_LOGMAP_DEG20 : RSOT_LOGMAP_DEG16;
+    for (int i = 0; i <= n; ++i) H.c[i] = f64 ? rsot_logmap_poly20[i] : rsot_logmap_poly16[i];
+    return H;
+}
+
 GeoPoly geo_poly(bool f64, double kcs) {
     GeoPoly P{};
     const int n = f64 ? RSOT_GEO_DEG18 : RSOT_GEO_DEG14;
@@ -260,8 +292,9 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
 
 // Alg. 5, the sums of one step: per target j (lane) over the item's tiles,
 // the plan weight w_qj = mu_q p_qj at (psi, y_plan) (the gradient pass's
-// term) times the log map at the current point y_cur_j,
-//   log_y(x) = theta / sin(theta) (x - cos(theta) y),  theta = d_g(x, y),
+// term, with its underflow skip) times the log map at the current point
+// y_cur, log_y(x) = theta / sin(theta) (x - cos(theta) y) with
+// cos(theta) = x.y and theta / sin(theta) from the squared chord 2 - 2 x.y,
 // summed in FP64 with the weight's FP32 or FP64 exponential; and the weight.
 template <bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_sphere_karcher(
@@ -270,7 +303,7 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
     const double *__restrict__ y_cur, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
     const uint32_t *__restrict__ col_idx, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
-    int64_t n_seg, int64_t seg, const GeoPoly P, double *__restrict__ kpart) {
+    int64_t n_seg, int64_t seg, const GeoPoly P, const LogPoly H, double *__restrict__ kpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Item it = col_item<MODE>(wave, wi_block, wi_range, perm, n_tiles, n_blocks, n_wi,
@@ -295,14 +328,11 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
             const double v = sphere_z<F64>(P, sc, bq);
             const double wgt = F64 ? exp2(v) : (double)__builtin_amdgcn_exp2f((float)v);
             if (!(wgt > 0.0)) continue;
-            const double d0 = r.x - yc[0], d1 = r.y - yc[1], d2 = r.z - yc[2];
-            const double h = 0.5 * sqrt(fma(d0, d0, fma(d1, d1, d2 * d2)));
-            const double th = 2.0 * asin(fmin(h, 1.0));
-            const double ct = cos(th);
-            const double f = th > 0.0 ? th / sin(th) : 1.0;
-            at[0] += wgt * f * (r.x - ct * yc[0]);
-            at[1] += wgt * f * (r.y - ct * yc[1]);
-            at[2] += wgt * f * (r.z - ct * yc[2]);
+            const double ct = fma(r.x, yc[0], fma(r.y, yc[1], r.z * yc[2]));
+            const double wf = wgt * theta_over_sin<F64>(P, H, fma(-2.0, ct, 2.0));
+            at[0] = fma(wf, fma(-ct, yc[0], r.x), at[0]);
+            at[1] = fma(wf, fma(-ct, yc[1], r.y), at[1]);
+            at[2] = fma(wf, fma(-ct, yc[2], r.z), at[2]);
             at[3] += wgt;
         }
         const double sc = tref[t].y;
@@ -440,12 +470,13 @@ extern "C" rsot_status rsot_sphere_karcher_step(rsot_problem *p, double eps, con
     const int64_t n_wi = p->last_n_wi, n_seg = p->last_n_seg, seg = p->last_seg;
     RSOT_TRY(grow_buf(p, &p->mpart, &p->mpart_cap, (size_t)std::max<int64_t>(n_wi, 1) * 64 * 4));
     const GeoPoly P = geo_poly(f64, p->last_kcs);
+    const LogPoly H = log_poly(f64);
     const unsigned grid = col_grid(p, mode, n_wi, n_seg);
     RSOT_HIP(hipEventRecord(p->ev0, p->stream));
 #define RSOT_SK(F, M)                                                                          \
     hipLaunchKernelGGL((k_sphere_karcher<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,    \
                        p->tile_ref, p->trec, p->tperm, y_cur, p->wi_block, p->wi_range,          \
-                       p->wi_perm, p->col_idx, p->n_tiles, p->n_blocks, n_wi, n_seg, seg, P,     \
+                       p->wi_perm, p->col_idx, p->n_tiles, p->n_blocks, n_wi, n_seg, seg, P, H,  \
                        p->mpart)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SK(true, MODE_DENSE);

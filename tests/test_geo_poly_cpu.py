@@ -13,10 +13,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "paper_2507_23602_amd", "csrc", "rsot_geo_poly.h")
 
 
-def _coeffs():
+def _coeffs(name="geo"):
     txt = open(HEADER).read()
     out = {}
-    for deg, body in re.findall(r"rsot_geo_poly(\d+)\[\d+\] = \{(.*?)\};", txt, flags=re.S):
+    for deg, body in re.findall(r"rsot_" + name + r"_poly(\d+)\[\d+\] = \{(.*?)\};", txt,
+                                flags=re.S):
         out[int(deg)] = [float(v) for v in body.replace("\n", " ").split(",")]
     return out
 
@@ -84,3 +85,19 @@ def test_pairs_against_acos_on_both_hemispheres():
             far += u < 2.0
         assert worst < tol, (deg, worst)
     assert far > 3000                     # both branches exercised
+
+
+def test_log_map_factor_against_sin():
+    """theta / sin(theta) of the logarithmic map from the squared chord, on
+    the near hemisphere (s <= 2), against asin and sin; H(0) = 1 and
+    H(2) = pi / 2."""
+    c = _coeffs("logmap")
+    assert sorted(c) == [16, 20]
+    for deg, tol in ((16, 1e-13), (20, 2e-15)):
+        assert abs(_F(c[deg], 0.0) - 1.0) < tol
+        assert abs(_F(c[deg], 2.0) - math.pi / 2.0) < tol
+        worst = 0.0
+        for s in np.linspace(1e-6, 2.0, 2001):
+            th = 2.0 * math.asin(math.sqrt(s) / 2.0)
+            worst = max(worst, abs(_F(c[deg], s) - th / math.sin(th)))
+        assert worst < tol, (deg, worst)
