@@ -79,9 +79,12 @@ typedef enum {
 
 /* The cost c(x, y).
  * SQEUCLID: cost_scale |x - y|^2 (Sec. 2; cost_scale 1/2 is the paper's).
- * SPHERE  : cost_scale d_g(x, y)^2 with d_g the great-circle distance on the
- *           unit sphere, computed as 2 asin(|x - y| / 2) (Sec. 6.4 uses
- *           c = d_g^2: cost_scale 1). Requires dim 3 and points and targets
+ * SPHERE  : cost_scale d_g(x, y)^2 with d_g = acos(x.y) the great-circle
+ *           distance on the unit sphere (Sec. 6.4 uses c = d_g^2: cost_scale
+ *           1). The pair loops evaluate d_g^2 as a polynomial in the squared
+ *           chord 2 - 2 x.y (absolute error below 3e-13 where the exponential
+ *           is FP32, a few FP64 rounding units on the FP64 loop), through the
+ *           antipode on the far hemisphere. Requires dim 3 and points and targets
  *           of unit norm (| |v|^2 - 1 | <= 1e-9, else INVALID_ARG), and the
  *           DENSE or TILE rule; the tile rule's box bounds pass through the
  *           chord (the geodesic increases with it) and it culls whole blocks

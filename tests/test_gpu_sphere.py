@@ -209,3 +209,33 @@ def test_sphere_rejections():
     with pytest.raises(rsot.RsotError) as e:
         eu.sphere_karcher_step(np.zeros(p.n), p.eps, p.y)
     assert e.value.code == rsot.ERR_INVALID_ARG
+
+
+def test_sphere_member_in_a_batched_call():
+    """A batch mixing a sphere problem with squared Euclidean ones: the
+    sphere member runs its own kernels inside the call, and every member's
+    J and gradient equal its single call bit for bit."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    ps = W.sphere_problem(4, 700, 2e-2, seed=51)
+    sph = rsot.Problem(ps.x, ps.mu, ps.y, ps.nu, cost="sphere", cost_scale=1.0,
+                       fp64_below_points=0)
+    eu = [W.cube_mixture(8, 300 + 100 * i, 1e-2) for i in range(2)]
+    eus = [rsot.Problem(q.x, q.mu, q.y, q.nu) for q in eu]
+    probs = [eus[0], sph, eus[1]]
+    eps = [eu[0].eps, ps.eps, eu[1].eps]
+    psis = [torch.as_tensor(W.random_psi(60 + i, pr.n, e), device="cuda")
+            for i, (pr, e) in enumerate(zip(probs, eps))]
+    J, grads, infos, _ = rsot.dual_eval_batched(probs, eps, psis)
+    for i, (pr, e, psi) in enumerate(zip(probs, eps, psis)):
+        r = pr.dual_eval(psi, e)
+        assert J[i] == r.J, i
+        assert torch.equal(grads[i], r.grad), i
+    ref = oracle.dual_eval_sphere(ps.x, ps.mu, ps.y, ps.nu, psis[1].cpu().numpy(), ps.eps)
+    _check(_Member(J[1], grads[1], infos[1]), ref, ps, "mixed_fp32")
+
+
+class _Member:
+    """J, grad and info of one batched member, shaped as a dual_eval result"""
+    def __init__(self, J, grad, info):
+        self.J, self.grad, self.info = J, grad, info
