@@ -833,8 +833,9 @@ def sphere_leg(eval_k=7, eval_n=65536):
     blue-noise sampling by Lloyd's algorithm with Riemannian barycentres
     (Algs. 4-5) for N = 4..9 at eps = 1e-2 and tol 1e-3, as in the paper's
     figure; then the evaluation rate of the sphere pair loop on icosphere(7)
-    (983,040 points) against 65,536 targets, dense, mixed and FP64, the
-    mixed gradient re-checked against the FP64 one."""
+    (983,040 points) against 65,536 targets, dense, mixed and FP64 (the
+    mixed gradient re-checked against the FP64 one), one barycentre step in
+    each, and the geodesic tile rule at tau 1e-12 against the dense J."""
     import torch
     from paper_2507_23602_amd import rsot, sphere, workloads as W
     x, mu = W.sphere_quadrature(4, "harmonic")
@@ -862,13 +863,28 @@ def sphere_leg(eval_k=7, eval_n=65536):
         kms = min(pr.sphere_karcher_step(psi, p.eps, dev[2], alpha=0.5)[3] for _ in range(2))
         rates[prec] = {"ms": best, "pairs_s": p.nq * p.n / (best * 1e-3), "karcher_ms": kms}
         pr.close()
+    # the geodesic tile rule (tau 1e-12, |J| reference from the dense FP64
+    # evaluation) on the same problem
+    pr = rsot.Problem(*dev, cost="sphere", cost_scale=1.0, precision="mixed", truncation="tile",
+                      tau=1e-12)
+    dense_J = rsot.Problem(*dev, cost="sphere", cost_scale=1.0, precision="fp64")
+    Jref = dense_J.dual_eval(psi, p.eps).J
+    dense_J.close()
+    pr.set_reference(abs(Jref))
+    pr.dual_eval(psi, p.eps)
+    rt = min((pr.dual_eval(psi, p.eps) for _ in range(3)), key=lambda r: r.info["kernel_ms"])
+    rates["tile"] = {"ms": rt.info["kernel_ms"], "kept_frac": rt.info["kept_pairs"] / (p.nq * p.n),
+                     "effective_pairs_s": p.nq * p.n / (rt.info["kernel_ms"] * 1e-3),
+                     "J_rel_vs_fp64_dense": abs(rt.J - Jref) / abs(Jref), "tau": 1e-12}
+    pr.close()
     nu_t = torch.as_tensor(p.nu, device="cuda")
     eg = torch.max(torch.abs(grads["mixed"] - grads["fp64"]) /
                    (nu_t + grads["fp64"] + nu_t)).item()
     log(f"[bench] sphere evaluation {p.name}: mixed {rates['mixed']['ms']:.1f} ms "
         f"({rates['mixed']['pairs_s']:.3e} pairs/s), fp64 {rates['fp64']['ms']:.1f} ms; "
         f"mixed vs fp64 e_g {eg:.1e}; barycentre step {rates['mixed']['karcher_ms']:.1f} / "
-        f"{rates['fp64']['karcher_ms']:.1f} ms")
+        f"{rates['fp64']['karcher_ms']:.1f} ms; tile rule {rates['tile']['ms']:.1f} ms, kept "
+        f"{rates['tile']['kept_frac']:.4f}, J vs FP64 dense {rates['tile']['J_rel_vs_fp64_dense']:.1e}")
     return {"blue_noise": runs, "eval_workload": p.name, "eval": rates,
             "grad_err_mixed_vs_fp64": eg}
 
