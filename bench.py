@@ -113,6 +113,8 @@ def main():
                     help="truncation-strategy study on both densities (0: skip)")
     ap.add_argument("--sphere", type=int, default=1,
                     help="blue-noise sampling and evaluation rate on the sphere (0: skip)")
+    ap.add_argument("--barycenter", type=int, default=1,
+                    help="damped-Lloyd Wasserstein barycentre of two 2D sources (0: skip)")
     ap.add_argument("--trunc-tol", type=str, default="1e-3",
                     help="stopping tolerances of the truncation study, comma separated")
     ap.add_argument("--gpu-size", type=str, default="2-5x1-3",
@@ -370,6 +372,8 @@ def main():
             legs.append(("trunc_study", lambda: trunc_study_leg(tols=tols)))
         if args.sphere and not args.quick:
             legs.append(("sphere", sphere_leg))
+        if args.barycenter and not args.quick:
+            legs.append(("barycenter", barycenter_leg))
         if args.gpu_size and not args.quick:
             rr, gg = args.gpu_size.split("x")
             r0, r1 = (int(v) for v in rr.split("-"))
@@ -887,6 +891,31 @@ def sphere_leg(eval_k=7, eval_n=65536):
         f"{rates['tile']['kept_frac']:.4f}, J vs FP64 dense {rates['tile']['J_rel_vs_fp64_dense']:.1e}")
     return {"blue_noise": runs, "eval_workload": p.name, "eval": rates,
             "grad_err_mixed_vs_fp64": eg}
+
+
+def barycenter_leg(n_cells=128, n_points=4096, eps=5e-3, tol=1e-4):
+    """Sec. 6.2: the damped Lloyd barycentre (theta = 1/2, lambda = 1/2 each)
+    of two Gaussian-blob densities on 128 x 128 squares (98,304 points each)
+    with 4,096 support points from uniform starts, eps 5e-3, FP64 pair loop,
+    to ||dy|| <= 1e-4 ||y||; the points' mean against the sources' weighted
+    mean (an invariant of the iteration)."""
+    import numpy as np
+    from paper_2507_23602_amd import barycenter, workloads as W
+    y = np.zeros((1, 2))
+    a = W.gaussian_blob_square(n_cells, (0.3, 0.35), 0.10, y, eps)
+    b = W.gaussian_blob_square(n_cells, (0.7, 0.6), 0.12, y, eps)
+    src = [(a.x, a.mu), (b.x, b.mu)]
+    y0 = W.uniform_targets(33, n_points, 2) * 0.6 + 0.2
+    yb, lg = barycenter.damped_lloyd(src, y0, eps, tol=tol, max_outer=300, solve_tol=1e-8)
+    M = 0.5 * ((a.mu[:, None] * a.x).sum(0) + (b.mu[:, None] * b.x).sum(0))
+    merr = float(np.max(np.abs(yb.mean(0) - M)))
+    solves = sum(sum(r["solve_iterations"]) for r in lg)
+    log(f"[bench] barycenter: {len(lg)} Lloyd iterations, {lg[-1]['seconds']:.2f} s, "
+        f"{solves} solver iterations, rel dy {lg[-1]['rel_dy']:.1e}, mean vs sources {merr:.1e}")
+    return {"workload": f"blob2_square{n_cells}_nb{n_points}_eps{eps:g}", "iterations": len(lg),
+            "seconds": lg[-1]["seconds"], "solver_iterations": solves,
+            "rel_dy": lg[-1]["rel_dy"], "mean_err": merr, "J_first": lg[0]["J"],
+            "J_last": lg[-1]["J"]}
 
 
 def cpu_model():
