@@ -85,6 +85,41 @@ def test_sphere_dense_probed_items(prec):
     assert el <= (1e-12 if prec == "fp64" else 1e-6), el
 
 
+def test_sphere_full_size_sampled_against_the_oracle():
+    """The rate problem (icosphere(7), 983,040 points x 65,536 targets,
+    eps = 1e-2, dense, one item per tile with probes): L_q of both pair loops
+    at 512 seeded points against the oracle's, the mixed gradient against the
+    FP64 one element by element, and both against Sum g = Sum mu - Sum nu."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    p = W.sphere_problem(7, 65536, 1e-2, seed=40)
+    _say(f"sphere full size {p.name}")
+    psi = W.random_psi(48, p.n, p.eps)
+    idx = np.random.default_rng(52).choice(p.nq, 512, replace=False)
+    ref = oracle.dual_eval_sphere(p.x[idx], p.mu[idx], p.y, p.nu, psi, p.eps, want_grad=False,
+                                  want_L=True)
+    dev = [torch.as_tensor(a, device="cuda") for a in (p.x, p.mu, p.y, p.nu)]
+    out = {}
+    for prec, tol in (("mixed", 1e-6), ("fp64", 1e-12)):
+        prob = rsot.Problem(*dev, cost="sphere", cost_scale=1.0, precision=prec)
+        r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+        assert r.info["fp64_pairs"] == int(prec == "fp64")
+        L = prob.lse().cpu().numpy()[idx]
+        el = float(np.max(np.abs(L - ref.L) / np.maximum(1.0, np.abs(ref.L))))
+        gs = abs(float(r.grad.sum().item()) - (p.mu.sum() - p.nu.sum()))
+        _say(f"  {prec}: sampled L vs oracle {el:.1e}, |sum g| {gs:.1e}, "
+             f"{r.info['kernel_ms']:.1f} ms")
+        assert el <= tol, (prec, el)
+        assert gs < (1e-12 if prec == "fp64" else 1e-9)
+        out[prec] = r
+        prob.close()
+    g64 = out["fp64"].grad.cpu().numpy()
+    eg = _grad_err(out["mixed"].grad.cpu().numpy(), g64, p.nu)
+    dJ = abs(out["mixed"].J - out["fp64"].J) / abs(out["fp64"].J)
+    _say(f"  mixed vs fp64: e_g {eg:.1e}, J {dJ:.1e}")
+    assert eg <= 1e-6 and dJ <= 1e-9
+
+
 @pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
 def test_sphere_tile_rule_parity(prec):
     """The geodesic tile rule: the kept (tile, block) set byte for byte and
