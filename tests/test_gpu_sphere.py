@@ -85,6 +85,47 @@ def test_sphere_dense_probed_items(prec):
     assert el <= (1e-12 if prec == "fp64" else 1e-6), el
 
 
+@pytest.mark.parametrize("case", ["one_target", "ragged", "cost_half"])
+def test_sphere_edge_cases(case):
+    """A single target, point and target counts that are not multiples of
+    64 (ragged tiles and blocks), and cost_scale 1/2: J, gradients and L_q
+    against the oracle on both pair loops."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    x, mu = W.sphere_quadrature(3, "harmonic")
+    cs = 1.0
+    if case == "one_target":
+        y = W.sphere_points(53, 1)
+    elif case == "ragged":
+        keep = np.random.default_rng(54).choice(x.shape[0], x.shape[0] - 37, replace=False)
+        x, mu = x[keep], mu[keep] / mu[keep].sum()
+        y = W.sphere_points(55, 203)
+    else:
+        y = W.sphere_points(56, 150)
+        cs = 0.5
+    n = y.shape[0]
+    nu = np.full(n, 1.0 / n)
+    eps = 2e-2
+    psi = W.random_psi(57, n, eps)
+    ref = oracle.dual_eval_sphere(x, mu, y, nu, psi, eps, cost_scale=cs, want_L=True)
+    for prec in ("mixed_fp32", "fp64"):
+        extra = {"fp64_below_points": 0} if prec == "mixed_fp32" else {}
+        prob = rsot.Problem(x, mu, y, nu, cost="sphere", cost_scale=cs,
+                            precision="fp64" if prec == "fp64" else "mixed", **extra)
+        r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), eps)
+        g = r.grad.cpu().numpy()
+        eg = _grad_err(g, ref.grad, nu)
+        dJ = abs(r.J - ref.J) / abs(ref.J)
+        L = prob.lse().cpu().numpy()
+        el = float(np.max(np.abs(L - ref.L) / np.maximum(1.0, np.abs(ref.L))))
+        _say(f"  {case} {prec}: nq={x.shape[0]} n={n} dJ {dJ:.1e} e_g {eg:.1e} L {el:.1e}")
+        if prec == "fp64":
+            assert dJ <= 1e-12 and eg <= 1e-11 and el <= 1e-12
+        else:
+            assert dJ <= 1e-9 and eg <= 1e-6 and el <= 1e-6
+        prob.close()
+
+
 def test_sphere_full_size_sampled_against_the_oracle():
     """The rate problem (icosphere(7), 983,040 points x 65,536 targets,
     eps = 1e-2, dense, one item per tile with probes): L_q of both pair loops
