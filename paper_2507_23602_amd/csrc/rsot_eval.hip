@@ -1155,7 +1155,8 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     const double *__restrict__ partk, const int64_t *__restrict__ wi_ptr, int64_t n_seg1,
     int64_t n_tiles, double kcs, int want_A, double lcorr, double corr,
     double *__restrict__ qA, double *__restrict__ qlse, int32_t *__restrict__ qkept,
-    double2 *__restrict__ tile_ref, double *__restrict__ tile_part) {
+    double2 *__restrict__ tile_ref, double *__restrict__ tile_part,
+    double *__restrict__ tile_smax) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -1192,6 +1193,10 @@ __global__ __launch_bounds__(256) void k_pass1_combine(
     const double ds = wave_sum(dm > -INFINITY ? exp(dl - dm) : 0.0);
     const double ks = wave_sum(real ? kept : 0.0);
     const double es = wave_sum(real && empty ? 1.0 : 0.0);
+    if (tile_smax) {
+        const double sm = wave_max(real && !empty ? S : -INFINITY);
+        if (lane == 0) tile_smax[t] = sm;
+    }
     if (lane == 0) {
         tile_ref[t] = make_double2(RT, exp2(RT) * corr);
         tile_part[t * 4 + 0] = js;
@@ -1626,7 +1631,8 @@ static void launch_pass1(rsot_problem *p, double kcs, const Pass1Work &pw) {
                        p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                        MODE == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
                        p->n_tiles, kcs, MODE == MODE_MASK ? 1 : 0, pass_lcorr(p, F64),
-                       pass_corr(p, F64), p->qA, p->qlse, p->qkept, p->tile_ref, p->tile_part);
+                       pass_corr(p, F64), p->qA, p->qlse, p->qkept, p->tile_ref, p->tile_part,
+                       p->tile_smax);
 }
 
 template <int D, bool F64, int MODE>
@@ -1663,7 +1669,7 @@ static void launch_passes_sphere(rsot_problem *p, bool f64, int mode, bool grad,
                        p->stream, p->qp, p->qmu, p->qlog2mu, p->qperm, p->part1, p->part1k,
                        mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr, pw.n_seg1,
                        p->n_tiles, 0.0, 0, pass_lcorr(p, f64), pass_corr(p, f64), p->qA,
-                       p->qlse, p->qkept, p->tile_ref, p->tile_part);
+                       p->qlse, p->qkept, p->tile_ref, p->tile_part, p->tile_smax);
     (void)hipEventRecord(p->ev_mid, p->stream);
     if (grad) rsot_sphere_pass2(p, f64, mode, kcs, n_wi, n_seg, seg);
 }
@@ -2353,7 +2359,7 @@ extern "C" rsot_status rsot_dual_eval_batched(rsot_problem *const *ps, int n, co
                                e.mode == MODE_DENSE ? (const int64_t *)nullptr : p->wi1_ptr,
                                e.pw.n_seg1, p->n_tiles, e.kcs, 0, pass_lcorr(p, false),
                                pass_corr(p, false), p->qA, p->qlse, p->qkept, p->tile_ref,
-                               p->tile_part);
+                               p->tile_part, p->tile_smax);
         }
         for (int gi = 0; gi < ng; ++gi) {
             const int k0 = gstart[(size_t)gi], cnt = gstart[(size_t)gi + 1] - k0;

@@ -82,6 +82,8 @@ struct rsot_problem {
     // per-evaluation partials and scalars
     double *tile_part = nullptr; // [n_tiles*4] sum mu L2, logD part, kept, empty
     double2 *tile_ref = nullptr; // [n_tiles] gradient-pass reference {R_T, 2^R_T * corr}
+    double *tile_smax = nullptr; // [n_tiles] sphere cost: max over the tile of S'_q, the
+                                 // gradient-side bound of whole-tile skips
     double *blk_gpart = nullptr; // [n_blocks*2] |g|_1, |g|_inf per block
     double *dscal = nullptr;     // [32] device scalars
     double *hscal = nullptr;     // [32] pinned host copy

@@ -477,6 +477,7 @@ static rsot_status create_impl(rsot_problem *p, const double *x, const double *m
     RSOT_TRY(dalloc(p, &p->tile_cnt, p->n_tiles));
     RSOT_TRY(dalloc(p, &p->tile_part, p->n_tiles * 4));
     RSOT_TRY(dalloc(p, &p->tile_ref, p->n_tiles));
+    if (p->opt.cost_kind == RSOT_COST_SPHERE) RSOT_TRY(dalloc(p, &p->tile_smax, p->n_tiles));
     RSOT_TRY(dalloc(p, &p->ty, p->n_pad * 3));
     RSOT_TRY(dalloc(p, &p->tnu, p->n_pad));
     RSOT_TRY(dalloc(p, &p->tlog2nu, p->n_pad));

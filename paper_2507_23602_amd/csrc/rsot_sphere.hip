@@ -15,7 +15,11 @@
 // z2 from above: a pair whose bound lies more than 160 below the running
 // maximum (objective pass) or below -160 (gradient-side passes, whose
 // exponents are already normalised) has an exponential that is zero in FP32
-// and below any FP64 rounding of its sum, and skips the polynomial.
+// and below any FP64 rounding of its sum, and skips the polynomial. The same
+// bound over a whole target block (objective pass: kappa max psi + log2 nu(B)
+// at the least squared distance from the point to the block's box) or point
+// tile (gradient side: B_j + max S' at the least squared distance from the
+// target to the tile's box) skips the block or tile.
 // The exponentials and their chunk sums run
 // in FP32 (mixed) or FP64 as in the squared Euclidean passes, with the same
 // work items, partials and merges. Target records hold {y_j, B_j}; point
@@ -106,6 +110,16 @@ LogPoly log_poly(bool f64) {
     return H;
 }
 
+// least squared distance from the point (x0, x1, x2) to the box [lo, hi]
+__device__ __forceinline__ double box_dist2(const double *__restrict__ lo,
+                                            const double *__restrict__ hi, double x0, double x1,
+                                            double x2) {
+    const double g0 = fmax(fmax(lo[0] - x0, x0 - hi[0]), 0.0);
+    const double g1 = fmax(fmax(lo[1] - x1, x1 - hi[1]), 0.0);
+    const double g2 = fmax(fmax(lo[2] - x2, x2 - hi[2]), 0.0);
+    return fma(g0, g0, fma(g1, g1, g2 * g2));
+}
+
 GeoPoly geo_poly(bool f64, double kcs) {
     GeoPoly P{};
     const int n = f64 ? RSOT_GEO_DEG18 : RSOT_GEO_DEG14;
@@ -139,8 +153,11 @@ __global__ __launch_bounds__(256) void k_sphere_pass1(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
     const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
     const int32_t *__restrict__ wi_tile, const int64_t *__restrict__ wi_range,
-    const int32_t *__restrict__ perm, int64_t n_items, int64_t n_blocks, int64_t seg1,
-    int64_t n_seg1, const GeoPoly P, double *__restrict__ part, double *__restrict__ partk) {
+    const int32_t *__restrict__ perm, const double *__restrict__ blk_lo,
+    const double *__restrict__ blk_hi, const double *__restrict__ blk_lnnu,
+    const double *__restrict__ blk_stat, double kappa, int64_t n_items, int64_t n_blocks,
+    int64_t seg1, int64_t n_seg1, const GeoPoly P, double *__restrict__ part,
+    double *__restrict__ partk) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t w, t, e0, e1;
@@ -173,6 +190,10 @@ __global__ __launch_bounds__(256) void k_sphere_pass1(
     }
     for (int64_t e = e0; e < e1; ++e) {
         const int64_t b = MODE == MODE_DENSE ? e : (int64_t)(row_idx[e] & ~RSOT_PARTIAL_BIT);
+        kept += (double)blk_cnt[b];
+        const double ub = fma(kappa, blk_stat[b * 4], blk_lnnu[b] * RSOT_LOG2E) -
+                          P.kcs * box_dist2(blk_lo + b * 3, blk_hi + b * 3, xr.x, xr.y, xr.z);
+        if (ub < m - 160.0) continue;
         const double4 *T = trec + b * 64;
         for (int k0 = 0; k0 < 64; k0 += CH) {
             double tv[CH];
@@ -201,7 +222,6 @@ __global__ __launch_bounds__(256) void k_sphere_pass1(
                 s += (double)cs;
             }
         }
-        kept += (double)blk_cnt[b];
     }
     part[w * 64 + lane] = s > 0.0 ? m + log2(s) : -INFINITY;
     partk[w * 64 + lane] = kept;
@@ -249,8 +269,10 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
     const double4 *__restrict__ qp, const double2 *__restrict__ tref,
     const double4 *__restrict__ trec, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
-    const uint32_t *__restrict__ col_idx, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
-    int64_t n_seg, int64_t seg, const GeoPoly P, double *__restrict__ gpart) {
+    const uint32_t *__restrict__ col_idx, const double *__restrict__ tile_lo,
+    const double *__restrict__ tile_hi, const double *__restrict__ tile_smax, int64_t n_tiles,
+    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, const GeoPoly P,
+    double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Item it = col_item<MODE>(wave, wi_block, wi_range, perm, n_tiles, n_blocks, n_wi,
@@ -261,6 +283,10 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
     double acc = 0.0;
     for (int64_t e = it.e0; e < it.e1; ++e) {
         const int64_t t = MODE == MODE_DENSE ? e : (int64_t)(col_idx[e] & ~RSOT_PARTIAL_BIT);
+        if (rec.w + tile_smax[t] -
+                P.kcs * box_dist2(tile_lo + t * 3, tile_hi + t * 3, rec.x, rec.y, rec.z) <
+            -160.0)
+            continue;
         const double4 *Q = qp + t * 64;
         double a = 0.0;
         for (int i0 = 0; i0 < 64; i0 += CH) {
@@ -302,8 +328,10 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
     const double4 *__restrict__ trec, const int32_t *__restrict__ tperm,
     const double *__restrict__ y_cur, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
-    const uint32_t *__restrict__ col_idx, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
-    int64_t n_seg, int64_t seg, const GeoPoly P, const LogPoly H, double *__restrict__ kpart) {
+    const uint32_t *__restrict__ col_idx, const double *__restrict__ tile_lo,
+    const double *__restrict__ tile_hi, const double *__restrict__ tile_smax, int64_t n_tiles,
+    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, const GeoPoly P, const LogPoly H,
+    double *__restrict__ kpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Item it = col_item<MODE>(wave, wi_block, wi_range, perm, n_tiles, n_blocks, n_wi,
@@ -319,6 +347,10 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t e = it.e0; e < it.e1; ++e) {
         const int64_t t = MODE == MODE_DENSE ? e : (int64_t)(col_idx[e] & ~RSOT_PARTIAL_BIT);
+        if (rec.w + tile_smax[t] -
+                P.kcs * box_dist2(tile_lo + t * 3, tile_hi + t * 3, rec.x, rec.y, rec.z) <
+            -160.0)
+            continue;
         const double4 *Q = qp + t * 64;
         double at[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < 64; ++i) {
@@ -422,10 +454,12 @@ void rsot_sphere_pass1(rsot_problem *p, bool f64, int mode, double kcs, int64_t 
                        int64_t seg1, int64_t n_seg1) {
     const unsigned grid = mode == MODE_DENSE ? (unsigned)((n_items + 3) / 4) : xcd_run_grid(n_items);
     const GeoPoly P = geo_poly(f64, kcs);
+    const double kappa = kcs / p->opt.cost_scale;
 #define RSOT_SP1(F, M)                                                                         \
     hipLaunchKernelGGL((k_sphere_pass1<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,      \
                        p->trec, p->blk_cnt, p->row_idx, p->wi1_tile, p->wi1_range, p->wi1_perm,  \
-                       n_items, p->n_blocks, seg1, n_seg1, P, p->part1, p->part1k)
+                       p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, kappa, n_items,           \
+                       p->n_blocks, seg1, n_seg1, P, p->part1, p->part1k)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SP1(true, MODE_DENSE);
         else RSOT_SP1(false, MODE_DENSE);
@@ -443,7 +477,8 @@ void rsot_sphere_pass2(rsot_problem *p, bool f64, int mode, double kcs, int64_t 
 #define RSOT_SP2(F, M)                                                                         \
     hipLaunchKernelGGL((k_sphere_pass2<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,      \
                        p->tile_ref, p->trec, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,   \
-                       p->n_tiles, p->n_blocks, n_wi, n_seg, seg, P, p->gpart)
+                       p->tile_lo, p->tile_hi, p->tile_smax, p->n_tiles, p->n_blocks, n_wi,      \
+                       n_seg, seg, P, p->gpart)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SP2(true, MODE_DENSE);
         else RSOT_SP2(false, MODE_DENSE);
@@ -476,8 +511,8 @@ extern "C" rsot_status rsot_sphere_karcher_step(rsot_problem *p, double eps, con
 #define RSOT_SK(F, M)                                                                          \
     hipLaunchKernelGGL((k_sphere_karcher<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,    \
                        p->tile_ref, p->trec, p->tperm, y_cur, p->wi_block, p->wi_range,          \
-                       p->wi_perm, p->col_idx, p->n_tiles, p->n_blocks, n_wi, n_seg, seg, P, H,  \
-                       p->mpart)
+                       p->wi_perm, p->col_idx, p->tile_lo, p->tile_hi, p->tile_smax, p->n_tiles, \
+                       p->n_blocks, n_wi, n_seg, seg, P, H, p->mpart)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SK(true, MODE_DENSE);
         else RSOT_SK(false, MODE_DENSE);
