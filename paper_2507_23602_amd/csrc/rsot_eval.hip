@@ -1044,10 +1044,10 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
 }
 
 // Objective pass under the cutoff rules (mixed precision): items in the order
-// of their first target block, dealt to the XCDs in runs. Built for eight
-// waves per SIMD: the straddling-chunk path needs more registers than the
-// fast path, and at six or seven waves the pass lost more to exposed load
-// latency than a few spilled values cost.
+// of their first target block, dealt to the XCDs in runs. The straddling-
+// chunk path needs more registers than the fast path (72 vector registers:
+// seven waves per SIMD); holding it to eight waves spills and was slower
+// (GEOM evaluation on the 3D benchmark workload 171.5 -> 182.7 ms).
 template <int D>
 __global__ __launch_bounds__(256) void k_pass1_cut(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
