@@ -690,7 +690,7 @@ class Multilevel:
             pass
 
     def solve(self, eps, level, tol=1e-6, level_tol=0.0, max_iter=10000, callback=None,
-              stage_tol=0.0, lbfgs_m=10):
+              stage_tol=0.0, lbfgs_m=10, test_flip_gradient=False):
         """rsot_solve_multilevel. ``callback(iter_info)`` is called after every
         accepted iteration of every level; a true return value cancels.
         ``level_tol`` / ``stage_tol``: ||grad||_1 targets of non-final levels
@@ -704,6 +704,7 @@ class Multilevel:
         mp.base.max_iter = max_iter
         mp.base.stage_tol = stage_tol
         mp.base.lbfgs_m = lbfgs_m
+        mp.base.test_flip_gradient = int(bool(test_flip_gradient))
         cb = None
         if callback is not None:
             def _cb(ptr, _user):
@@ -720,7 +721,7 @@ class Multilevel:
         rc = lib.rsot_solve_multilevel(self._h, ctypes.byref(mp), psi.ctypes.data,
                                        ctypes.byref(info))
         if rc not in (OK, ERR_NOT_CONVERGED):
-            raise RsotError(rc, "rsot_solve_multilevel")
+            raise RsotError(rc, "rsot_solve_multilevel", psi=psi, info=info.as_dict())
         return psi, info.as_dict()
 
 

@@ -120,3 +120,27 @@ def test_multilevel_solve_small():
     g1 = np.abs(r.grad).sum()
     _say(f"  oracle |g|_1 at multilevel psi = {g1:.3e}")
     assert g1 < 2e-6
+
+
+def test_multilevel_stalled_levels_and_final_failure():
+    """Failure handling across levels (host-side hook: the solver sees -grad,
+    so no line search can decrease J): every non-final step stalls and hands
+    its iterate on (counted in stalled_levels), and the final step's
+    RSOT_ERR_LINESEARCH is the solve's status, with the info attached."""
+    import torch
+    from paper_2507_23602_amd import rsot
+    meshes = W.disk_hierarchy(rings=6, levels=3)
+    sources = [W.quadrature(m) for m in meshes]
+    yf = W.blob_targets_disk(1024, seed=5)
+    nuf = np.full(1024, 1 / 1024)
+    levels = rsot.target_hierarchy(torch.as_tensor(yf, device="cuda"),
+                                   torch.as_tensor(nuf, device="cuda"), [64, 256, 1024])
+    ml = rsot.Multilevel(sources, [(l[0], l[1]) for l in levels], precision="fp64")
+    with pytest.raises(rsot.RsotError) as e:
+        ml.solve([0.04, 0.02, 0.01], [0, 1, 2], tol=1e-8, test_flip_gradient=True)
+    err = e.value
+    _say(f"  status {err.code}, info {err.info}")
+    assert err.code == rsot.ERR_LINESEARCH
+    assert err.info["stalled_levels"] == 2 and err.info["n_steps"] == 3
+    assert err.info["iterations"] == [0, 0, 0]
+    assert np.all(np.isfinite(err.psi))
