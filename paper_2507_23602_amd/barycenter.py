@@ -20,6 +20,18 @@ import numpy as np
 from . import rsot
 
 
+def _solve(prob, eps, psi0, tol):
+    """rsot_solve from psi0; a line search that cannot improve the iterate
+    at the pair loop's precision (RSOT_ERR_LINESEARCH) returns its best
+    iterate, which the outer iteration uses like any other solution"""
+    try:
+        return prob.solve([eps], psi0=psi0, tol=tol)
+    except rsot.RsotError as e:
+        if e.code != rsot.ERR_LINESEARCH or e.psi is None:
+            raise
+        return e.psi, e.info
+
+
 def damped_lloyd(sources, y0, eps, *, lambdas=None, theta=0.5, tol=1e-3, max_outer=200,
                  solve_tol=1e-8, cost_scale=0.5, precision="fp64", truncation="dense",
                  tau=1e-12):
@@ -50,7 +62,7 @@ def damped_lloyd(sources, y0, eps, *, lambdas=None, theta=0.5, tol=1e-3, max_out
         for i, (x, mu) in enumerate(sources):
             prob = rsot.Problem(x, mu, y, nu, cost_scale=cost_scale, precision=precision,
                                 truncation=truncation, tau=tau)
-            psi, info = prob.solve([eps], psi0=psis[i], tol=solve_tol)
+            psi, info = _solve(prob, eps, psis[i], solve_tol)
             _, first, _, _ = prob.plan_moments(torch.as_tensor(psi, device="cuda"), eps)
             prob.close()
             psis[i] = psi
@@ -103,7 +115,7 @@ def wasserstein_barycenter(sources, y0, nu0, eps, *, lambdas=None, alpha=1.0, be
         for i, (x, mu) in enumerate(sources):
             prob = rsot.Problem(x, mu, y, nu, cost_scale=cost_scale, precision=precision,
                                 truncation=truncation, tau=tau)
-            psi, info = prob.solve([eps], psi0=psis[i], tol=solve_tol)
+            psi, info = _solve(prob, eps, psis[i], solve_tol)
             mass, first, _, _ = prob.plan_moments(torch.as_tensor(psi, device="cuda"), eps)
             prob.close()
             psis[i] = psi

@@ -17,6 +17,18 @@ import numpy as np
 from . import rsot
 
 
+def _solve(prob, eps, psi0, tol):
+    """rsot_solve from psi0; a line search that cannot improve the iterate
+    at the pair loop's precision (RSOT_ERR_LINESEARCH) returns its best
+    iterate, which the outer iteration uses like any other solution"""
+    try:
+        return prob.solve([eps], psi0=psi0, tol=tol)
+    except rsot.RsotError as e:
+        if e.code != rsot.ERR_LINESEARCH or e.psi is None:
+            raise
+        return e.psi, e.info
+
+
 def lloyd(x, mu, y0, eps, *, nu=None, cost_scale=1.0, tol=1e-3, max_outer=200,
           inner_tol=1e-9, max_inner=50, alpha=0.5, solve_tol=1e-8, precision="fp64",
           truncation="dense", tau=1e-12):
@@ -35,7 +47,7 @@ def lloyd(x, mu, y0, eps, *, nu=None, cost_scale=1.0, tol=1e-3, max_outer=200,
     for it in range(max_outer):
         prob = rsot.Problem(x, mu, y, nu, cost="sphere", cost_scale=cost_scale,
                             precision=precision, truncation=truncation, tau=tau)
-        psi, info = prob.solve([eps], psi0=psi, tol=solve_tol)
+        psi, info = _solve(prob, eps, psi, solve_tol)
         yc = torch.as_tensor(y, device="cuda")
         inner = 0
         for inner in range(1, max_inner + 1):
