@@ -1,8 +1,11 @@
 """GPU tests of the squared geodesic cost on the unit sphere (Sec. 6.4,
-Algs. 4-5) through the C ABI, against the oracle: dense and tile-rule
-evaluations (values, gradients, kept sets), the Riemannian barycentre step,
-and Lloyd's algorithm on the uniform sphere, whose 4- and 6-point optima are
-the regular tetrahedron and octahedron."""
+Algs. 4-5) through the C ABI, against the oracle: dense evaluations (small,
+with probed items, full size on sampled points, edge cases), the tile rule
+(values, gradients, kept sets byte for byte), a sphere member inside a
+batched call, the Riemannian barycentre step (dense at two eps, and on the
+tile rule's lists), and Lloyd's algorithm on the uniform sphere, whose 4-
+and 6-point optima are the regular tetrahedron and octahedron, and on the
+harmonic density."""
 import math
 import sys
 
@@ -210,6 +213,33 @@ def test_sphere_karcher_step_parity(prec, eps):
     tol = 1e-12 if prec == "fp64" else 1e-6
     assert ey <= tol and es <= tol and em <= tol
     assert np.allclose(np.linalg.norm(yn.cpu().numpy(), axis=1), 1.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
+def test_sphere_karcher_step_under_the_tile_rule(prec):
+    """The barycentre step on the tile rule's lists (tau = 1e-12, the dense
+    objective as |J| reference): the kept set drops pairs, and the step
+    agrees with the oracle's dense step within the rule's bound (the
+    dropped weight is below tau |J| relative)."""
+    import torch
+    p = W.sphere_problem(5, 2000, 5e-3, seed=58)
+    prob = _problem(p, prec, truncation="tile", tau=1e-12)
+    psi = W.random_psi(59, p.n, p.eps)
+    dense = oracle.dual_eval_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    prob.set_reference(abs(dense.J))
+    yc = p.y + 0.01 * np.random.default_rng(60).standard_normal(p.y.shape)
+    yc /= np.linalg.norm(yc, axis=1, keepdims=True)
+    yn, step, mass, ms = prob.sphere_karcher_step(psi, p.eps, torch.as_tensor(yc, device="cuda"),
+                                                  alpha=0.5)
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    kept = r.info["kept_pairs"] / (p.nq * p.n)
+    ry, rs, rm = oracle.sphere_karcher_step(p.x, p.mu, p.y, p.nu, psi, p.eps, yc, alpha=0.5)
+    ey = float(np.max(np.abs(yn.cpu().numpy() - ry)))
+    em = float(np.max(np.abs(mass.cpu().numpy() - rm) / (p.nu + rm)))
+    _say(f"  {prec}: kept {kept:.3f}, y {ey:.1e}, mass {em:.1e}, {ms:.3f} ms")
+    assert kept < 0.9
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    assert ey <= tol and em <= tol
 
 
 @pytest.mark.parametrize("n,angles", [

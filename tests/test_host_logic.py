@@ -121,3 +121,25 @@ def test_truncation_study_inputs():
     assert np.array_equal(c.x, u.x) and np.array_equal(c.y, u.y)
     assert np.allclose(u.mu, 1.0 / u.nq, rtol=1e-12)
     assert not np.allclose(c.mu, u.mu)
+
+
+def test_drivers_continue_from_a_stalled_solve():
+    """The Lloyd and barycentre drivers take the best iterate of a solve
+    that ends on RSOT_ERR_LINESEARCH (the noise floor) and re-raise any
+    other error."""
+    import numpy as np
+    import pytest
+    from paper_2507_23602_amd import barycenter, rsot, sphere
+
+    class Fake:
+        def __init__(self, code):
+            self.code = code
+
+        def solve(self, eps, psi0=None, tol=None):
+            raise rsot.RsotError(self.code, "rsot_solve", psi=np.ones(3), info={"J": -1.0})
+
+    for mod in (sphere, barycenter):
+        psi, info = mod._solve(Fake(rsot.ERR_LINESEARCH), 1e-2, np.zeros(3), 1e-8)
+        assert np.all(psi == 1.0) and info["J"] == -1.0
+        with pytest.raises(rsot.RsotError):
+            mod._solve(Fake(rsot.ERR_NONFINITE), 1e-2, np.zeros(3), 1e-8)
