@@ -883,6 +883,16 @@ def sphere_leg(eval_k=7, eval_n=65536):
     rates["tile"] = {"ms": rt.info["kernel_ms"], "kept_frac": rt.info["kept_pairs"] / (p.nq * p.n),
                      "effective_pairs_s": p.nq * p.n / (rt.info["kernel_ms"] * 1e-3),
                      "J_rel_vs_fp64_dense": abs(rt.J - Jref) / abs(Jref), "tau": 1e-12}
+    # the same rule over culling groups of 32, 16 and 8 targets
+    groups = {}
+    for g in (32, 16, 8):
+        pr.set_tuning(0, 0, g)
+        pr.dual_eval(psi, p.eps)
+        rg = min((pr.dual_eval(psi, p.eps) for _ in range(3)), key=lambda r: r.info["kernel_ms"])
+        groups[str(g)] = {"ms": rg.info["kernel_ms"],
+                          "kept_frac": rg.info["kept_pairs"] / (p.nq * p.n),
+                          "J_rel_vs_fp64_dense": abs(rg.J - Jref) / abs(Jref)}
+    rates["tile"]["groups"] = groups
     pr.close()
     nu_t = torch.as_tensor(p.nu, device="cuda")
     eg = torch.max(torch.abs(grads["mixed"] - grads["fp64"]) /
@@ -892,7 +902,9 @@ def sphere_leg(eval_k=7, eval_n=65536):
         f"{rates['fp64']['ms']:.1f} ms; "
         f"mixed vs fp64 e_g {eg:.1e}; barycentre step {rates['mixed']['karcher_ms']:.1f} / "
         f"{rates['fp64']['karcher_ms']:.1f} ms; tile rule {rates['tile']['ms']:.1f} ms, kept "
-        f"{rates['tile']['kept_frac']:.4f}, J vs FP64 dense {rates['tile']['J_rel_vs_fp64_dense']:.1e}")
+        f"{rates['tile']['kept_frac']:.4f}, J vs FP64 dense {rates['tile']['J_rel_vs_fp64_dense']:.1e}; "
+        + ", ".join(f"groups of {g} {v['ms']:.1f} ms kept {v['kept_frac']:.4f}"
+                    for g, v in groups.items()))
     return {"blue_noise": runs, "eval_workload": p.name, "eval": rates,
             "grad_err_mixed_vs_fp64": eg}
 

@@ -87,8 +87,8 @@ typedef enum {
  *           antipode on the far hemisphere. Requires dim 3 and points and targets
  *           of unit norm (| |v|^2 - 1 | <= 1e-9, else INVALID_ARG), and the
  *           DENSE or TILE rule; the tile rule's box bounds pass through the
- *           chord (the geodesic increases with it) and it culls whole blocks
- *           (tile_group is ignored). Batched calls run such members one by
+ *           chord (the geodesic increases with it), over whole blocks or
+ *           culling groups as for SQEUCLID. Batched calls run such members one by
  *           one; the moments, maps, refinement, multilevel and allocation-free
  *           calls return INVALID_ARG for them (rsot_sphere_karcher_step is
  *           the sphere's own moment call). */

@@ -394,7 +394,7 @@ __device__ __forceinline__ double grp_lnU(const double *__restrict__ tile_lo,
                                           const double *__restrict__ ghi,
                                           const double *__restrict__ glnnu,
                                           const double *__restrict__ gpsi, int64_t t, int64_t G,
-                                          double cs, double eps) {
+                                          double cs, double eps, bool sphere = false) {
     double dmin2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -402,6 +402,7 @@ __device__ __forceinline__ double grp_lnU(const double *__restrict__ tile_lo,
                                  ghi[G * 3 + k]);
         dmin2 += g * g;
     }
+    if (sphere) dmin2 = geo_of_chord2(dmin2);
     return glnnu[G] + (gpsi[G] - cs * dmin2) / eps;
 }
 
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) void k_tile_ref_grp(
     const double *__restrict__ ty, const double *__restrict__ tnu,
     const double *__restrict__ tpsi, const int32_t *__restrict__ tperm, int64_t n_tiles,
     int64_t n_groups, int g, double cs, double eps, double ln_eta_ng,
-    int32_t *__restrict__ gstar, double *__restrict__ thr) {
+    int32_t *__restrict__ gstar, double *__restrict__ thr, int sphere) {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_tile_ref_grp(
     int64_t bm = 0;
     for (int64_t b = lane; b < n_blocks; b += 64) {
         const double v = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
-                                     cs, eps);
+                                     cs, eps, sphere != 0);
         if (v > bmax) {
             bmax = v;
             bm = b;
@@ -449,18 +450,20 @@ __global__ __launch_bounds__(256) void k_tile_ref_grp(
     }
     double gv = -INFINITY;
     if (lane < ng)
-        gv = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, bm * ng + lane, cs, eps);
+        gv = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, bm * ng + lane, cs, eps,
+                        sphere != 0);
     gv = wave_max(gv);
     const double floor_v = gv - 1e-9 * (fabs(gv) + 1.0);
     double best = -INFINITY;
     int64_t bi = INT64_MAX;
     for (int64_t b = lane; b < n_blocks; b += 64) {
         const double v = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu, blk_stat, t, b,
-                                     cs, eps);
+                                     cs, eps, sphere != 0);
         if (!(v >= floor_v)) continue;
         for (int i = 0; i < ng; ++i) {
             const int64_t G = b * ng + i;
-            const double lnU = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, G, cs, eps);
+            const double lnU = grp_lnU<D>(tile_lo, tile_hi, glo, ghi, glnnu, gpsi, t, G, cs, eps,
+                                          sphere != 0);
             if (lnU > best) {
                 best = lnU;
                 bi = G;
@@ -486,6 +489,7 @@ __global__ __launch_bounds__(256) void k_tile_ref_grp(
                 const double f = box_far_pt(tile_lo[t * 3 + k], tile_hi[t * 3 + k], ty[j * 3 + k]);
                 dmax2 += f * f;
             }
+            if (sphere) dmax2 = geo_of_chord2(dmax2);
             lb = log(tnu[j]) + (tpsi[j] - cs * dmax2) / eps;
         }
     }
@@ -506,7 +510,8 @@ __device__ __forceinline__ uint32_t group_chunks(int64_t t, int64_t b, int g,
                                                  const double *__restrict__ ghi,
                                                  const double *__restrict__ glnnu,
                                                  const double *__restrict__ gpsi, int32_t gs,
-                                                 double th, double cs, double eps) {
+                                                 double th, double cs, double eps,
+                                                 bool sphere) {
     const int ng = 64 / g, cpg = g / 8;
     const double inv_eps = 1.0 / eps;
     double tl[3], thb[3];
@@ -526,6 +531,7 @@ __device__ __forceinline__ uint32_t group_chunks(int64_t t, int64_t b, int g,
                 const double gp = box_gap(tl[k], thb[k], glo[G * 3 + k], ghi[G * 3 + k]);
                 dmin2 += gp * gp;
             }
+            if (sphere) dmin2 = geo_of_chord2(dmin2);
             keep = bound_above(glnnu[G], gpsi[G] - cs * dmin2, eps, inv_eps, th);
         }
         if (keep) m |= ((1u << cpg) - 1u) << (i * cpg);
@@ -604,10 +610,10 @@ __global__ __launch_bounds__(256) void k_cull(
                     const double th = thr[t];
                     const bool holds = gs >= 0 && gs / (64 / grp) == b;
                     const double lnU = tile_lnU<D>(tile_lo, tile_hi, blk_lo, blk_hi, blk_lnnu,
-                                                   blk_stat, t, b, cs, eps);
+                                                   blk_stat, t, b, cs, eps, sphere != 0);
                     if (holds || lnU > th - 1e-9)
                         m = group_chunks<D>(t, b, grp, tile_lo, tile_hi, glo, ghi, glnnu, gpsi, gs,
-                                            th, cs, eps);
+                                            th, cs, eps, sphere != 0);
                     if (gm_out) gm_out[r * ncols + k] = (uint8_t)m;
                 }
                 if (m) {
@@ -645,7 +651,7 @@ __global__ __launch_bounds__(256) void k_cull(
                     const uint32_t m =
                         gm_in ? (uint32_t)gm_in[r * ncols + k]
                               : group_chunks<D>(t, b, grp, tile_lo, tile_hi, glo, ghi, glnnu,
-                                                gpsi, bstar[t], thr[t], cs, eps);
+                                                gpsi, bstar[t], thr[t], cs, eps, sphere != 0);
                     if (ROWS) {
                         uint32_t cm2 = 0;
                         for (int q = 0; q < 8; ++q)
@@ -1688,7 +1694,6 @@ static void cull_segments(int64_t nrows, int64_t ncols, int *nseg, int64_t *seg_
 
 // Culling group of the tile rule: targets per group (64 = whole blocks)
 static int tile_group(const rsot_problem *p) {
-    if (p->opt.cost_kind == RSOT_COST_SPHERE) return 64;      // whole blocks only
     return p->opt.tile_group > 0 ? (int)p->opt.tile_group : RSOT_TILE_GROUP_DEFAULT;
 }
 
@@ -1918,12 +1923,14 @@ static rsot_status plan_begin(EvalPlan &e) {
             hipLaunchKernelGGL(k_tile_ref_grp<2>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->ty, p->tnu,
                                p->tpsi, p->tperm, p->n_tiles, ng, grp, cs, eps, ln_eta_ng,
-                               p->tile_bstar, p->tile_thr);
+                               p->tile_bstar, p->tile_thr,
+                               p->opt.cost_kind == RSOT_COST_SPHERE ? 1 : 0);
         else
             hipLaunchKernelGGL(k_tile_ref_grp<3>, gtile, dim3(256), 0, st, p->tile_lo, p->tile_hi,
                                p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, p->grp_lo, p->grp_hi, p->grp_lnnu, p->grp_psi, p->ty, p->tnu,
                                p->tpsi, p->tperm, p->n_tiles, ng, grp, cs, eps, ln_eta_ng,
-                               p->tile_bstar, p->tile_thr);
+                               p->tile_bstar, p->tile_thr,
+                               p->opt.cost_kind == RSOT_COST_SPHERE ? 1 : 0);
     } else if (tile_rule) {
         const double ln_eta_nb = std::log(p->opt.tau * p->absJ_ref / (eps * p->sum_mu)) -
                                  std::log((double)p->n_blocks);

@@ -152,8 +152,9 @@ template <bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_sphere_pass1(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
     const int32_t *__restrict__ blk_cnt, const uint32_t *__restrict__ row_idx,
-    const int32_t *__restrict__ wi_tile, const int64_t *__restrict__ wi_range,
-    const int32_t *__restrict__ perm, const double *__restrict__ blk_lo,
+    const uint16_t *__restrict__ row_cm, const int32_t *__restrict__ wi_tile,
+    const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
+    const double *__restrict__ blk_lo,
     const double *__restrict__ blk_hi, const double *__restrict__ blk_lnnu,
     const double *__restrict__ blk_stat, double kappa, int64_t n_items, int64_t n_blocks,
     int64_t seg1, int64_t n_seg1, const GeoPoly P, double *__restrict__ part,
@@ -189,13 +190,25 @@ __global__ __launch_bounds__(256) void k_sphere_pass1(
         if (m0 > -INFINITY) m = ceil(m0 - rq) + rq;
     }
     for (int64_t e = e0; e < e1; ++e) {
-        const int64_t b = MODE == MODE_DENSE ? e : (int64_t)(row_idx[e] & ~RSOT_PARTIAL_BIT);
-        kept += (double)blk_cnt[b];
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : row_idx[e];
+        const int64_t b = (int64_t)(ent & ~RSOT_PARTIAL_BIT);
+        // tile rule with culling groups: an entry marked partial keeps only
+        // the 8-target chunks whose class bits say so
+        const bool part = MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT);
+        const uint32_t cm = part ? (uint32_t)row_cm[e] : 0u;
+        if (part) {
+            const int cnt = blk_cnt[b];
+            for (int c = 0; c < 8; ++c)
+                if ((cm >> (2 * c)) & 2u) kept += (double)std::min(8, std::max(0, cnt - 8 * c));
+        } else {
+            kept += (double)blk_cnt[b];
+        }
         const double ub = fma(kappa, blk_stat[b * 4], blk_lnnu[b] * RSOT_LOG2E) -
                           P.kcs * box_dist2(blk_lo + b * 3, blk_hi + b * 3, xr.x, xr.y, xr.z);
         if (ub < m - 160.0) continue;
         const double4 *T = trec + b * 64;
         for (int k0 = 0; k0 < 64; k0 += CH) {
+            if (part && !((cm >> (k0 / 4)) & 2u)) continue;
             double tv[CH];
             double cm = -INFINITY;
 #pragma unroll
@@ -269,10 +282,10 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
     const double4 *__restrict__ qp, const double2 *__restrict__ tref,
     const double4 *__restrict__ trec, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
-    const uint32_t *__restrict__ col_idx, const double *__restrict__ tile_lo,
-    const double *__restrict__ tile_hi, const double *__restrict__ tile_smax, int64_t n_tiles,
-    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, const GeoPoly P,
-    double *__restrict__ gpart) {
+    const uint32_t *__restrict__ col_idx, const uint8_t *__restrict__ col_cm,
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ tile_smax, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
+    int64_t n_seg, int64_t seg, const GeoPoly P, double *__restrict__ gpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Item it = col_item<MODE>(wave, wi_block, wi_range, perm, n_tiles, n_blocks, n_wi,
@@ -282,8 +295,14 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
     const double ym[3] = {-2.0 * rec.x, -2.0 * rec.y, -2.0 * rec.z};
     double acc = 0.0;
     for (int64_t e = it.e0; e < it.e1; ++e) {
-        const int64_t t = MODE == MODE_DENSE ? e : (int64_t)(col_idx[e] & ~RSOT_PARTIAL_BIT);
-        if (rec.w + tile_smax[t] -
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
+        const int64_t t = (int64_t)(ent & ~RSOT_PARTIAL_BIT);
+        // culling groups: lanes of dropped 8-target chunks take no terms
+        const double Bl = (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT) &&
+                           !((col_cm[e] >> (lane >> 3)) & 1u))
+                              ? -INFINITY
+                              : rec.w;
+        if (Bl + tile_smax[t] -
                 P.kcs * box_dist2(tile_lo + t * 3, tile_hi + t * 3, rec.x, rec.y, rec.z) <
             -160.0)
             continue;
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
                     const double4 r = ld4(Q + i0 + k);
-                    const double sc = chord2(ym, r.x, r.y, r.z), bq = rec.w + r.w;
+                    const double sc = chord2(ym, r.x, r.y, r.z), bq = Bl + r.w;
                     if (fma(-P.kcs, sc, bq) >= -160.0) cs += exp2(sphere_z<F64>(P, sc, bq));
                 }
                 a += cs;
@@ -304,7 +323,7 @@ __global__ __launch_bounds__(256) void k_sphere_pass2(
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
                     const double4 r = ld4(Q + i0 + k);
-                    const double sc = chord2(ym, r.x, r.y, r.z), bq = rec.w + r.w;
+                    const double sc = chord2(ym, r.x, r.y, r.z), bq = Bl + r.w;
                     if (fma(-P.kcs, sc, bq) >= -160.0)
                         cs += __builtin_amdgcn_exp2f((float)sphere_z<F64>(P, sc, bq));
                 }
@@ -328,10 +347,10 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
     const double4 *__restrict__ trec, const int32_t *__restrict__ tperm,
     const double *__restrict__ y_cur, const int32_t *__restrict__ wi_block,
     const int64_t *__restrict__ wi_range, const int32_t *__restrict__ perm,
-    const uint32_t *__restrict__ col_idx, const double *__restrict__ tile_lo,
-    const double *__restrict__ tile_hi, const double *__restrict__ tile_smax, int64_t n_tiles,
-    int64_t n_blocks, int64_t n_wi, int64_t n_seg, int64_t seg, const GeoPoly P, const LogPoly H,
-    double *__restrict__ kpart) {
+    const uint32_t *__restrict__ col_idx, const uint8_t *__restrict__ col_cm,
+    const double *__restrict__ tile_lo, const double *__restrict__ tile_hi,
+    const double *__restrict__ tile_smax, int64_t n_tiles, int64_t n_blocks, int64_t n_wi,
+    int64_t n_seg, int64_t seg, const GeoPoly P, const LogPoly H, double *__restrict__ kpart) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const Item it = col_item<MODE>(wave, wi_block, wi_range, perm, n_tiles, n_blocks, n_wi,
@@ -346,8 +365,13 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
         for (int k = 0; k < 3; ++k) yc[k] = y_cur[(int64_t)src * 3 + k];
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t e = it.e0; e < it.e1; ++e) {
-        const int64_t t = MODE == MODE_DENSE ? e : (int64_t)(col_idx[e] & ~RSOT_PARTIAL_BIT);
-        if (rec.w + tile_smax[t] -
+        const uint32_t ent = MODE == MODE_DENSE ? (uint32_t)e : col_idx[e];
+        const int64_t t = (int64_t)(ent & ~RSOT_PARTIAL_BIT);
+        const double Bl = (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT) &&
+                           !((col_cm[e] >> (lane >> 3)) & 1u))
+                              ? -INFINITY
+                              : rec.w;
+        if (Bl + tile_smax[t] -
                 P.kcs * box_dist2(tile_lo + t * 3, tile_hi + t * 3, rec.x, rec.y, rec.z) <
             -160.0)
             continue;
@@ -355,7 +379,7 @@ __global__ __launch_bounds__(256) void k_sphere_karcher(
         double at[4] = {0.0, 0.0, 0.0, 0.0};
         for (int i = 0; i < 64; ++i) {
             const double4 r = ld4(Q + i);
-            const double sc = chord2(ym, r.x, r.y, r.z), bq = rec.w + r.w;
+            const double sc = chord2(ym, r.x, r.y, r.z), bq = Bl + r.w;
             if (fma(-P.kcs, sc, bq) < -160.0) continue;
             const double v = sphere_z<F64>(P, sc, bq);
             const double wgt = F64 ? exp2(v) : (double)__builtin_amdgcn_exp2f((float)v);
@@ -457,7 +481,8 @@ void rsot_sphere_pass1(rsot_problem *p, bool f64, int mode, double kcs, int64_t 
     const double kappa = kcs / p->opt.cost_scale;
 #define RSOT_SP1(F, M)                                                                         \
     hipLaunchKernelGGL((k_sphere_pass1<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,      \
-                       p->trec, p->blk_cnt, p->row_idx, p->wi1_tile, p->wi1_range, p->wi1_perm,  \
+                       p->trec, p->blk_cnt, p->row_idx, p->row_cm, p->wi1_tile, p->wi1_range,    \
+                       p->wi1_perm,                                                              \
                        p->blk_lo, p->blk_hi, p->blk_lnnu, p->blk_stat, kappa, n_items,           \
                        p->n_blocks, seg1, n_seg1, P, p->part1, p->part1k)
     if (mode == MODE_DENSE) {
@@ -477,7 +502,8 @@ void rsot_sphere_pass2(rsot_problem *p, bool f64, int mode, double kcs, int64_t 
 #define RSOT_SP2(F, M)                                                                         \
     hipLaunchKernelGGL((k_sphere_pass2<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,      \
                        p->tile_ref, p->trec, p->wi_block, p->wi_range, p->wi_perm, p->col_idx,   \
-                       p->tile_lo, p->tile_hi, p->tile_smax, p->n_tiles, p->n_blocks, n_wi,      \
+                       p->col_cm, p->tile_lo, p->tile_hi, p->tile_smax, p->n_tiles, p->n_blocks, \
+                       n_wi,                                                                     \
                        n_seg, seg, P, p->gpart)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SP2(true, MODE_DENSE);
@@ -511,7 +537,8 @@ extern "C" rsot_status rsot_sphere_karcher_step(rsot_problem *p, double eps, con
 #define RSOT_SK(F, M)                                                                          \
     hipLaunchKernelGGL((k_sphere_karcher<F, M>), dim3(grid), dim3(256), 0, p->stream, p->qp,    \
                        p->tile_ref, p->trec, p->tperm, y_cur, p->wi_block, p->wi_range,          \
-                       p->wi_perm, p->col_idx, p->tile_lo, p->tile_hi, p->tile_smax, p->n_tiles, \
+                       p->wi_perm, p->col_idx, p->col_cm, p->tile_lo, p->tile_hi, p->tile_smax,  \
+                       p->n_tiles,                                                               \
                        p->n_blocks, n_wi, n_seg, seg, P, H, p->mpart)
     if (mode == MODE_DENSE) {
         if (f64) RSOT_SK(true, MODE_DENSE);

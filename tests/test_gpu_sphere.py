@@ -191,6 +191,67 @@ def test_sphere_tile_rule_parity(prec):
     assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
 
 
+def _chunk_keep_from_groups(keep_g, slots, n_blocks, g):
+    """The oracle's (tile, group) keep matrix as the library's per (tile,
+    block) chunk bits, and the mask of chunks that hold a real target."""
+    nt = keep_g.shape[0]
+    bits = np.zeros((nt, n_blocks), dtype=np.uint8)
+    real = np.zeros(n_blocks * 8, dtype=bool)
+    real[slots // 8] = True
+    for c in range(8):
+        grp = (np.arange(n_blocks) * 64 + 8 * c) // g
+        ok = grp < keep_g.shape[1]
+        col = np.zeros((nt, n_blocks), dtype=bool)
+        col[:, ok] = keep_g[:, grp[ok]] > 0
+        bits |= (col.astype(np.uint8) << c)
+    return bits, real.reshape(n_blocks, 8)
+
+
+@pytest.mark.parametrize("prec", ["mixed_fp32", "fp64"])
+@pytest.mark.parametrize("group", [32, 16, 8])
+def test_sphere_tile_rule_groups(prec, group):
+    """The geodesic tile rule over culling groups of g targets: the kept
+    (tile, chunk) set bit for bit, the kept-pair count and J, grad against
+    the oracle's rule on the library's tiles and groups; finer groups keep
+    fewer pairs than whole blocks (groups of 8); the barycentre step on the
+    grouped lists against the oracle's dense step."""
+    import torch
+    p = W.sphere_problem(5, 2000, 5e-3, seed=43)
+    tau = 1e-8
+    prob = _problem(p, prec, truncation="tile", tau=tau, tile_group=group)
+    psi = W.random_psi(44, p.n, p.eps)
+    dense = oracle.dual_eval_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    prob.set_reference(abs(dense.J))
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    tile_of, block_of, nt, nb = prob.partition()
+    tile_of = tile_of.cpu().numpy()
+    slots = prob.target_slots().cpu().numpy()
+    group_of = (slots // group).astype(np.int32)
+    ng = nb * 64 // group
+    ref = oracle.dual_eval_tile_sphere(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, group_of,
+                                       ng, tau, abs(dense.J), want_keep=True)
+    _say(f"  group {group} {prec}: kept gpu {r.info['kept_pairs']} oracle {ref.kept} "
+         f"of {p.nq * p.n}")
+    assert r.info["kept_pairs"] == ref.kept
+    if group == 8:
+        assert ref.kept < 45489152        # fewer than whole blocks keep on this problem
+    bits = prob.tile_chunk_keep().cpu().numpy()
+    ref_bits, real = _chunk_keep_from_groups(ref.keep, slots, nb, group)
+    realbits = np.packbits(real[:, ::-1], axis=1, bitorder="big").reshape(-1)
+    assert np.array_equal(bits & realbits[None, :], ref_bits & realbits[None, :])
+    _check(r, ref, p, prec)
+    assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
+    yc = p.y + 0.01 * np.random.default_rng(61).standard_normal(p.y.shape)
+    yc /= np.linalg.norm(yc, axis=1, keepdims=True)
+    yn, _, mass, _ = prob.sphere_karcher_step(psi, p.eps, torch.as_tensor(yc, device="cuda"))
+    ry, _, rm = oracle.sphere_karcher_step(p.x, p.mu, p.y, p.nu, psi, p.eps, yc)
+    ey = float(np.max(np.abs(yn.cpu().numpy() - ry)))
+    em = float(np.max(np.abs(mass.cpu().numpy() - rm) / (p.nu + rm)))
+    _say(f"    barycentre step on the grouped lists: y {ey:.1e}, mass {em:.1e}")
+    # the dropped weight is below tau |J| relative (tau = 1e-8 here)
+    assert ey <= 1e-6 and em <= 1e-6
+
+
 @pytest.mark.parametrize("prec,eps", [("mixed_fp32", 2e-2), ("fp64", 2e-2), ("mixed_fp32", 2.0),
                                       ("fp64", 2.0)])
 def test_sphere_karcher_step_parity(prec, eps):
