@@ -92,7 +92,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="dense mixed only")
     ap.add_argument("--main-extras", type=int, default=1,
                     help="0: skip the extras on the benchmark workload itself (rules, FP64, "
-                         "moments, solves) and run only the legs")
+                         "moments, solves) and run only the legs; 2: only its GEOM and "
+                         "tile-rule rows")
     ap.add_argument("--quick", action="store_true",
                     help="skip the disk multilevel, batched and learned legs")
     ap.add_argument("--ml-spread", action="store_true",
@@ -228,11 +229,32 @@ def main():
                             "pass1_ms": rr.info["pass1_ms"], "pass2_ms": rr.info["pass2_ms"]}
             log(f"[bench] {rule}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
                 f"effective {pairs/tt:.3e} pairs/s, kept {kept/tt:.3e} pairs/s")
-        # the tile rule at each culling granularity (targets per group)
-        extras["tile_groups"] = {}
-        prob.set_truncation("tile", tau=1e-12)
-        for g in (64, 32, 16, 8):
-            prob.set_tuning(0, 0, g)
+        if args.main_extras != 2:
+            # the tile rule at each culling granularity (targets per group)
+            extras["tile_groups"] = {}
+            prob.set_truncation("tile", tau=1e-12)
+            for g in (64, 32, 16, 8):
+                prob.set_tuning(0, 0, g)
+                rr = prob.dual_eval(psi, p.eps, out=grad)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                k = max(2, args.steps)
+                for _ in range(k):
+                    rr = prob.dual_eval(psi, p.eps, out=grad)
+                torch.cuda.synchronize()
+                tt = (time.perf_counter() - ts) / k
+                kept = rr.info["kept_pairs"]
+                extras["tile_groups"][str(g)] = {
+                    "ms_per_eval": tt * 1e3, "kept_frac": kept / pairs, "kept_pairs_s": kept / tt,
+                    "setup_ms": rr.info["setup_ms"], "pass1_ms": rr.info["pass1_ms"],
+                    "pass2_ms": rr.info["pass2_ms"], "J_minus_dense_rel": (r.J - rr.J) / absJ}
+                log(f"[bench] tile rule, groups of {g}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
+                    f"culling {rr.info['setup_ms']:.2f} ms, pass1 {rr.info['pass1_ms']:.2f} ms, "
+                    f"pass2 {rr.info['pass2_ms']:.2f} ms")
+            # the autotuner's choice for this problem (culling group, then the
+            # work segments of both passes), timed like the rows above
+            prob.set_tuning(0, 0, 0)
+            tune = prob.autotune(psi, p.eps, reps=2)
             rr = prob.dual_eval(psi, p.eps, out=grad)
             torch.cuda.synchronize()
             ts = time.perf_counter()
@@ -241,123 +263,103 @@ def main():
                 rr = prob.dual_eval(psi, p.eps, out=grad)
             torch.cuda.synchronize()
             tt = (time.perf_counter() - ts) / k
-            kept = rr.info["kept_pairs"]
-            extras["tile_groups"][str(g)] = {
-                "ms_per_eval": tt * 1e3, "kept_frac": kept / pairs, "kept_pairs_s": kept / tt,
-                "setup_ms": rr.info["setup_ms"], "pass1_ms": rr.info["pass1_ms"],
-                "pass2_ms": rr.info["pass2_ms"], "J_minus_dense_rel": (r.J - rr.J) / absJ}
-            log(f"[bench] tile rule, groups of {g}: {tt*1e3:.2f} ms/eval, kept {kept/pairs:.4f}, "
-                f"culling {rr.info['setup_ms']:.2f} ms, pass1 {rr.info['pass1_ms']:.2f} ms, "
-                f"pass2 {rr.info['pass2_ms']:.2f} ms")
-        # the autotuner's choice for this problem (culling group, then the
-        # work segments of both passes), timed like the rows above
-        prob.set_tuning(0, 0, 0)
-        tune = prob.autotune(psi, p.eps, reps=2)
-        rr = prob.dual_eval(psi, p.eps, out=grad)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        k = max(2, args.steps)
-        for _ in range(k):
+            extras["tile_tuned"] = dict(tune, ms_per_eval=tt * 1e3,
+                                        kept_frac=rr.info["kept_pairs"] / pairs,
+                                        J_minus_dense_rel=(r.J - rr.J) / absJ)
+            log(f"[bench] tile rule, autotuned {tune}: {tt*1e3:.2f} ms/eval, "
+                f"kept {rr.info['kept_pairs']/pairs:.4f}")
+            prob.set_tuning(0, 0, 0)
+            prob.set_truncation("dense")
+            prob.set_precision("fp64")
             rr = prob.dual_eval(psi, p.eps, out=grad)
-        torch.cuda.synchronize()
-        tt = (time.perf_counter() - ts) / k
-        extras["tile_tuned"] = dict(tune, ms_per_eval=tt * 1e3,
-                                    kept_frac=rr.info["kept_pairs"] / pairs,
-                                    J_minus_dense_rel=(r.J - rr.J) / absJ)
-        log(f"[bench] tile rule, autotuned {tune}: {tt*1e3:.2f} ms/eval, "
-            f"kept {rr.info['kept_pairs']/pairs:.4f}")
-        prob.set_tuning(0, 0, 0)
-        prob.set_truncation("dense")
-        prob.set_precision("fp64")
-        rr = prob.dual_eval(psi, p.eps, out=grad)
-        ts = time.perf_counter()
-        rr = prob.dual_eval(psi, p.eps, out=grad)
-        torch.cuda.synchronize()
-        tf = time.perf_counter() - ts
-        extras["fp64_dense"] = {"ms_per_eval": tf * 1e3, "pairs_s": pairs / tf, "J": rr.J,
-                                "J_mixed_minus_fp64_rel": (r.J - rr.J) / abs(rr.J)}
-        g64 = grad.clone()
-        prob.set_precision("mixed")
-        rm = prob.dual_eval(psi, p.eps, out=grad)
-        # plan moments and transport maps (Secs. 6.2, 6.3), dense, at the same
-        # psi: device time of the moment / map kernels after the evaluation
-        prob.plan_moments(psi, p.eps)
-        prob.transport_maps(psi, p.eps)
-        mom_ms = min(prob.plan_moments(psi, p.eps)[3] for _ in range(3))
-        map_ms = min(prob.transport_maps(psi, p.eps)[3] for _ in range(3))
-        extras["plan_moments"] = {"moments_ms": mom_ms, "moments_pairs_s": pairs / (mom_ms * 1e-3),
-                                  "maps_ms": map_ms, "maps_pairs_s": pairs / (map_ms * 1e-3),
-                                  "note": "kernels after the evaluation that gives L_q; "
-                                          "dense, mixed precision"}
-        log(f"[bench] plan moments {mom_ms:.1f} ms ({pairs / (mom_ms * 1e-3):.3e} pairs/s), "
-            f"maps {map_ms:.1f} ms ({pairs / (map_ms * 1e-3):.3e} pairs/s)")
-        nu_t = torch.as_tensor(p.nu, device=dev)
-        eg = torch.max(torch.abs(grad - g64) / (nu_t + g64 + nu_t)).item()
-        extras["fp64_dense"]["grad_err_mixed_vs_fp64"] = eg
-        log(f"[bench] fp64 dense: {tf*1e3:.1f} ms/eval; mixed vs fp64: "
-            f"J rel {(rm.J - rr.J)/abs(rr.J):.2e}, grad err {eg:.2e}")
-        prob.close()
+            ts = time.perf_counter()
+            rr = prob.dual_eval(psi, p.eps, out=grad)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - ts
+            extras["fp64_dense"] = {"ms_per_eval": tf * 1e3, "pairs_s": pairs / tf, "J": rr.J,
+                                    "J_mixed_minus_fp64_rel": (r.J - rr.J) / abs(rr.J)}
+            g64 = grad.clone()
+            prob.set_precision("mixed")
+            rm = prob.dual_eval(psi, p.eps, out=grad)
+            # plan moments and transport maps (Secs. 6.2, 6.3), dense, at the same
+            # psi: device time of the moment / map kernels after the evaluation
+            prob.plan_moments(psi, p.eps)
+            prob.transport_maps(psi, p.eps)
+            mom_ms = min(prob.plan_moments(psi, p.eps)[3] for _ in range(3))
+            map_ms = min(prob.transport_maps(psi, p.eps)[3] for _ in range(3))
+            extras["plan_moments"] = {"moments_ms": mom_ms, "moments_pairs_s": pairs / (mom_ms * 1e-3),
+                                      "maps_ms": map_ms, "maps_pairs_s": pairs / (map_ms * 1e-3),
+                                      "note": "kernels after the evaluation that gives L_q; "
+                                              "dense, mixed precision"}
+            log(f"[bench] plan moments {mom_ms:.1f} ms ({pairs / (mom_ms * 1e-3):.3e} pairs/s), "
+                f"maps {map_ms:.1f} ms ({pairs / (map_ms * 1e-3):.3e} pairs/s)")
+            nu_t = torch.as_tensor(p.nu, device=dev)
+            eg = torch.max(torch.abs(grad - g64) / (nu_t + g64 + nu_t)).item()
+            extras["fp64_dense"]["grad_err_mixed_vs_fp64"] = eg
+            log(f"[bench] fp64 dense: {tf*1e3:.1f} ms/eval; mixed vs fp64: "
+                f"J rel {(rm.J - rr.J)/abs(rr.J):.2e}, grad err {eg:.2e}")
+            prob.close()
 
-        # time to ||grad||_1 < 1e-6 on the 2D workload (FP64 path)
-        c1 = W.config1()
-        pr1 = rsot.Problem(c1.x, c1.mu, c1.y, c1.nu, precision="fp64")
-        pr1.solve([c1.eps], tol=1e-6)                     # warm (kernels loaded)
-        ts = time.perf_counter()
-        psi1, info1 = pr1.solve([c1.eps], tol=1e-6)
-        tsol = time.perf_counter() - ts
-        extras["time_to_tol_config1"] = {"workload": c1.name, "seconds": tsol,
-                                         "iterations": info1["iterations"],
-                                         "evaluations": info1["evaluations"],
-                                         "grad_l1": info1["grad_l1"],
-                                         "status": info1["status"]}
-        log(f"[bench] config1 solve: {tsol*1e3:.1f} ms, {info1['iterations']} it, "
-            f"{info1['evaluations']} evals, |g|_1={info1['grad_l1']:.2e}")
-        pr1.close()
+            # time to ||grad||_1 < 1e-6 on the 2D workload (FP64 path)
+            c1 = W.config1()
+            pr1 = rsot.Problem(c1.x, c1.mu, c1.y, c1.nu, precision="fp64")
+            pr1.solve([c1.eps], tol=1e-6)                     # warm (kernels loaded)
+            ts = time.perf_counter()
+            psi1, info1 = pr1.solve([c1.eps], tol=1e-6)
+            tsol = time.perf_counter() - ts
+            extras["time_to_tol_config1"] = {"workload": c1.name, "seconds": tsol,
+                                             "iterations": info1["iterations"],
+                                             "evaluations": info1["evaluations"],
+                                             "grad_l1": info1["grad_l1"],
+                                             "status": info1["status"]}
+            log(f"[bench] config1 solve: {tsol*1e3:.1f} ms, {info1['iterations']} it, "
+                f"{info1['evaluations']} evals, |g|_1={info1['grad_l1']:.2e}")
+            pr1.close()
 
-        # time to ||grad||_1 < 1e-6 on the 3D workload from psi = 0: mixed
-        # precision, tile rule, eps schedule eps*2^K .. eps (Sec. 4.2), stages
-        # before the last to 1e-5
-        K = int(math.floor(math.log2(0.1 / p.eps)))
-        sched = [p.eps * 2.0 ** k for k in range(K, 0, -1)] + [p.eps]
-        pr2 = rsot.Problem(p.x, p.mu, p.y, p.nu, truncation="tile", tau=1e-12)
-        ts = time.perf_counter()
-        psi2, info2 = pr2.solve(sched, tol=1e-6, stage_tol=1e-5)
-        t2 = time.perf_counter() - ts
-        extras["time_to_tol_config2"] = {"workload": p.name, "seconds": t2, "eps_schedule": sched,
-                                         "truncation": "tile", "tau": 1e-12,
-                                         "iterations": info2["iterations"],
-                                         "evaluations": info2["evaluations"],
-                                         "grad_l1": info2["grad_l1"],
-                                         "kept_frac": info2["kept_frac"],
-                                         "status": info2["status"],
-                                         "recheck": fp64_recheck(p, psi2)}
-        log(f"[bench] config2 solve: {t2:.2f} s, {info2['iterations']} it, "
-            f"{info2['evaluations']} evals, |g|_1={info2['grad_l1']:.2e}")
-        pr2.close()
+            # time to ||grad||_1 < 1e-6 on the 3D workload from psi = 0: mixed
+            # precision, tile rule, eps schedule eps*2^K .. eps (Sec. 4.2), stages
+            # before the last to 1e-5
+            K = int(math.floor(math.log2(0.1 / p.eps)))
+            sched = [p.eps * 2.0 ** k for k in range(K, 0, -1)] + [p.eps]
+            pr2 = rsot.Problem(p.x, p.mu, p.y, p.nu, truncation="tile", tau=1e-12)
+            ts = time.perf_counter()
+            psi2, info2 = pr2.solve(sched, tol=1e-6, stage_tol=1e-5)
+            t2 = time.perf_counter() - ts
+            extras["time_to_tol_config2"] = {"workload": p.name, "seconds": t2, "eps_schedule": sched,
+                                             "truncation": "tile", "tau": 1e-12,
+                                             "iterations": info2["iterations"],
+                                             "evaluations": info2["evaluations"],
+                                             "grad_l1": info2["grad_l1"],
+                                             "kept_frac": info2["kept_frac"],
+                                             "status": info2["status"],
+                                             "recheck": fp64_recheck(p, psi2)}
+            log(f"[bench] config2 solve: {t2:.2f} s, {info2['iterations']} it, "
+                f"{info2['evaluations']} evals, |g|_1={info2['grad_l1']:.2e}")
+            pr2.close()
 
-        # the same from the combined multilevel start (Sec. 5.3): source cubes
-        # of 16^3 / 32^3 / 64^3 cells (same mixture density), k-means targets
-        # 4,096 / 16,384 / 65,536; the schedule on the coarsest level, the final
-        # eps on the finer ones; every level to 1e-6
-        srcs = [(q.x, q.mu) for q in (W.cube_mixture(16, p.n, p.eps),
-                                      W.cube_mixture(32, p.n, p.eps))] + [(p.x, p.mu)]
-        ts = time.perf_counter()
-        hier = rsot.target_hierarchy(torch.as_tensor(p.y, device=dev),
-                                     torch.as_tensor(p.nu, device=dev),
-                                     [4096, 16384, p.n], lloyd_iters=20, seed=6)
-        ml2 = rsot.Multilevel(srcs, hier, precision="mixed", truncation="tile", tau=1e-12)
-        psi3, info3 = ml2.solve(sched + [p.eps] * 2, [0] * len(sched) + [1, 2], tol=1e-6,
-                                stage_tol=1e-5)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter() - ts
-        ml2.close()
-        extras["time_to_tol_config2_multilevel"] = {
-            "workload": p.name, "seconds": t3, "source_cells": [16, 32, 64],
-            "targets": [int(h[1].numel()) for h in hier], "iterations": info3["iterations"],
-            "seconds_per_level": info3["seconds"], "grad_l1": info3["grad_l1"],
-            "status": info3["status"], "recheck": fp64_recheck(p, psi3)}
-        log(f"[bench] config2 multilevel solve: {t3:.2f} s (hierarchy included), iterations "
-            f"{info3['iterations']}, |g|_1={info3['grad_l1']:.2e}")
+            # the same from the combined multilevel start (Sec. 5.3): source cubes
+            # of 16^3 / 32^3 / 64^3 cells (same mixture density), k-means targets
+            # 4,096 / 16,384 / 65,536; the schedule on the coarsest level, the final
+            # eps on the finer ones; every level to 1e-6
+            srcs = [(q.x, q.mu) for q in (W.cube_mixture(16, p.n, p.eps),
+                                          W.cube_mixture(32, p.n, p.eps))] + [(p.x, p.mu)]
+            ts = time.perf_counter()
+            hier = rsot.target_hierarchy(torch.as_tensor(p.y, device=dev),
+                                         torch.as_tensor(p.nu, device=dev),
+                                         [4096, 16384, p.n], lloyd_iters=20, seed=6)
+            ml2 = rsot.Multilevel(srcs, hier, precision="mixed", truncation="tile", tau=1e-12)
+            psi3, info3 = ml2.solve(sched + [p.eps] * 2, [0] * len(sched) + [1, 2], tol=1e-6,
+                                    stage_tol=1e-5)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter() - ts
+            ml2.close()
+            extras["time_to_tol_config2_multilevel"] = {
+                "workload": p.name, "seconds": t3, "source_cells": [16, 32, 64],
+                "targets": [int(h[1].numel()) for h in hier], "iterations": info3["iterations"],
+                "seconds_per_level": info3["seconds"], "grad_l1": info3["grad_l1"],
+                "status": info3["status"], "recheck": fp64_recheck(p, psi3)}
+            log(f"[bench] config2 multilevel solve: {t3:.2f} s (hierarchy included), iterations "
+                f"{info3['iterations']}, |g|_1={info3['grad_l1']:.2e}")
         out["extras"] = extras
 
     legs = []
