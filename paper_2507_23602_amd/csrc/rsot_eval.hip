@@ -545,7 +545,8 @@ __device__ __forceinline__ uint32_t group_chunks(int64_t t, int64_t b, int g,
 // wavefront handles one (row, segment), lanes over its columns.
 // FILL = false classifies every pair of the segment, counts the kept entries
 // into scnt and stores the classes as bits, one 64-bit word per 64 columns
-// (kbits: kept, pbits: needs the per-pair test); FILL = true reads the words
+// (kbits: kept, pbits: needs the per-pair test); it runs on the rows only
+// (the column bits are these transposed, k_transpose_bits). FILL = true reads the words
 // back and writes the entries in increasing order, from the row's start
 // ptr[row] plus the counts of the row's earlier segments: the index (with
 // RSOT_PARTIAL_BIT when the pair needs the per-pair test) and, for such
@@ -681,6 +682,55 @@ __global__ void k_seg_sum(const int32_t *__restrict__ scnt, int64_t nrows, int n
     cnt[r] = c;
 }
 
+// The column culling from the row count pass's bits: both passes classify
+// every (tile, block) pair with the same function of the same operands, so
+// the column bits are the row bits transposed. One wavefront per 64 x 64 bit
+// tile: lane l holds the row word of tile t0 + l; the ballot over lanes of
+// bit j is the column word of block b0 + j. PB: the partial bits too.
+template <bool PB>
+__global__ __launch_bounds__(256) void k_transpose_bits(
+    const uint64_t *__restrict__ rk, const uint64_t *__restrict__ rp, int64_t n_tiles,
+    int64_t n_blocks, uint64_t *__restrict__ ck, uint64_t *__restrict__ cp) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwt = (n_tiles + 63) / 64, nwb = (n_blocks + 63) / 64;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv >= nwt * nwb) return;
+    const int64_t tw = wv / nwb, bw = wv % nwb;
+    const int64_t t = tw * 64 + lane;
+    const uint64_t k = t < n_tiles ? rk[t * nwb + bw] : 0ull;
+    const uint64_t q = (PB && t < n_tiles) ? rp[t * nwb + bw] : 0ull;
+    uint64_t ko = 0, qo = 0;
+    for (int j = 0; j < 64; ++j) {
+        const uint64_t mk = __ballot((k >> j) & 1ull);
+        if (lane == j) ko = mk;
+        if (PB) {
+            const uint64_t mq = __ballot((q >> j) & 1ull);
+            if (lane == j) qo = mq;
+        }
+    }
+    const int64_t b = bw * 64 + lane;
+    if (b < n_blocks) {
+        ck[b * nwt + tw] = ko;
+        if (PB) cp[b * nwt + tw] = qo;
+    }
+}
+
+// kept (tile, block) pairs per (block, segment of seg_len tiles) from the
+// column bits
+__global__ void k_col_seg_counts(const uint64_t *__restrict__ ck, int64_t n_tiles,
+                                 int64_t n_blocks, int nseg, int64_t seg_len,
+                                 int32_t *__restrict__ scnt) {
+    const int64_t rs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rs >= n_blocks * nseg) return;
+    const int64_t b = rs / nseg, sg = rs % nseg;
+    const int64_t nwt = (n_tiles + 63) / 64;
+    const int64_t w0 = sg * seg_len / 64;
+    const int64_t w1 = std::min<int64_t>(nwt, (sg + 1) * seg_len / 64);
+    int32_t c = 0;
+    for (int64_t w = w0; w < w1; ++w) c += __popcll(ck[b * nwt + w]);
+    scnt[rs] = c;
+}
+
 // out = in^T for a rows x cols byte matrix, through 64 x 64 tiles in LDS
 // (grid: x over column tiles, y over row tiles)
 __global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t *__restrict__ in,
@@ -780,6 +830,101 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
         ptr[n] = sums[1023];
         *total_out = (double)sums[1023];
     }
+}
+
+// The same exclusive prefix sums for long arrays, over pieces of 1024
+// entries in three launches: each piece's sum (k_scan_piece), the scan of
+// the piece sums in one workgroup (k_scan_top), then each piece's own scan
+// offset by its piece's prefix (k_scan_apply). psum holds
+// ceil(n / 1024) entries.
+__device__ __forceinline__ int64_t scan_term(const int32_t *__restrict__ cnt, int64_t i,
+                                             int64_t n, int seg) {
+    if (i >= n) return 0;
+    const int64_t c = cnt[i];
+    return seg > 0 ? (c + seg - 1) / seg : c;
+}
+
+// inclusive scan of v over the 1024 threads of the workgroup; *total gets the
+// workgroup's sum (wsum: 16 entries of shared memory)
+__device__ __forceinline__ int64_t group_scan_1024(int64_t v, int64_t *wsum, int64_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        int64_t s = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int64_t t = __shfl_up(s, o, 64);
+            if (lane >= o) s += t;
+        }
+        if (lane < 16) wsum[lane] = s;
+    }
+    __syncthreads();
+    const int64_t r = v + (w > 0 ? wsum[w - 1] : 0);
+    *total = wsum[15];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_piece(const int32_t *__restrict__ cnt, int64_t n,
+                                                     int seg, int64_t *__restrict__ psum) {
+    __shared__ int64_t wsum[16];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    int64_t total = 0;
+    (void)group_scan_1024(scan_term(cnt, i, n, seg), wsum, &total);
+    if (threadIdx.x == 0) psum[blockIdx.x] = total;
+}
+
+// one workgroup: psum (np entries) becomes its exclusive prefix sums;
+// ptr[n] and *total_out get the total
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *__restrict__ psum, int64_t np,
+                                                   int64_t *__restrict__ ptr, int64_t n,
+                                                   double *__restrict__ total_out) {
+    __shared__ int64_t wsum[16];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < np; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < np ? psum[i] : 0;
+        int64_t total = 0;
+        const int64_t inc = group_scan_1024(v, wsum, &total);
+        if (i < np) psum[i] = carry + inc - v;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        ptr[n] = carry;
+        *total_out = (double)carry;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(const int32_t *__restrict__ cnt, int64_t n,
+                                                     int seg, const int64_t *__restrict__ psum,
+                                                     int64_t *__restrict__ ptr) {
+    __shared__ int64_t wsum[16];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t v = scan_term(cnt, i, n, seg);
+    int64_t total = 0;
+    const int64_t inc = group_scan_1024(v, wsum, &total);
+    if (i < n) ptr[i] = psum[blockIdx.x] + inc - v;
+}
+
+// exclusive prefix sums of cnt (or of ceil(cnt / seg) when seg > 0) into
+// ptr[0..n], the total also into *total_out; psum: ceil(n / 1024) entries
+static void launch_scan(hipStream_t st, const int32_t *cnt, int64_t n, int seg, int64_t *ptr,
+                        double *total_out, int64_t *psum) {
+    if (n <= 4096) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, n, seg, ptr, total_out);
+        return;
+    }
+    const int64_t np = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_piece, dim3((unsigned)np), dim3(1024), 0, st, cnt, n, seg, psum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, psum, np, ptr, n, total_out);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)np), dim3(1024), 0, st, cnt, n, seg, psum,
+                       ptr);
 }
 
 // work items of the gradient pass: block b owns ceil(len_b / seg) segments of
@@ -1708,6 +1853,8 @@ static rsot_status ensure_cull_buffers(rsot_problem *p, bool tile_rule, hipStrea
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->wi1_ptr, sizeof(int64_t) * (p->n_tiles + 1)));
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->row_cnt, sizeof(int32_t) * p->n_tiles));
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->col_cnt, sizeof(int32_t) * p->n_blocks));
+        const int64_t np = (std::max(p->n_tiles, p->n_blocks) + 1023) / 1024;
+        RSOT_TRY(rsot_dev_alloc(p, (void **)&p->scan_tmp, sizeof(int64_t) * np));
         int ns = 1;
         int64_t len = 0;
         cull_segments(p->n_tiles, p->n_blocks, &ns, &len);
@@ -1819,6 +1966,29 @@ static void launch_cull(rsot_problem *p, hipStream_t st, int D, bool tile_rule, 
         hipLaunchKernelGGL(k_transpose_u8,
                            dim3((unsigned)((p->n_blocks + 63) / 64), (unsigned)((p->n_tiles + 63) / 64)),
                            dim3(256), 0, st, p->gmask, p->n_tiles, p->n_blocks, p->gmaskT);
+}
+
+// The column count pass: the row count pass's bits transposed, then the
+// kept pairs per (block, segment of its tiles) and per block.
+static void launch_col_counts(rsot_problem *p, hipStream_t st, bool tile_rule) {
+    const bool pb = !tile_rule || tile_group(p) < 64;
+    const int64_t waves = ((p->n_tiles + 63) / 64) * ((p->n_blocks + 63) / 64);
+    const dim3 g((unsigned)((waves + 3) / 4));
+    if (pb)
+        hipLaunchKernelGGL(k_transpose_bits<true>, g, dim3(256), 0, st, p->row_kbits,
+                           p->row_pbits, p->n_tiles, p->n_blocks, p->col_kbits, p->col_pbits);
+    else
+        hipLaunchKernelGGL(k_transpose_bits<false>, g, dim3(256), 0, st, p->row_kbits,
+                           (const uint64_t *)nullptr, p->n_tiles, p->n_blocks, p->col_kbits,
+                           (uint64_t *)nullptr);
+    int nseg = 1;
+    int64_t seg_len = 0;
+    cull_segments(p->n_blocks, p->n_tiles, &nseg, &seg_len);
+    const int64_t nrs = p->n_blocks * nseg;
+    hipLaunchKernelGGL(k_col_seg_counts, dim3((unsigned)((nrs + 255) / 256)), dim3(256), 0, st,
+                       p->col_kbits, p->n_tiles, p->n_blocks, nseg, seg_len, p->col_scnt);
+    hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)((p->n_blocks + 255) / 256)), dim3(256), 0, st,
+                       p->col_scnt, p->n_blocks, nseg, p->col_cnt);
 }
 
 // One evaluation in stages, so that a batch of problems can share host
@@ -1950,16 +2120,14 @@ static rsot_status plan_begin(EvalPlan &e) {
                            p->tpsi, p->tlog2nu, p->tperm, p->n_pad, e.kappa, p->dscal, p->tG);
     }
     launch_cull(p, st, D, tile_rule, true, false, eps);
-    launch_cull(p, st, D, tile_rule, false, false, eps);
+    launch_col_counts(p, st, tile_rule);
     e.seg = seg_cfg > 0 ? seg_cfg : 64;
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->row_cnt, p->n_tiles, 0, p->row_ptr,
-                       p->dscal + SC_ROWTOT);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->col_cnt, p->n_blocks, 0, p->col_ptr,
-                       p->dscal + SC_COLTOT);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->col_cnt, p->n_blocks, (int)e.seg,
-                       p->wi_ptr, p->dscal + SC_NWI);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->row_cnt, p->n_tiles,
-                       (int)e.seg1_cfg, p->wi1_ptr, p->dscal + SC_NWI1);
+    launch_scan(st, p->row_cnt, p->n_tiles, 0, p->row_ptr, p->dscal + SC_ROWTOT, p->scan_tmp);
+    launch_scan(st, p->col_cnt, p->n_blocks, 0, p->col_ptr, p->dscal + SC_COLTOT, p->scan_tmp);
+    launch_scan(st, p->col_cnt, p->n_blocks, (int)e.seg, p->wi_ptr, p->dscal + SC_NWI,
+                p->scan_tmp);
+    launch_scan(st, p->row_cnt, p->n_tiles, (int)e.seg1_cfg, p->wi1_ptr, p->dscal + SC_NWI1,
+                p->scan_tmp);
     RSOT_HIP(hipGetLastError());
     RSOT_HIP(hipMemcpyAsync(p->hscal, p->dscal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
                             st));

@@ -126,6 +126,7 @@ struct rsot_problem {
     int64_t *col_ptr = nullptr;  // [n_blocks+1]
     int32_t *row_cnt = nullptr;  // [n_tiles]
     int32_t *col_cnt = nullptr;  // [n_blocks]
+    int64_t *scan_tmp = nullptr; // [ceil(max(n_tiles, n_blocks) / 1024)] piece sums of the scans
     int32_t *row_scnt = nullptr; // kept entries per (tile, segment of its blocks)
     int32_t *col_scnt = nullptr; // kept entries per (block, segment of its tiles)
     // culling classes of the count pass, read back by the fill pass: one bit
