@@ -1059,6 +1059,15 @@ __device__ __forceinline__ void lse_block_fast(RP T, double x0, double x1, doubl
     for (int k0 = 0; k0 < 64; k0 += CH) lse_chunk_fast<D>(T, k0, x0, x1, x2, m, s);
 }
 
+// c + (in ? 1 : 0) as one add with carry: the lane mask of the predicate is
+// the carry input. Left to itself the compiler packs the eight predicates of
+// a chunk into a byte and counts its bits, about 2.5 instructions a pair.
+__device__ __forceinline__ int add_pred(int c, bool in) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+    asm("v_addc_co_u32 %0, vcc, 0, %0, %1" : "+v"(c) : "s"(m) : "vcc");
+    return c;
+}
+
 // The same for a chunk that straddles the cutoff of a T1 rule: each pair
 // takes the test t_j > G_j - A (c < C), failing pairs enter as 2^-inf = 0;
 // kept pairs are counted. The chunk's records and cutoff constants are taken
@@ -1077,7 +1086,7 @@ __device__ __forceinline__ void lse_chunk_mask(RP T, int k0, GP G, double x0, do
     for (int k = 0; k < CH; ++k) {
         const double t = pair_exp<D>(x0, x1, x2, trec_at<D>(T, k0 + k));
         const bool in = t > G[k0 + k] - A;
-        kc += in;
+        kc = add_pred(kc, in);
         u[k] = in ? (float)(t - m) : -INFINITY;
         cs += __builtin_amdgcn_exp2f(u[k]);
     }
@@ -1195,10 +1204,10 @@ __device__ __forceinline__ void pass1_item(const double4 *__restrict__ qp, RP tr
 }
 
 // Objective pass under the cutoff rules (mixed precision): items in the order
-// of their first target block, dealt to the XCDs in runs. The straddling-
-// chunk path needs more registers than the fast path (72 vector registers:
-// seven waves per SIMD); holding it to eight waves spills and was slower
-// (GEOM evaluation on the 3D benchmark workload 171.5 -> 182.7 ms).
+// of their first target block, dealt to the XCDs in runs. With the kept
+// count taken as an add with carry the kernel holds 43 vector registers
+// (eight waves per SIMD); the compiler's own count, the predicates packed
+// into bytes, needed 72.
 template <int D>
 __global__ __launch_bounds__(256) void k_pass1_cut(
     const double4 *__restrict__ qp, const double4 *__restrict__ trec,
