@@ -330,6 +330,52 @@ def test_tile_rule_parity(prec, d, group):
     assert -1e-13 * abs(dense.J) <= dense.J - ref.J <= tau * abs(dense.J)
 
 
+@pytest.mark.parametrize("rule,group", [("tile", 64), ("tile", 8), ("geom", 64)])
+def test_culling_parity_many_tiles(rule, group):
+    """Culling past one workgroup's prefix sums: 331,776 points (5,184 tiles,
+    more than the 4,096 counts one scan workgroup takes) x 2,000 targets (a
+    ragged last block). The kept set against the oracle's rule: (tile, chunk)
+    bits and per-point |I_q| for the tile rule, the kept-pair count and per-
+    point |I_q| (up to near ties) for GEOM. The column lists, built from the
+    transposed row bits, carry the gradient: J and grad against the oracle."""
+    import torch
+    _say(f"culling with many tiles: {rule}, group {group}")
+    p = W.cube_mixture(24, 2000, 1e-3)
+    psi = W.random_psi(21, p.n, p.eps)
+    dense = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps)
+    tau = 1e-8
+    prob = _problem(p.x, p.mu, p.y, p.nu, precision="mixed", truncation=rule, tau=tau,
+                    tile_group=group)
+    tile_of, block_of, nt, nb = prob.partition()
+    assert nt > 4096 and p.n % 64 != 0
+    prob.set_reference(abs(dense.J))
+    r = prob.dual_eval(torch.as_tensor(psi, device="cuda"), p.eps)
+    tile_of = tile_of.cpu().numpy()
+    cnt = prob.kept_counts().cpu().numpy()
+    if rule == "tile":
+        slots = prob.target_slots().cpu().numpy()
+        group_of = (slots // group).astype(np.int32)
+        ng = nb * 64 // group
+        ref = oracle.dual_eval_tile(p.x, p.mu, p.y, p.nu, psi, p.eps, tile_of, nt, group_of, ng,
+                                    tau, abs(dense.J), want_L=True, want_keep=True)
+        bits = prob.tile_chunk_keep().cpu().numpy()
+        ref_bits, real = _chunk_keep_from_groups(ref.keep, slots, nb, group, p.n)
+        realbits = np.packbits(real[:, ::-1], axis=1, bitorder="big").reshape(-1)
+        assert np.array_equal(bits & realbits[None, :], ref_bits & realbits[None, :])
+        ref_cnt = (ref.keep[tile_of] > 0).astype(np.int64) @ np.bincount(group_of, minlength=ng)
+        assert np.array_equal(cnt, ref_cnt)
+    else:
+        C = r.info["cutoff"]
+        ref = oracle.dual_eval(p.x, p.mu, p.y, p.nu, psi, p.eps, cutoff=C, want_L=True)
+        ref_cnt, near = oracle.kept_counts(p.x, p.y, C, rel_band=1e-12)
+        assert np.all(np.abs(cnt.astype(np.int64) - ref_cnt) <= near)
+    _say(f"  tiles {nt}, blocks {nb}: kept gpu {r.info['kept_pairs']} oracle {ref.kept} of "
+         f"{p.nq * p.n}")
+    assert r.info["kept_pairs"] == ref.kept
+    assert 0 < ref.kept < p.nq * p.n
+    _check(prob, p.x, p.mu, p.y, p.nu, psi, p.eps, "mixed", ref=ref, r=r)
+
+
 def test_tile_rule_groups_keep_fewer_pairs():
     """Finer culling groups give a tighter rule: on the same problem groups
     of 8 targets keep fewer pairs than whole blocks, and every granularity
