@@ -984,14 +984,14 @@ __device__ __forceinline__ void lse_chunk(RP T, int k0, GP G, double x0, double 
             m = mn;
         }
         if (F64) {
-            double cs = 0.0;
+            double cs = exp2(tv[0] - m);
 #pragma unroll
-            for (int k = 0; k < CH; ++k) cs += exp2(tv[k] - m);
+            for (int k = 1; k < CH; ++k) cs += exp2(tv[k] - m);
             s += cs;
         } else {
-            float cs = 0.0f;
+            float cs = __builtin_amdgcn_exp2f((float)(tv[0] - m));
 #pragma unroll
-            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
+            for (int k = 1; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
             s += (double)cs;
         }
     }
@@ -1028,7 +1028,8 @@ __device__ __forceinline__ void lse_chunk_fast(RP T, int k0, double x0, double x
         v = fma(x1, r.y, v);
         if (D == 3) v = fma(x2, r.z, v);
         u[k] = (float)v;
-        cs += __builtin_amdgcn_exp2f(u[k]);
+        const float e = __builtin_amdgcn_exp2f(u[k]);
+        cs = k == 0 ? e : cs + e;
     }
     if (!(cs <= 2.0f)) {
         float mx = u[0];
@@ -1046,7 +1047,8 @@ __device__ __forceinline__ void lse_chunk_fast(RP T, int k0, double x0, double x
                 v = fma(x0, r.x, v);
                 v = fma(x1, r.y, v);
                 if (D == 3) v = fma(x2, r.z, v);
-                cs += __builtin_amdgcn_exp2f((float)v);
+                const float e = __builtin_amdgcn_exp2f((float)v);
+                cs = k == 0 ? e : cs + e;
             }
         }
     }
@@ -1088,7 +1090,8 @@ __device__ __forceinline__ void lse_chunk_mask(RP T, int k0, GP G, double x0, do
         const bool in = t > G[k0 + k] - A;
         kc = add_pred(kc, in);
         u[k] = in ? (float)(t - m) : -INFINITY;
-        cs += __builtin_amdgcn_exp2f(u[k]);
+        const float e = __builtin_amdgcn_exp2f(u[k]);
+        cs = k == 0 ? e : cs + e;
     }
     if (!(cs <= 2.0f)) {
         float mx = u[0];
@@ -1101,7 +1104,10 @@ __device__ __forceinline__ void lse_chunk_mask(RP T, int k0, GP G, double x0, do
             cs = 0.0f;
             const float fdm = (float)dm;
 #pragma unroll
-            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f(u[k] - fdm);
+            for (int k = 0; k < CH; ++k) {
+                const float e = __builtin_amdgcn_exp2f(u[k] - fdm);
+                cs = k == 0 ? e : cs + e;
+            }
         }
     }
     s += (double)cs;
@@ -1393,7 +1399,8 @@ __device__ __forceinline__ double mass_chunk(QP Q, int i0, AP qA, double Y0, dou
                 v = fma(r.y, Y1, v);
                 if (D == 3) v = fma(r.z, Y2, v);
             }
-            cs += exp2(v);
+            const double e = exp2(v);
+            cs = k == 0 ? e : cs + e;
         }
         return cs;
     } else {
@@ -1413,7 +1420,8 @@ __device__ __forceinline__ double mass_chunk(QP Q, int i0, AP qA, double Y0, dou
                 if (D == 3) v = fma(r.z, Y2, v);
                 u = (float)v;
             }
-            cs += __builtin_amdgcn_exp2f(u);
+            const float e = __builtin_amdgcn_exp2f(u);
+            cs = k == 0 ? e : cs + e;
         }
         return (double)cs;
     }
@@ -2850,14 +2858,14 @@ __device__ __forceinline__ void lse_tile(const double4 *__restrict__ Q, double Y
             m = mn;
         }
         if (F64) {
-            double cs = 0.0;
+            double cs = exp2(tv[0] - m);
 #pragma unroll
-            for (int k = 0; k < CH; ++k) cs += exp2(tv[k] - m);
+            for (int k = 1; k < CH; ++k) cs += exp2(tv[k] - m);
             s += cs;
         } else {
-            float cs = 0.0f;
+            float cs = __builtin_amdgcn_exp2f((float)(tv[0] - m));
 #pragma unroll
-            for (int k = 0; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
+            for (int k = 1; k < CH; ++k) cs += __builtin_amdgcn_exp2f((float)(tv[k] - m));
             s += (double)cs;
         }
     }
