@@ -168,7 +168,7 @@ struct rsot_problem {
     double last_kcs = 0.0;       // kappa * cost_scale of the last evaluation
     double *mpart = nullptr;     // plan moments: per-item partial first moments
     size_t mpart_cap = 0;
-    float *tyf = nullptr;        // transport maps: FP32 target coordinates {y0, y1, y2, 0}
+    float *tyf = nullptr;        // transport maps: FP32 target coordinates less their block's box centre {y0, y1, y2, 0}
     int64_t last_refine_pairs = 0;   // (tile, fine block) pairs x 64 x 64 of the last refinement
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_p1 = nullptr, ev_mid = nullptr, ev_p2 = nullptr;
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;   // batched call

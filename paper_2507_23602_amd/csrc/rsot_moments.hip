@@ -213,6 +213,45 @@ __device__ __forceinline__ void map_chunk(RP T, int k0, GP G, YP Yf, const doubl
     for (int d = 0; d < D; ++d) sy[d] += (double)cy[d];
 }
 
+// The FP32 path of map_chunk. Yc holds the targets' coordinates relative to
+// their block's centre c_B (FP32), so a pair adds w (y_j - c_B) with one FMA
+// per coordinate and the caller subtracts (x_q - c_B) times the block's
+// weight wB in FP64; the offsets stay of the block's size. The modal target
+// takes the chunk's largest FP64 exponent first and looks up its index only
+// when it beats the running best: the first target reaching it, as a pair-
+// by-pair strict comparison finds. FULL: every pair of the chunk is kept.
+template <int D, bool FULL, typename RP, typename GP>
+__device__ __forceinline__ void map_chunk32(RP T, int k0, GP G, const float4 *__restrict__ Yc,
+                                            double x0, double x1, double x2, double A,
+                                            double Lt, int64_t jbase, double &wB, double *sy,
+                                            double &best, int64_t &bj) {
+    float cw = 0.0f, cy[3] = {0.0f, 0.0f, 0.0f};
+    double tv[CH];
+    double cmax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const double t = pair_exp<D>(x0, x1, x2, trec_at<D>(T, k0 + k));
+        const bool in = FULL || t > G[k0 + k] - A;
+        tv[k] = in ? t : -INFINITY;
+        cmax = fmax(cmax, tv[k]);
+        const float w = __builtin_amdgcn_exp2f(in ? (float)(t - Lt) : -INFINITY);
+        const float4 yk = Yc[k0 + k];
+        const float yy[3] = {yk.x, yk.y, yk.z};
+        cw = k == 0 ? w : cw + w;
+#pragma unroll
+        for (int d = 0; d < D; ++d) cy[d] = k == 0 ? w * yy[d] : fmaf(w, yy[d], cy[d]);
+    }
+    wB += (double)cw;
+#pragma unroll
+    for (int d = 0; d < D; ++d) sy[d] += (double)cy[d];
+    if (cmax > best) {
+        best = cmax;
+#pragma unroll
+        for (int k = CH - 1; k >= 0; --k)
+            if (tv[k] == cmax) bj = jbase + k0 + k;
+    }
+}
+
 template <int D, bool F64, int MODE>
 __global__ __launch_bounds__(256) void k_maps(
     const double4 *__restrict__ qp, const double *__restrict__ qlse,
@@ -220,7 +259,8 @@ __global__ __launch_bounds__(256) void k_maps(
     const double *__restrict__ trec3, const double *__restrict__ tG,
     const float4 *__restrict__ tyf, const double *__restrict__ ty,
     const int32_t *__restrict__ tperm, const int64_t *__restrict__ row_ptr,
-    const uint32_t *__restrict__ row_idx, const uint16_t *__restrict__ row_cm, int64_t n_tiles,
+    const uint32_t *__restrict__ row_idx, const uint16_t *__restrict__ row_cm,
+    const double *__restrict__ blk_lo, const double *__restrict__ blk_hi, int64_t n_tiles,
     int64_t n_blocks, double kcs, double s0, double s1, double s2,
     double *__restrict__ bary_out, int32_t *__restrict__ modal_out) {
     const int lane = threadIdx.x & 63;
@@ -246,11 +286,31 @@ __global__ __launch_bounds__(256) void k_maps(
         if (MODE == MODE_MASK && (ent & RSOT_PARTIAL_BIT)) cm = F64 ? 0x5555u : (uint32_t)row_cm[e];
         else if (MODE == MODE_LIST && (ent & RSOT_PARTIAL_BIT)) cm = row_cm[e];
         auto block = [&](auto T) {
-            for (int c = 0; c < 8; ++c) {
-                const int cls = (int)((cm >> (2 * c)) & 3u);
-                if (cls == PAIR_SKIP) continue;
-                map_chunk<D, F64>(T, 8 * c, tG + b * 64, tyf + b * 64, ty + b * 64 * 3, cls, x0,
-                                  x1, x2, A, Lt, b * 64, sw, sy, best, bj);
+            if constexpr (F64) {
+                for (int c = 0; c < 8; ++c) {
+                    const int cls = (int)((cm >> (2 * c)) & 3u);
+                    if (cls == PAIR_SKIP) continue;
+                    map_chunk<D, F64>(T, 8 * c, tG + b * 64, tyf + b * 64, ty + b * 64 * 3, cls,
+                                      x0, x1, x2, A, Lt, b * 64, sw, sy, best, bj);
+                }
+            } else {
+                double wB = 0.0;
+                for (int c = 0; c < 8; ++c) {
+                    const int cls = (int)((cm >> (2 * c)) & 3u);
+                    if (cls == PAIR_SKIP) continue;
+                    if (cls == PAIR_FULL)
+                        map_chunk32<D, true>(T, 8 * c, tG + b * 64, tyf + b * 64, x0, x1, x2, A,
+                                             Lt, b * 64, wB, sy, best, bj);
+                    else
+                        map_chunk32<D, false>(T, 8 * c, tG + b * 64, tyf + b * 64, x0, x1, x2, A,
+                                              Lt, b * 64, wB, sy, best, bj);
+                }
+                const double xq[3] = {x0, x1, x2};
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    sy[d] = fma(-(xq[d] - 0.5 * (blk_lo[b * 3 + d] + blk_hi[b * 3 + d])), wB,
+                                sy[d]);
+                sw += wB;
             }
         };
         if constexpr (D == 3) block(trec + b * 64);
@@ -267,11 +327,18 @@ __global__ __launch_bounds__(256) void k_maps(
     if (modal_out) modal_out[dst] = bj >= 0 ? tperm[bj] : -1;
 }
 
-__global__ void k_target_f32(const double *__restrict__ ty, int64_t n_pad,
+// FP32 target coordinates relative to the centre of their block's box (the
+// transport maps' offsets; 0 in the third slot for 2D)
+__global__ void k_target_f32(const double *__restrict__ ty, const double *__restrict__ blk_lo,
+                             const double *__restrict__ blk_hi, int dim, int64_t n_pad,
                              float4 *__restrict__ tyf) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_pad) return;
-    tyf[j] = make_float4((float)ty[j * 3], (float)ty[j * 3 + 1], (float)ty[j * 3 + 2], 0.0f);
+    const int64_t b = j / 64;
+    float c[3] = {0.0f, 0.0f, 0.0f};
+    for (int d = 0; d < dim; ++d)
+        c[d] = (float)(ty[j * 3 + d] - 0.5 * (blk_lo[b * 3 + d] + blk_hi[b * 3 + d]));
+    tyf[j] = make_float4(c[0], c[1], c[2], 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,7 +369,8 @@ void launch_maps(rsot_problem *p, int mode, double *bary, int32_t *modal) {
 #define RSOT_MAP(M)                                                                            \
     hipLaunchKernelGGL((k_maps<D, F64, M>), g, dim3(256), 0, p->stream, p->qp, p->qlse,         \
                        p->qperm, p->trec, p->trec3, p->tG, (const float4 *)p->tyf, p->ty,       \
-                       p->tperm, p->row_ptr, p->row_idx, p->row_cm, p->n_tiles, p->n_blocks,    \
+                       p->tperm, p->row_ptr, p->row_idx, p->row_cm, p->blk_lo, p->blk_hi,       \
+                       p->n_tiles, p->n_blocks,                                                 \
                        p->last_kcs, p->shift[0], p->shift[1], p->shift[2], bary, modal)
     if (mode == MODE_DENSE) RSOT_MAP(MODE_DENSE);
     else if (mode == MODE_LIST) RSOT_MAP(MODE_LIST);
@@ -362,7 +430,8 @@ extern "C" rsot_status rsot_transport_maps(rsot_problem *p, double eps, const do
     if (!p->tyf) {
         RSOT_TRY(rsot_dev_alloc(p, (void **)&p->tyf, sizeof(float) * 4 * (size_t)p->n_pad));
         hipLaunchKernelGGL(k_target_f32, dim3((unsigned)((p->n_pad + 255) / 256)), dim3(256), 0,
-                           p->stream, p->ty, p->n_pad, (float4 *)p->tyf);
+                           p->stream, p->ty, p->blk_lo, p->blk_hi, p->dim, p->n_pad,
+                           (float4 *)p->tyf);
         RSOT_HIP(hipGetLastError());
     }
     double J = 0.0;
